@@ -1,0 +1,21 @@
+"""FP64 CPU oracle for the implicit ADI wave solver -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import it.  It shares no code with the HIP library.
+
+Parity status of each function (what pins it; see tests/test_oracle_pins.py):
+  thomas, tridiag_batched  -- dense LU on random diagonally dominant systems.
+  step_parts, run          -- dense Kronecker operators (factored form) on tiny
+                              heterogeneous grids; the unfactored eq. (CN1)
+                              solved densely (one-step gap shrinks like dt^6);
+                              the discrete standing-wave closed form; the
+                              continuous closed form; second-order convergence;
+                              the discrete energy invariant; x<->y symmetry.
+  start                    -- PAPER mode: eq. (CN2) verbatim; GHOST mode: the
+                              discrete standing-wave closed form from step 0.
+"""
+from .oracle import (build, lib, max_threads, thomas, tridiag_batched, step_parts, run,
+                     start, initial_levels, run_problem)
+
+__all__ = ["build", "lib", "max_threads", "thomas", "tridiag_batched", "step_parts", "run",
+           "start", "initial_levels", "run_problem"]
