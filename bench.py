@@ -1,0 +1,228 @@
+"""Benchmark of the ADI wave step on one MI355X.
+
+Workload (default): the 8192^2 FP32 heterogeneous case -- per-node wave speed
+in [1, 3] (16 seeded Gaussian bumps), dt = 0.4 h / max c, Ricker point source
+(f0 = 10) at the centre node, zero initial levels.  A "step" is one full ADI
+time step: right-hand side + x-line solves + y-line solves + update.
+
+Prints ONE JSON line:
+  value       Mpts/s = nx*ny*steps / t_timed / 1e6 (inputs resident in HBM)
+  roofline    dominant kernel: algorithmic bytes per launch / its mean duration
+              (HIP events around every launch on the solver's stream)
+  cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpts/s per ADI step + HBM GB/s (% peak); batched & adjoint vs plain, same GPU"
+HBM_PEAK_GBPS = 8000.0
+
+# Algorithmic bytes per grid node per launch (element size E, per-node coefficient):
+#   x_sweep_rhs     reads u^n and r, writes w                      3E
+#   y_solve_update  reads w, r, u^n, u^{n-1}, writes u^{n+1}       5E
+#   y_reduce        reads w and r                                  2E
+# The whole step's two-pass minimum is 8E (32 B/node in FP32).
+ALG_BYTES_PER_NODE = {"x_sweep_rhs": 3, "y_solve_update": 5, "y_reduce": 2}
+STEP_BYTES_PER_NODE = 8
+
+WORKLOADS = {
+    "c3": ("c3_heterogeneous_ricker_8192x8192_f32", "f32", 8192),
+    "c2f32": ("c2_gaussian_pulse_2048x2048_f32", "f32", 2048),
+    "c2f64": ("c2_gaussian_pulse_2048x2048_f64", "f64", 2048),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp"):
+        with open(os.path.join(ROOT, "paper_2006_10142_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel: str, launches_bytes: float):
+    """HBM traffic from the committed counter summary, if it matches the current source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data.get(workload, {}).get(kernel)
+        if not ent or ent.get("source_hash") != kernel_source_hash():
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def make_problem(key: str, nsteps: int):
+    from paper_2006_10142_amd import workloads as wl
+    if key == "c3":
+        return wl.config_c3(dtype="f32", nsteps=nsteps)
+    if key == "c2f32":
+        return wl.config_c2(dtype="f32", nsteps=nsteps)
+    return wl.config_c2(dtype="f64", nsteps=nsteps)
+
+
+def cpu_baseline(prob, steps: int):
+    """FP64 oracle on a bounded sample: `steps` ADI steps of the same workload."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    kappa = prob.kappa_field()
+    if prob.u_curr is not None:
+        up = np.asarray(prob.u_prev, np.float64)
+        uc = np.asarray(prob.u_curr, np.float64)
+    else:
+        up = np.asarray(prob.u0, np.float64)
+        uc = up.copy()
+    amp = None if prob.src_amp is None else np.asarray(prob.src_amp)[:steps]
+    si = prob.src_idx if prob.src_idx.size else None
+    t0 = time.perf_counter()
+    oracle.run(kappa, up, uc, prob.h, prob.dt, steps, src_idx=si, src_amp=amp)
+    t = time.perf_counter() - t0
+    return {"value": prob.nx * prob.ny * steps / t / 1e6, "unit": "Mpts/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{steps} ADI steps of the same {prob.nx}x{prob.ny} workload, FP64, "
+                      f"{t:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=50)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
+              "build (see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2006_10142_amd as adw
+
+    name, dtype, n = WORKLOADS[args.workload]
+    total = args.warmup + args.steps
+    prob = make_problem(args.workload, total)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    wave = adw.Wave(prob.nx, prob.ny, prob.h, prob.dt, dtype=tdt,
+                    c=torch.from_numpy(prob.c).to(dev) if prob.c is not None else prob.c_scalar)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    if prob.u_curr is not None:
+        a = torch.from_numpy(np.ascontiguousarray(prob.u_prev)).to(dev)
+        b = torch.from_numpy(np.ascontiguousarray(prob.u_curr)).to(dev)
+    else:
+        a = torch.from_numpy(np.ascontiguousarray(prob.u0)).to(dev)
+        b = wave.start(a)
+    src = {}
+    if prob.src_amp is not None:
+        amp = torch.from_numpy(np.ascontiguousarray(prob.src_amp)).to(dev)
+        src = dict(src_idx=torch.from_numpy(prob.src_idx).to(dev))
+    torch.cuda.synchronize()
+
+    def srcs(first, count):
+        if not src:
+            return {}
+        return dict(src, src_amp=amp[first:first + count])
+
+    # warm-up, then exactly `steps` timed steps bracketed by synchronisation
+    if args.warmup:
+        a, b = wave.step(a, b, args.warmup, **srcs(0, args.warmup))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    a, b = wave.step(a, b, args.steps, **srcs(args.warmup, args.steps))
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    npts = prob.nx * prob.ny
+    value = npts * args.steps / (ms / 1e3) / 1e6
+    if not torch.isfinite(b).all():
+        print("bench.py: non-finite field after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    # per-kernel durations (events around every launch, same stream)
+    psteps = max(1, min(args.profile_steps, args.steps))
+    (a, b), kms = wave.profile(a, b, psteps, **srcs(0, psteps))
+    esz = 4 if dtype == "f32" else 8
+    dom = max((k for k in kms if k in ALG_BYTES_PER_NODE), key=lambda k: kms[k])
+    alg_bytes = ALG_BYTES_PER_NODE[dom] * esz * npts
+    achieved = alg_bytes / (kms[dom] / 1e3) / 1e9
+    traffic = load_traffic(name, dom, alg_bytes)
+
+    # achievable copy bandwidth on this GPU (1 GiB read + 1 GiB write)
+    x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    adw.stream_copy(x, y)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        adw.stream_copy(x, y)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * x.numel() * 4 * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del x, y
+
+    step_gbps = STEP_BYTES_PER_NODE * esz * npts * args.steps / (ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": name, "nx": prob.nx, "ny": prob.ny,
+                   "coefficient": "per-node" if prob.c is not None else "constant",
+                   "source": "ricker point source" if src else "none",
+                   "launch_plan": wave.info()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic},
+        "step_algorithmic_GBps": round(step_gbps, 1),
+        "step_frac_of_peak": round(step_gbps / HBM_PEAK_GBPS, 4),
+        "kernel_ms": {k: round(v, 5) for k, v in kms.items()},
+        "copy_GBps": round(copy_gbps, 1),
+        "create_ms": round(create_ms, 2),
+        "wall_s_timed": round(wall, 4),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
+    wave.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * adiwave.h -- C ABI of the MI355X (gfx950) ADI solver for the implicit
+ * finite-difference 2-D acoustic wave equation.
+ *
+ * Method (Altybay, Ruzhansky, Tokmagambetov, "A parallel hybrid implementation
+ * of the 2D acoustic wave equation", Sec. 2):
+ *   u_tt - kappa(x, y) (u_xx + u_yy) = f on the unit square, zero Dirichlet
+ *   walls (eqs. (f1)-(f5)); kappa is the paper's coefficient c of eq. (f1),
+ *   taken here time-independent and per cell, and supplied either as a wave
+ *   speed (kappa = speed^2) or directly.
+ *   Time discretisation: the three-level implicit scheme of eq. (CN1) with
+ *   weights 1/2 on levels k+1 and k-1, factored in the alternating-direction
+ *   way of eqs. (fr1)-(fr2): first an implicit solve along every x-line, then
+ *   along every y-line.  With beta = dt^2/2 and r = beta kappa / h^2, one step
+ *   n -> n+1 is
+ *     rho   = dt^2 (kappa Lap_h u^n + f^n)               (5-point Laplacian)
+ *           = 2 r (u_W + u_E + u_S + u_N - 4 u_C) + dt^2 f^n
+ *     (I - beta K Lxx) w = rho      x-lines: -r w_{i-1} + (1+2r) w_i - r w_{i+1}
+ *     (I - beta K Lyy) d = w        y-lines: same coefficients along j
+ *     u^{n+1} = 2 u^n - u^{n-1} + d
+ *   The paper solves the line systems by cyclic reduction (Sec. 3.1); this
+ *   library solves them by an exact partition (sub-structuring) method, which
+ *   reaches the same solution up to rounding.
+ *
+ * Grids and layout: nx x ny interior nodes, spacing h (the walls are not
+ * stored); every field is row-major, node (i, j) at offset j*nx + i, x fastest.
+ * All field pointers are DEVICE pointers of the handle's element type
+ * (float for ADI_F32, double for ADI_F64), owned by the caller, contiguous,
+ * and must stay valid until the work queued on the handle's stream is done.
+ * Index arrays are device int32 arrays of flat node offsets j*nx + i.
+ *
+ * Ownership: the library owns the handle and its device workspace
+ * (coefficient field r, the x-sweep result w, chunk summaries of the y-line
+ * partition, reduced-system solution).  They are allocated by the create call
+ * and freed by the destroy call; stepping allocates nothing.
+ *
+ * Streams: every call queues work on the HIP stream bound to the handle (or
+ * passed explicitly) and returns without synchronising, except where stated.
+ *
+ * Errors: every entry point returns an adi_status.  Arguments are validated
+ * before anything is queued; on error nothing is written to the outputs and
+ * adi_last_error() returns a message (per host thread).  HIP runtime failures
+ * map to ADI_EHIP with the runtime's error string.
+ */
+#ifndef ADIWAVE_H
+#define ADIWAVE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adi_wave_s* adi_wave_t;          /* opaque; owned by the library */
+
+typedef enum { ADI_F32 = 0, ADI_F64 = 1 } adi_dtype;
+
+typedef enum {
+    ADI_OK = 0,
+    ADI_EINVAL = -1,          /* bad argument, detected before any work is queued */
+    ADI_ENOMEM = -2,          /* device allocation failed (create only) */
+    ADI_EHIP = -3,            /* HIP runtime error */
+    ADI_EUNSUPPORTED = -4     /* valid but outside what the kernels handle (sizes) */
+} adi_status;
+
+typedef enum {
+    ADI_START_PAPER = 0,      /* u^1 = u^0 + dt psi, eq. (CN2): first order in time */
+    ADI_START_GHOST = 1       /* scheme at n = 0 with ghost level u^{-1} = u^1 - 2 dt psi */
+} adi_start_mode;
+
+/* Point sources: f^n is zero except at `count` nodes, where it takes the values
+ * amp[k*count + s] for the k-th step of the call (the level n whose right-hand
+ * side is being built, eq. (CN1) uses f^k).  A discrete delta of strength s(t)
+ * is f = s(t)/h^2 at its node.  count may be 0 (idx/amp ignored).  At most
+ * ADI_MAX_SOURCES sources per call.  Offsets outside [0, nx*ny) are ignored. */
+#define ADI_MAX_SOURCES 1024
+typedef struct {
+    int count;
+    const int* idx;           /* device, count node offsets */
+    const void* amp;          /* device, nsteps x count values of the handle's type */
+} adi_source;
+
+/* Receivers: after step k of a call, u^{n+1} at node idx[r] is written to
+ * traces[k*count + r].  count may be 0.  An offset outside [0, nx*ny) records NaN. */
+typedef struct {
+    int count;
+    const int* idx;           /* device, count node offsets */
+    void* traces;             /* device, nsteps x count values of the handle's type */
+} adi_receivers;
+
+/* ---------------------------------------------------------------- handle ---- */
+
+/* Create a solver for an nx x ny interior grid with spacing h and time step dt.
+ * speed: device field (nx*ny, handle type) of wave speeds (kappa = speed^2),
+ *        or NULL to use the constant speed_scalar.  Speeds must be > 0.
+ * The per-node coefficient r = dt^2 speed^2 / (2 h^2) is computed on the
+ * device in the handle's type and kept in the workspace.
+ * hip_stream: hipStream_t the handle queues on (NULL = default stream).
+ * Limits: 1 <= nx <= 16384 (8192 for ADI_F64), 1 <= ny, nx*ny < 2^31.
+ * Synchronises the stream before returning (the workspace is ready). */
+adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
+                           const void* speed, double speed_scalar, adi_dtype dtype,
+                           void* hip_stream);
+
+/* Replace the coefficient by kappa directly (device field of the handle's
+ * type, or NULL to use kappa_scalar).  Queued on the handle's stream. */
+adi_status adi_wave_set_kappa(adi_wave_t w, const void* kappa, double kappa_scalar);
+
+/* Rebind the handle to another HIP stream. */
+adi_status adi_wave_set_stream(adi_wave_t w, void* hip_stream);
+
+/* Level u^1 from u^0 (Sec. 2, eq. (CN2) for ADI_START_PAPER; the second-order
+ * ghost-level start for ADI_START_GHOST).  psi: device field or NULL (zero
+ * initial velocity).  f0: sources of level 0 (amp holds 1 x count values) or
+ * NULL.  u1 must not alias u0 or psi. */
+adi_status adi_wave_start(adi_wave_t w, const void* u0, const void* psi,
+                          const adi_source* f0, int mode, void* u1);
+
+/* nsteps ADI steps (Sec. 2 scheme, Sec. 3 Algorithm 1 time loop).
+ * On entry *u_prev, *u_curr point to u^{n-1}, u^n.  Each step writes u^{n+1}
+ * over u^{n-1} and swaps the two pointers, so on return *u_curr points to
+ * u^{n+nsteps} and *u_prev to u^{n+nsteps-1} (the roles rotate as the
+ * paper's swap of level matrices).  f, rec: may be NULL.  nsteps >= 0. */
+adi_status adi_wave_step(adi_wave_t w, void** u_prev, void** u_curr,
+                         const adi_source* f, const adi_receivers* rec, int nsteps);
+
+/* Free the handle and its workspace (synchronises the handle's stream). */
+adi_status adi_wave_destroy(adi_wave_t w);
+
+/* ------------------------------------------------------- batched line solve -- */
+
+/* Solve `batch` independent tridiagonal systems of size n:
+ *   a[k] x[k-1] + b[k] x[k] + c[k] x[k+1] = d[k],  k = 0..n-1
+ * (a[0] and c[n-1] are ignored).  Element k of system s is at offset
+ * s*sys_stride + k*elem_stride (in elements) in each of a, b, c, d (device,
+ * dtype).  The solution overwrites d; a, b, c are not modified.  No pivoting:
+ * the systems must be solvable by Gaussian elimination without pivoting
+ * (e.g. strictly diagonally dominant), as the paper's line systems are.
+ * Contiguous systems (elem_stride == 1, n <= 16384 / 8192 for f64) are solved
+ * one per workgroup on chip; other layouts one per thread, with a library
+ * workspace of batch*n values allocated on first use and kept.
+ * hip_stream: stream to queue on (NULL = default). */
+adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* a,
+                                 const void* b, const void* c, void* d,
+                                 long long sys_stride, long long elem_stride,
+                                 void* hip_stream);
+
+/* ------------------------------------------------------ introspection/timing -- */
+
+typedef struct {
+    int nx, ny;
+    int dtype;
+    int x_threads_per_line;   /* x-sweep: threads cooperating on one x-line */
+    int x_elems_per_thread;   /* x-sweep: contiguous nodes per thread */
+    int x_rows_per_strip;     /* x-sweep: consecutive rows per thread group */
+    int y_chunk_rows;         /* y-lines are split in chunks of this many rows */
+    int y_chunks;             /* number of chunks per y-line */
+    int kernels_per_step;     /* launches queued per ADI step */
+    size_t workspace_bytes;   /* device bytes owned by the handle */
+} adi_wave_info;
+
+adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
+
+/* Override the launch configuration chosen at create (for the autotuner).
+ * Any field <= 0 keeps the current value.  Reallocates chunk workspace if the
+ * chunk size changes (synchronises the stream). */
+typedef struct {
+    int x_threads_per_line;   /* 64, 256 or 1024 */
+    int x_elems_per_thread;   /* 2, 4, 8 or 16 (f64: up to 8) */
+    int x_rows_per_strip;     /* >= 1 */
+    int y_chunk_rows;         /* 16 or 32 */
+} adi_tuning;
+adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t);
+
+/* Run nsteps steps exactly as adi_wave_step does, with HIP events around every
+ * launch; on return (the stream is synchronised) ms_per_kernel[k] holds the
+ * mean duration in milliseconds of launch kind k over the steps and names[k]
+ * its name, for k < *nkinds (at most 8). */
+adi_status adi_wave_profile(adi_wave_t w, void** u_prev, void** u_curr,
+                            const adi_source* f, int nsteps, double* ms_per_kernel,
+                            const char** names, int* nkinds);
+
+/* Plain device copy kernel of `bytes` bytes (a multiple of 16, 16-byte aligned
+ * pointers), for measuring achievable HBM bandwidth next to the solver. */
+adi_status adi_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char* adi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADIWAVE_H */

@@ -1,0 +1,232 @@
+"""MI355X (gfx950) ADI solver for the implicit finite-difference 2-D acoustic
+wave equation (Altybay, Ruzhansky, Tokmagambetov, Sec. 2 scheme, Sec. 3 time loop).
+
+Thin Python binding of libadiwave.so: argument marshalling only.  Every
+arithmetic step runs in the HIP kernels; PyTorch supplies device memory and the
+current stream.  There is no CPU fallback: a missing library raises.
+
+    import torch, paper_2006_10142_amd as adw
+    wave = adw.Wave(nx, ny, h, dt, c=speed_tensor_or_scalar, dtype=torch.float32)
+    u1 = wave.start(u0, mode="ghost")
+    u_prev, u_curr = wave.step(u0, u1, nsteps=100)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+from . import _lib
+from ._lib import AdiError
+
+__all__ = ["Wave", "tridiag_solve_batched", "stream_copy", "AdiError", "lib_path"]
+
+lib_path = _lib.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dtype) -> int:
+    torch = _torch()
+    if dtype == torch.float32:
+        return _lib.ADI_F32
+    if dtype == torch.float64:
+        return _lib.ADI_F64
+    raise TypeError(f"unsupported dtype {dtype} (float32 or float64)")
+
+
+def _stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _field(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _index(t, name):
+    torch = _torch()
+    if t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous() or t.dim() != 1:
+        raise ValueError(f"{name} must be a contiguous 1-D int32 device tensor")
+    return t
+
+
+class Wave:
+    """Handle of one nx x ny grid (interior nodes, spacing h, time step dt).
+
+    c: wave speed, scalar or (ny, nx) device tensor; the coefficient of the
+    Laplacian is kappa = c**2.  Alternatively pass ``kappa=`` directly.
+    """
+
+    def __init__(self, nx: int, ny: int, h: float, dt: float, c=1.0, dtype=None,
+                 kappa=None):
+        torch = _torch()
+        dtype = torch.float32 if dtype is None else dtype
+        self.nx, self.ny, self.h, self.dt, self.dtype = int(nx), int(ny), float(h), float(dt), dtype
+        self._code = _dtype_code(dtype)
+        lib = _lib.load()
+        handle = ctypes.c_void_p()
+        speed_ptr, speed_scalar = None, 1.0
+        if kappa is None and isinstance(c, torch.Tensor):
+            speed_ptr = _field(c, dtype, (self.ny, self.nx), "c")
+        elif kappa is None:
+            speed_scalar = float(c)
+        self._stream = torch.cuda.current_stream().cuda_stream
+        _lib.check(lib.adi_wave_create(ctypes.byref(handle), self.nx, self.ny, self.h, self.dt,
+                                       speed_ptr, speed_scalar, self._code,
+                                       ctypes.c_void_p(self._stream)))
+        self._h = handle
+        if kappa is not None:
+            self.set_kappa(kappa)
+
+    # -- plumbing ------------------------------------------------------------
+    def _sync_stream(self):
+        s = _torch().cuda.current_stream().cuda_stream
+        if s != self._stream:
+            _lib.check(_lib.load().adi_wave_set_stream(self._h, ctypes.c_void_p(s)))
+            self._stream = s
+
+    def _shape(self):
+        return (self.ny, self.nx)
+
+    def _sources(self, src_idx, src_amp, nsteps):
+        if src_idx is None or src_idx.numel() == 0:
+            return None
+        _index(src_idx, "src_idx")
+        n = src_idx.numel()
+        if src_amp is None or src_amp.dtype != self.dtype or src_amp.device.type != "cuda" \
+                or not src_amp.is_contiguous() or src_amp.numel() < nsteps * n:
+            raise ValueError("src_amp must be a contiguous device tensor of the handle dtype "
+                             "holding nsteps x count values")
+        return _lib.AdiSource(n, src_idx.data_ptr(), src_amp.data_ptr())
+
+    # -- API -----------------------------------------------------------------
+    def set_kappa(self, kappa):
+        """Replace the coefficient by kappa (scalar or (ny, nx) device tensor)."""
+        self._sync_stream()
+        torch = _torch()
+        if isinstance(kappa, torch.Tensor):
+            ptr, sc = _field(kappa, self.dtype, self._shape(), "kappa"), 1.0
+        else:
+            ptr, sc = None, float(kappa)
+        _lib.check(_lib.load().adi_wave_set_kappa(self._h, ptr, sc))
+
+    def start(self, u0, psi=None, src_idx=None, src_amp0=None, mode: str = "ghost", out=None):
+        """Level u^1 from u^0 (mode 'paper': eq. (CN2); 'ghost': second-order start)."""
+        self._sync_stream()
+        torch = _torch()
+        p0 = _field(u0, self.dtype, self._shape(), "u0")
+        pp = None if psi is None else _field(psi, self.dtype, self._shape(), "psi")
+        u1 = torch.empty_like(u0) if out is None else out
+        p1 = _field(u1, self.dtype, self._shape(), "u1")
+        src = self._sources(src_idx, src_amp0, 1)
+        m = {"paper": _lib.ADI_START_PAPER, "ghost": _lib.ADI_START_GHOST}[mode]
+        _lib.check(_lib.load().adi_wave_start(self._h, p0, pp,
+                                              ctypes.byref(src) if src else None, m, p1))
+        return u1
+
+    def step(self, u_prev, u_curr, nsteps: int = 1, src_idx=None, src_amp=None,
+             rec_idx=None, traces=None) -> Tuple:
+        """nsteps ADI steps; returns (u_prev, u_curr) holding u^{n+nsteps-1}, u^{n+nsteps}.
+
+        The two tensors are reused: u^{n+1} overwrites u^{n-1} each step, so the
+        returned pair is (u_prev, u_curr) or (u_curr, u_prev) depending on parity.
+        rec_idx/traces: int32 node offsets and a (nsteps, count) output tensor.
+        """
+        self._sync_stream()
+        a = _field(u_prev, self.dtype, self._shape(), "u_prev")
+        b = _field(u_curr, self.dtype, self._shape(), "u_curr")
+        src = self._sources(src_idx, src_amp, nsteps)
+        rec = None
+        if rec_idx is not None and rec_idx.numel() > 0:
+            _index(rec_idx, "rec_idx")
+            if traces is None or traces.dtype != self.dtype or not traces.is_contiguous() \
+                    or traces.numel() < nsteps * rec_idx.numel():
+                raise ValueError("traces must be a contiguous (nsteps, count) tensor of the handle dtype")
+            rec = _lib.AdiReceivers(rec_idx.numel(), rec_idx.data_ptr(), traces.data_ptr())
+        pa, pb = ctypes.c_void_p(a.value), ctypes.c_void_p(b.value)
+        _lib.check(_lib.load().adi_wave_step(self._h, ctypes.byref(pa), ctypes.byref(pb),
+                                             ctypes.byref(src) if src else None,
+                                             ctypes.byref(rec) if rec else None, int(nsteps)))
+        if pb.value == b.value:
+            return u_prev, u_curr
+        return u_curr, u_prev
+
+    def profile(self, u_prev, u_curr, nsteps: int, src_idx=None, src_amp=None):
+        """Run nsteps steps with per-launch events; returns ((u_prev, u_curr), {kernel: mean ms})."""
+        self._sync_stream()
+        a = _field(u_prev, self.dtype, self._shape(), "u_prev")
+        b = _field(u_curr, self.dtype, self._shape(), "u_curr")
+        src = self._sources(src_idx, src_amp, nsteps)
+        ms = (ctypes.c_double * 8)()
+        names = (ctypes.c_char_p * 8)()
+        nk = ctypes.c_int(0)
+        pa, pb = ctypes.c_void_p(a.value), ctypes.c_void_p(b.value)
+        _lib.check(_lib.load().adi_wave_profile(self._h, ctypes.byref(pa), ctypes.byref(pb),
+                                                ctypes.byref(src) if src else None, int(nsteps),
+                                                ms, names, ctypes.byref(nk)))
+        out = {names[k].decode(): ms[k] for k in range(nk.value)}
+        levels = (u_prev, u_curr) if pb.value == b.value else (u_curr, u_prev)
+        return levels, out
+
+    def info(self) -> dict:
+        inf = _lib.AdiWaveInfo()
+        _lib.check(_lib.load().adi_wave_get_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _lib.AdiWaveInfo._fields_}
+
+    def set_tuning(self, x_threads_per_line=0, x_elems_per_thread=0, x_rows_per_strip=0,
+                   y_chunk_rows=0):
+        self._sync_stream()
+        t = _lib.AdiTuning(x_threads_per_line, x_elems_per_thread, x_rows_per_strip, y_chunk_rows)
+        _lib.check(_lib.load().adi_wave_set_tuning(self._h, ctypes.byref(t)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.load().adi_wave_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tridiag_solve_batched(a, b, c, d, n: int, batch: int, sys_stride: int, elem_stride: int = 1):
+    """Solve batch tridiagonal systems in place in d (see tridiag_solve_batched in adiwave.h)."""
+    torch = _torch()
+    for name, t in (("a", a), ("b", b), ("c", c), ("d", d)):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor")
+        if t.dtype != d.dtype:
+            raise TypeError("a, b, c and d must share one dtype")
+    if n > 0 and batch > 0:
+        need = (batch - 1) * sys_stride + (n - 1) * elem_stride + 1
+        for name, t in (("a", a), ("b", b), ("c", c), ("d", d)):
+            if t.numel() < need:
+                raise ValueError(f"{name} holds {t.numel()} values, the layout needs {need}")
+    code = _dtype_code(d.dtype)
+    _lib.check(_lib.load().tridiag_solve_batched(code, int(n), int(batch), a.data_ptr(),
+                                                 b.data_ptr(), c.data_ptr(), d.data_ptr(),
+                                                 int(sys_stride), int(elem_stride), _stream_ptr()))
+    return d
+
+
+def stream_copy(src, dst):
+    """Device copy through the library's plain copy kernel (bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst too small")
+    _lib.check(_lib.load().adi_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream_ptr()))
+    return dst

@@ -1,0 +1,672 @@
+// adiwave.hip -- C-ABI runtime of the gfx950 ADI wave solver: handles,
+// workspace, launch planning, argument validation and error reporting.
+// The operations and their layouts are specified in include/adiwave.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "adiwave.h"
+#include "kernels.hpp"
+
+using namespace adw;
+
+// --------------------------------------------------------------- errors ----
+namespace {
+
+thread_local std::string g_err;
+
+adi_status fail(adi_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define ADI_HIP(call)                                                                \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return fail(ADI_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define ADI_LAUNCHED(name)                                                           \
+    do {                                                                             \
+        hipError_t e_ = hipGetLastError();                                           \
+        if (e_ != hipSuccess)                                                        \
+            return fail(ADI_EHIP, std::string("launch ") + (name) + ": " +           \
+                                      hipGetErrorString(e_));                        \
+    } while (0)
+
+size_t esize(adi_dtype t) { return t == ADI_F64 ? 8 : 4; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// ---------------------------------------------------------- launch plans ----
+struct XPlan { int tr, s, rs; };
+
+// Smallest (threads per line, nodes per thread) whose product covers nx.
+bool choose_x(int nx, adi_dtype dt, XPlan& p)
+{
+    static const int cand[][2] = {{64, 2}, {64, 4}, {64, 8}, {64, 16}, {256, 8},
+                                  {256, 16}, {1024, 8}, {1024, 16}};
+    for (auto& c : cand) {
+        if (dt == ADI_F64 && c[1] > 8) continue;
+        if ((long long)c[0] * c[1] >= nx) { p.tr = c[0]; p.s = c[1]; return true; }
+    }
+    return false;
+}
+
+int x_groups_per_wg(int tr) { return tr >= 256 ? 1 : 256 / tr; }
+
+// rows per strip: enough workgroups to cover 256 CUs twice, at most 32 rows
+int choose_rows(int ny, int tr)
+{
+    const int g = x_groups_per_wg(tr);
+    int rs = ny / (512 * g);
+    return std::max(1, std::min(32, rs));
+}
+
+struct YScanPlan { int sk, p; };
+bool choose_yscan(int K, YScanPlan& q)
+{
+    static const int ps[] = {16, 64, 256};
+    static const int sks[] = {2, 4, 8, 16};
+    for (int p : ps)
+        for (int sk : sks)
+            if ((long long)p * sk >= K) { q.p = p; q.sk = sk; return true; }
+    return false;
+}
+
+// ---------------------------------------------------- template dispatch ----
+template <typename T, int S, int TR>
+void launch_x1(int grid, const XArgs<T>& a, hipStream_t st)
+{
+    constexpr int NT = TR >= 256 ? TR : 256;
+    hipLaunchKernelGGL((k_xsweep<T, S, TR>), dim3(grid), dim3(NT), 0, st, a);
+}
+
+template <typename T, int TR>
+bool launch_x_s(int s, int grid, const XArgs<T>& a, hipStream_t st)
+{
+    switch (s) {
+        case 2: launch_x1<T, 2, TR>(grid, a, st); return true;
+        case 4: launch_x1<T, 4, TR>(grid, a, st); return true;
+        case 8: launch_x1<T, 8, TR>(grid, a, st); return true;
+        case 16:
+            if constexpr (sizeof(T) == 4) { launch_x1<T, 16, TR>(grid, a, st); return true; }
+            return false;
+    }
+    return false;
+}
+
+template <typename T>
+bool launch_x(const XPlan& p, int grid, const XArgs<T>& a, hipStream_t st)
+{
+    switch (p.tr) {
+        case 64: return launch_x_s<T, 64>(p.s, grid, a, st);
+        case 256: return launch_x_s<T, 256>(p.s, grid, a, st);
+        case 1024: return launch_x_s<T, 1024>(p.s, grid, a, st);
+    }
+    return false;
+}
+
+template <typename T, int P>
+bool launch_yscan_sk(int sk, int grid, const YArgs<T>& a, hipStream_t st)
+{
+    switch (sk) {
+        case 2: hipLaunchKernelGGL((k_yscan<T, 2, P>), dim3(grid), dim3(256), 0, st, a); return true;
+        case 4: hipLaunchKernelGGL((k_yscan<T, 4, P>), dim3(grid), dim3(256), 0, st, a); return true;
+        case 8: hipLaunchKernelGGL((k_yscan<T, 8, P>), dim3(grid), dim3(256), 0, st, a); return true;
+        case 16: hipLaunchKernelGGL((k_yscan<T, 16, P>), dim3(grid), dim3(256), 0, st, a); return true;
+    }
+    return false;
+}
+
+template <typename T>
+bool launch_yscan(const YScanPlan& q, int nx, const YArgs<T>& a, hipStream_t st)
+{
+    const int cb = 256 / q.p;
+    const int grid = (nx + cb - 1) / cb;
+    switch (q.p) {
+        case 16: return launch_yscan_sk<T, 16>(q.sk, grid, a, st);
+        case 64: return launch_yscan_sk<T, 64>(q.sk, grid, a, st);
+        case 256: return launch_yscan_sk<T, 256>(q.sk, grid, a, st);
+    }
+    return false;
+}
+
+template <typename T>
+bool launch_ysolve(int M, dim3 grid, const YArgs<T>& a, hipStream_t st)
+{
+    switch (M) {
+        case 16: hipLaunchKernelGGL((k_ysolve<T, 16>), grid, dim3(256), 0, st, a); return true;
+        case 32: hipLaunchKernelGGL((k_ysolve<T, 32>), grid, dim3(256), 0, st, a); return true;
+    }
+    return false;
+}
+
+template <typename T, int S, int TR>
+void launch_tri1(long long batch, const TriArgs<T>& a, hipStream_t st)
+{
+    constexpr int NT = TR >= 256 ? TR : 256;
+    constexpr int G = NT / TR;
+    const long long grid = (batch + G - 1) / G;
+    hipLaunchKernelGGL((k_tridiag_wg<T, S, TR>), dim3((unsigned)grid), dim3(NT), 0, st, a);
+}
+
+template <typename T, int TR>
+bool launch_tri_s(int s, long long batch, const TriArgs<T>& a, hipStream_t st)
+{
+    switch (s) {
+        case 2: launch_tri1<T, 2, TR>(batch, a, st); return true;
+        case 4: launch_tri1<T, 4, TR>(batch, a, st); return true;
+        case 8: launch_tri1<T, 8, TR>(batch, a, st); return true;
+        case 16:
+            if constexpr (sizeof(T) == 4) { launch_tri1<T, 16, TR>(batch, a, st); return true; }
+            return false;
+    }
+    return false;
+}
+
+template <typename T>
+bool launch_tri(const XPlan& p, long long batch, const TriArgs<T>& a, hipStream_t st)
+{
+    switch (p.tr) {
+        case 64: return launch_tri_s<T, 64>(p.s, batch, a, st);
+        case 256: return launch_tri_s<T, 256>(p.s, batch, a, st);
+        case 1024: return launch_tri_s<T, 1024>(p.s, batch, a, st);
+    }
+    return false;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- handle ----
+struct adi_wave_s {
+    int nx = 0, ny = 0;
+    double h = 0, dt = 0;
+    adi_dtype dtype = ADI_F32;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void* r = nullptr;     // nx*ny
+    void* w = nullptr;     // nx*ny
+    void* sum = nullptr;   // 8 * K * nx
+    void* X = nullptr;     // K * nx
+    XPlan xp{};
+    int M = 32, K = 0;
+    YScanPlan yq{};
+    size_t bytes = 0;
+};
+
+namespace {
+
+void free_ws(adi_wave_s* w)
+{
+    if (w->r) (void)hipFree(w->r);
+    if (w->w) (void)hipFree(w->w);
+    if (w->sum) (void)hipFree(w->sum);
+    if (w->X) (void)hipFree(w->X);
+    w->r = w->w = w->sum = w->X = nullptr;
+}
+
+adi_status alloc_chunks(adi_wave_s* w)
+{
+    const size_t es = esize(w->dtype);
+    if (w->sum) (void)hipFree(w->sum);
+    if (w->X) (void)hipFree(w->X);
+    w->sum = w->X = nullptr;
+    w->K = (w->ny + w->M - 1) / w->M;
+    if (!choose_yscan(w->K, w->yq))
+        return fail(ADI_EUNSUPPORTED, "too many y-chunks for the interface solver");
+    const size_t nsum = (size_t)kSummaryPlanes * w->K * w->nx;
+    const size_t nX = (size_t)w->K * w->nx;
+    if (hipMalloc(&w->sum, nsum * es) != hipSuccess || hipMalloc(&w->X, nX * es) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ADI_ENOMEM, "hipMalloc of y-chunk workspace failed");
+    }
+    w->bytes = 2 * (size_t)w->nx * w->ny * es + (nsum + nX) * es;
+    return ADI_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+adi_status check_handle(adi_wave_t w)
+{
+    if (!w) return fail(ADI_EINVAL, "null handle");
+    return ADI_OK;
+}
+
+// f / rec validation (pointers only; offsets are checked on the host only when
+// the index arrays are host-visible, which device arrays are not)
+adi_status check_src(const adi_source* f)
+{
+    if (!f || f->count == 0) return ADI_OK;
+    if (f->count < 0 || f->count > ADI_MAX_SOURCES)
+        return fail(ADI_EINVAL, "source count out of range [0, ADI_MAX_SOURCES]");
+    if (!f->idx || !f->amp) return fail(ADI_EINVAL, "source idx/amp is null");
+    return ADI_OK;
+}
+
+adi_status check_rec(const adi_receivers* r)
+{
+    if (!r || r->count == 0) return ADI_OK;
+    if (r->count < 0) return fail(ADI_EINVAL, "negative receiver count");
+    if (!r->idx || !r->traces) return fail(ADI_EINVAL, "receiver idx/traces is null");
+    return ADI_OK;
+}
+
+template <typename T>
+XArgs<T> make_x(const adi_wave_s* w, const void* u, const adi_source* f, int k, T rho_scale)
+{
+    XArgs<T> a{};
+    a.u = static_cast<const T*>(u);
+    a.r = static_cast<const T*>(w->r);
+    a.w = static_cast<T*>(w->w);
+    a.nx = w->nx;
+    a.ny = w->ny;
+    a.rows_per_strip = w->xp.rs;
+    a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && ((size_t)w->xp.s * sizeof(T)) % 16 == 0 &&
+            aligned16(u) && aligned16(w->r) && aligned16(w->w);
+    a.rho_scale = rho_scale;
+    a.tau2 = (T)(w->dt * w->dt);
+    if (f && f->count > 0) {
+        a.nsrc = f->count;
+        a.src_idx = f->idx;
+        a.src_amp = static_cast<const T*>(f->amp) + (size_t)k * f->count;
+    }
+    return a;
+}
+
+template <typename T>
+YArgs<T> make_y(const adi_wave_s* w, const void* u, const void* v, void* out, T alpha, T beta)
+{
+    YArgs<T> a{};
+    a.w = static_cast<const T*>(w->w);
+    a.r = static_cast<const T*>(w->r);
+    a.nx = w->nx;
+    a.ny = w->ny;
+    a.M = w->M;
+    a.K = w->K;
+    a.sum = static_cast<T*>(w->sum);
+    a.X = static_cast<T*>(w->X);
+    a.u = static_cast<const T*>(u);
+    a.v = static_cast<const T*>(v);
+    a.out = static_cast<T*>(out);
+    a.alpha = alpha;
+    a.beta = beta;
+    return a;
+}
+
+int x_grid(const adi_wave_s* w)
+{
+    const int g = x_groups_per_wg(w->xp.tr);
+    const int strips = (w->ny + w->xp.rs - 1) / w->xp.rs;
+    return (strips + g - 1) / g;
+}
+
+// Queue one solve: x-sweep of `u` (with sources f at step k) then the y-chain
+// writing out = alpha*u + beta*v + d.  `ev` (optional) receives 5 events
+// bracketing the 4 launches.
+template <typename T>
+adi_status queue_solve(adi_wave_s* w, const void* u, const void* v, void* out, T alpha, T beta,
+                       const adi_source* f, int k, T rho_scale, hipEvent_t* ev)
+{
+    hipStream_t st = w->stream;
+    if (ev) ADI_HIP(hipEventRecord(ev[0], st));
+    XArgs<T> xa = make_x<T>(w, u, f, k, rho_scale);
+    if (!launch_x<T>(w->xp, x_grid(w), xa, st))
+        return fail(ADI_EUNSUPPORTED, "no x-sweep kernel for this configuration");
+    ADI_LAUNCHED("x_sweep_rhs");
+    if (ev) ADI_HIP(hipEventRecord(ev[1], st));
+    YArgs<T> ya = make_y<T>(w, u, v, out, alpha, beta);
+    const dim3 yg((w->nx + 255) / 256, w->K);
+    hipLaunchKernelGGL((k_yreduce<T>), yg, dim3(256), 0, st, ya);
+    ADI_LAUNCHED("y_reduce");
+    if (ev) ADI_HIP(hipEventRecord(ev[2], st));
+    if (!launch_yscan<T>(w->yq, w->nx, ya, st))
+        return fail(ADI_EUNSUPPORTED, "no y-interface kernel for this configuration");
+    ADI_LAUNCHED("y_scan");
+    if (ev) ADI_HIP(hipEventRecord(ev[3], st));
+    if (!launch_ysolve<T>(w->M, yg, ya, st))
+        return fail(ADI_EUNSUPPORTED, "no y-solve kernel for this chunk size");
+    ADI_LAUNCHED("y_solve_update");
+    if (ev) ADI_HIP(hipEventRecord(ev[4], st));
+    return ADI_OK;
+}
+
+template <typename T>
+adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared)
+{
+    const long long n = (long long)w->nx * w->ny;
+    const double s = w->dt * w->dt / (2.0 * w->h * w->h);
+    const int grid = (int)std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_coef<T>), dim3(grid), dim3(256), 0, w->stream,
+                       static_cast<const T*>(field), (T)scalar, squared, (T)s,
+                       static_cast<T*>(w->r), n);
+    ADI_LAUNCHED("coef");
+    return ADI_OK;
+}
+
+template <typename T>
+adi_status do_step(adi_wave_s* w, void** u_prev, void** u_curr, const adi_source* f,
+                   const adi_receivers* rec, int nsteps)
+{
+    for (int k = 0; k < nsteps; ++k) {
+        adi_status s = queue_solve<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1), nullptr);
+        if (s != ADI_OK) return s;
+        if (rec && rec->count > 0) {
+            hipLaunchKernelGGL((k_record<T>), dim3((rec->count + 255) / 256), dim3(256), 0, w->stream,
+                               static_cast<const T*>(*u_prev), rec->idx,
+                               static_cast<T*>(rec->traces) + (size_t)k * rec->count, rec->count,
+                               (long long)w->nx * w->ny);
+            ADI_LAUNCHED("record");
+        }
+        std::swap(*u_prev, *u_curr);
+    }
+    return ADI_OK;
+}
+
+template <typename T>
+adi_status do_start(adi_wave_s* w, const void* u0, const void* psi, const adi_source* f0, int mode,
+                    void* u1)
+{
+    if (mode == ADI_START_PAPER) {
+        const long long n = (long long)w->nx * w->ny;
+        const int grid = (int)std::min<long long>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL((k_start_paper<T>), dim3(grid), dim3(256), 0, w->stream,
+                           static_cast<const T*>(u0), static_cast<const T*>(psi), (T)w->dt,
+                           static_cast<T*>(u1), n);
+        ADI_LAUNCHED("start_paper");
+        return ADI_OK;
+    }
+    // ghost start: u1 = u0 + dt psi + e,  (I - bKLxx)(I - bKLyy) e = rho(u0, f0) / 2
+    return queue_solve<T>(w, u0, psi, u1, T(1), psi ? (T)w->dt : T(0), f0, 0, T(0.5), nullptr);
+}
+
+}  // namespace
+
+// ================================================================== C ABI ====
+extern "C" {
+
+const char* adi_last_error(void) { return g_err.c_str(); }
+
+adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt, const void* speed,
+                           double speed_scalar, adi_dtype dtype, void* hip_stream)
+{
+    if (!out) return fail(ADI_EINVAL, "out is null");
+    *out = nullptr;
+    if (dtype != ADI_F32 && dtype != ADI_F64) return fail(ADI_EINVAL, "unknown dtype");
+    if (nx < 1 || ny < 1) return fail(ADI_EINVAL, "nx and ny must be >= 1");
+    if ((long long)nx * ny >= (1LL << 31)) return fail(ADI_EUNSUPPORTED, "nx*ny must be < 2^31");
+    if (!finite_pos(h) || !finite_pos(dt)) return fail(ADI_EINVAL, "h and dt must be finite and > 0");
+    if (!speed && !finite_pos(speed_scalar))
+        return fail(ADI_EINVAL, "speed_scalar must be finite and > 0 when speed is NULL");
+    XPlan xp{};
+    if (!choose_x(nx, dtype, xp))
+        return fail(ADI_EUNSUPPORTED, dtype == ADI_F64 ? "nx > 8192 is not supported for f64"
+                                                       : "nx > 16384 is not supported");
+    xp.rs = choose_rows(ny, xp.tr);
+
+    adi_wave_s* w = new adi_wave_s();
+    w->nx = nx; w->ny = ny; w->h = h; w->dt = dt; w->dtype = dtype;
+    w->stream = static_cast<hipStream_t>(hip_stream);
+    w->xp = xp;
+    w->M = 32;
+    if (hipGetDevice(&w->device) != hipSuccess) {
+        delete w;
+        return fail(ADI_EHIP, "hipGetDevice failed");
+    }
+    const size_t es = esize(dtype);
+    const size_t npts = (size_t)nx * ny;
+    if (hipMalloc(&w->r, npts * es) != hipSuccess || hipMalloc(&w->w, npts * es) != hipSuccess) {
+        (void)hipGetLastError();
+        free_ws(w);
+        delete w;
+        return fail(ADI_ENOMEM, "hipMalloc of the coefficient/x-sweep fields failed");
+    }
+    adi_status s = alloc_chunks(w);
+    if (s == ADI_OK)
+        s = (dtype == ADI_F32) ? set_coef<float>(w, speed, speed_scalar, 1)
+                               : set_coef<double>(w, speed, speed_scalar, 1);
+    if (s == ADI_OK && hipStreamSynchronize(w->stream) != hipSuccess)
+        s = fail(ADI_EHIP, "stream synchronise after create failed");
+    if (s != ADI_OK) {
+        free_ws(w);
+        delete w;
+        return s;
+    }
+    *out = w;
+    return ADI_OK;
+}
+
+adi_status adi_wave_set_kappa(adi_wave_t w, const void* kappa, double kappa_scalar)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!kappa && !finite_pos(kappa_scalar))
+        return fail(ADI_EINVAL, "kappa_scalar must be finite and > 0 when kappa is NULL");
+    return w->dtype == ADI_F32 ? set_coef<float>(w, kappa, kappa_scalar, 0)
+                               : set_coef<double>(w, kappa, kappa_scalar, 0);
+}
+
+adi_status adi_wave_set_stream(adi_wave_t w, void* hip_stream)
+{
+    if (adi_status s = check_handle(w)) return s;
+    w->stream = static_cast<hipStream_t>(hip_stream);
+    return ADI_OK;
+}
+
+adi_status adi_wave_start(adi_wave_t w, const void* u0, const void* psi, const adi_source* f0,
+                          int mode, void* u1)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!u0 || !u1) return fail(ADI_EINVAL, "u0 and u1 must be non-null");
+    if (u1 == u0 || (psi && u1 == psi)) return fail(ADI_EINVAL, "u1 must not alias u0 or psi");
+    if (mode != ADI_START_PAPER && mode != ADI_START_GHOST) return fail(ADI_EINVAL, "unknown start mode");
+    if (adi_status s = check_src(f0)) return s;
+    return w->dtype == ADI_F32 ? do_start<float>(w, u0, psi, f0, mode, u1)
+                               : do_start<double>(w, u0, psi, f0, mode, u1);
+}
+
+adi_status adi_wave_step(adi_wave_t w, void** u_prev, void** u_curr, const adi_source* f,
+                         const adi_receivers* rec, int nsteps)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!u_prev || !u_curr || !*u_prev || !*u_curr) return fail(ADI_EINVAL, "null level pointer");
+    if (*u_prev == *u_curr) return fail(ADI_EINVAL, "u_prev and u_curr must be distinct buffers");
+    if (nsteps < 0) return fail(ADI_EINVAL, "nsteps must be >= 0");
+    if (adi_status s = check_src(f)) return s;
+    if (adi_status s = check_rec(rec)) return s;
+    return w->dtype == ADI_F32 ? do_step<float>(w, u_prev, u_curr, f, rec, nsteps)
+                               : do_step<double>(w, u_prev, u_curr, f, rec, nsteps);
+}
+
+adi_status adi_wave_destroy(adi_wave_t w)
+{
+    if (!w) return ADI_OK;
+    (void)hipStreamSynchronize(w->stream);
+    free_ws(w);
+    delete w;
+    return ADI_OK;
+}
+
+adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!info) return fail(ADI_EINVAL, "info is null");
+    info->nx = w->nx;
+    info->ny = w->ny;
+    info->dtype = (int)w->dtype;
+    info->x_threads_per_line = w->xp.tr;
+    info->x_elems_per_thread = w->xp.s;
+    info->x_rows_per_strip = w->xp.rs;
+    info->y_chunk_rows = w->M;
+    info->y_chunks = w->K;
+    info->kernels_per_step = 4;
+    info->workspace_bytes = w->bytes;
+    return ADI_OK;
+}
+
+adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!t) return fail(ADI_EINVAL, "tuning is null");
+    XPlan xp = w->xp;
+    if (t->x_threads_per_line > 0) xp.tr = t->x_threads_per_line;
+    if (t->x_elems_per_thread > 0) xp.s = t->x_elems_per_thread;
+    if (t->x_rows_per_strip > 0) xp.rs = t->x_rows_per_strip;
+    if (xp.tr != 64 && xp.tr != 256 && xp.tr != 1024)
+        return fail(ADI_EINVAL, "x_threads_per_line must be 64, 256 or 1024");
+    if (xp.s != 2 && xp.s != 4 && xp.s != 8 && !(xp.s == 16 && w->dtype == ADI_F32))
+        return fail(ADI_EINVAL, "x_elems_per_thread must be 2, 4, 8 (or 16 for f32)");
+    if ((long long)xp.tr * xp.s < w->nx)
+        return fail(ADI_EINVAL, "x_threads_per_line * x_elems_per_thread must cover nx");
+    const int M = t->y_chunk_rows > 0 ? t->y_chunk_rows : w->M;
+    if (M != 16 && M != 32) return fail(ADI_EINVAL, "y_chunk_rows must be 16 or 32");
+    w->xp = xp;
+    if (M != w->M) {
+        if (hipStreamSynchronize(w->stream) != hipSuccess)
+            return fail(ADI_EHIP, "stream synchronise failed");
+        w->M = M;
+        return alloc_chunks(w);
+    }
+    return ADI_OK;
+}
+
+adi_status adi_wave_profile(adi_wave_t w, void** u_prev, void** u_curr, const adi_source* f,
+                            int nsteps, double* ms_per_kernel, const char** names, int* nkinds)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!u_prev || !u_curr || !*u_prev || !*u_curr) return fail(ADI_EINVAL, "null level pointer");
+    if (*u_prev == *u_curr) return fail(ADI_EINVAL, "u_prev and u_curr must be distinct buffers");
+    if (nsteps < 1 || nsteps > 100000) return fail(ADI_EINVAL, "nsteps must be in [1, 100000]");
+    if (!ms_per_kernel || !nkinds) return fail(ADI_EINVAL, "null output");
+    if (adi_status s = check_src(f)) return s;
+    static const char* kNames[4] = {"x_sweep_rhs", "y_reduce", "y_scan", "y_solve_update"};
+    std::vector<hipEvent_t> ev((size_t)nsteps * 5, nullptr);
+    adi_status st = ADI_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { st = fail(ADI_EHIP, "hipEventCreate failed"); break; }
+    for (int k = 0; k < nsteps && st == ADI_OK; ++k) {
+        hipEvent_t* e = &ev[(size_t)k * 5];
+        st = w->dtype == ADI_F32
+                 ? queue_solve<float>(w, *u_curr, *u_prev, *u_prev, 2.f, -1.f, f, k, 1.f, e)
+                 : queue_solve<double>(w, *u_curr, *u_prev, *u_prev, 2.0, -1.0, f, k, 1.0, e);
+        if (st == ADI_OK) std::swap(*u_prev, *u_curr);
+    }
+    if (st == ADI_OK && hipStreamSynchronize(w->stream) != hipSuccess)
+        st = fail(ADI_EHIP, "stream synchronise failed");
+    if (st == ADI_OK) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int k = 0; k < nsteps && st == ADI_OK; ++k)
+            for (int q = 0; q < 4; ++q) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[(size_t)k * 5 + q], ev[(size_t)k * 5 + q + 1]) != hipSuccess) {
+                    st = fail(ADI_EHIP, "hipEventElapsedTime failed");
+                    break;
+                }
+                acc[q] += ms;
+            }
+        if (st == ADI_OK) {
+            for (int q = 0; q < 4; ++q) {
+                ms_per_kernel[q] = acc[q] / nsteps;
+                if (names) names[q] = kNames[q];
+            }
+            *nkinds = 4;
+        }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
+
+adi_status adi_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream)
+{
+    if (!src || !dst) return fail(ADI_EINVAL, "null pointer");
+    if (bytes % 16 != 0 || !aligned16(src) || !aligned16(dst))
+        return fail(ADI_EINVAL, "bytes must be a multiple of 16 and pointers 16-byte aligned");
+    const long long n = (long long)(bytes / 16);
+    if (n == 0) return ADI_OK;
+    const int grid = (int)std::min<long long>((n + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       static_cast<const float4*>(src), static_cast<float4*>(dst), n);
+    ADI_LAUNCHED("copy");
+    return ADI_OK;
+}
+
+// scratch of the per-thread batched path, one per device, grown on demand
+static std::mutex g_scr_mu;
+static std::vector<std::pair<void*, size_t>> g_scr;
+
+adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* a, const void* b,
+                                 const void* c, void* d, long long sys_stride,
+                                 long long elem_stride, void* hip_stream)
+{
+    if (dtype != ADI_F32 && dtype != ADI_F64) return fail(ADI_EINVAL, "unknown dtype");
+    if (n < 0 || batch < 0) return fail(ADI_EINVAL, "n and batch must be >= 0");
+    if (n == 0 || batch == 0) return ADI_OK;
+    if (!a || !b || !c || !d) return fail(ADI_EINVAL, "null array");
+    if (d == a || d == b || d == c) return fail(ADI_EINVAL, "d must not alias a, b or c");
+    if (elem_stride < 1) return fail(ADI_EINVAL, "elem_stride must be >= 1");
+    if (batch > 1 && sys_stride < 1) return fail(ADI_EINVAL, "sys_stride must be >= 1 when batch > 1");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    XPlan p{};
+    const bool wg_path = elem_stride == 1 && choose_x(n, dtype, p);
+    const size_t es = esize(dtype);
+    if (wg_path) {
+        const bool vec = aligned16(a) && aligned16(b) && aligned16(c) && aligned16(d) &&
+                         ((size_t)sys_stride * es) % 16 == 0 && ((size_t)p.s * es) % 16 == 0;
+        bool ok;
+        if (dtype == ADI_F32) {
+            TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
+                             sys_stride, elem_stride, vec, nullptr};
+            ok = launch_tri<float>(p, batch, t, st);
+        } else {
+            TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
+                              sys_stride, elem_stride, vec, nullptr};
+            ok = launch_tri<double>(p, batch, t, st);
+        }
+        if (!ok) return fail(ADI_EUNSUPPORTED, "no batched kernel for this size");
+        ADI_LAUNCHED("tridiag_wg");
+        return ADI_OK;
+    }
+    int dev = 0;
+    ADI_HIP(hipGetDevice(&dev));
+    const size_t need = (size_t)n * batch * es;
+    void* scr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scr_mu);
+        if ((int)g_scr.size() <= dev) g_scr.resize(dev + 1, {nullptr, 0});
+        auto& slot = g_scr[dev];
+        if (slot.second < need) {
+            ADI_HIP(hipStreamSynchronize(st));
+            if (slot.first) (void)hipFree(slot.first);
+            slot = {nullptr, 0};
+            if (hipMalloc(&slot.first, need) != hipSuccess) {
+                (void)hipGetLastError();
+                slot.first = nullptr;
+                return fail(ADI_ENOMEM, "hipMalloc of batched-solve scratch failed");
+            }
+            slot.second = need;
+        }
+        scr = slot.first;
+    }
+    const unsigned grid = (unsigned)((batch + 255) / 256);
+    if (dtype == ADI_F32) {
+        TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
+                         sys_stride, elem_stride, 0, (float*)scr};
+        hipLaunchKernelGGL((k_tridiag_thread<float>), dim3(grid), dim3(256), 0, st, t);
+    } else {
+        TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
+                          sys_stride, elem_stride, 0, (double*)scr};
+        hipLaunchKernelGGL((k_tridiag_thread<double>), dim3(grid), dim3(256), 0, st, t);
+    }
+    ADI_LAUNCHED("tridiag_thread");
+    return ADI_OK;
+}
+
+}  // extern "C"

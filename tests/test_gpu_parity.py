@@ -1,0 +1,320 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (relative L2 over all interior nodes, computed in FP64):
+  FP64 runs  <= 1e-12 after the full run (single line solves and steps <= 1e-13);
+  FP32 runs  <= 1e-5 after the full run.
+FP32 inputs are rounded once by the workload generators; the oracle consumes
+those same values promoted to FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests.conftest import rel_l2
+from paper_2006_10142_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_RUN = {"f64": 1e-12, "f32": 1e-5}
+TOL_ONE = {"f64": 1e-13, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def adw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2006_10142_amd as m
+    m._lib.load()
+    return m
+
+
+def tdt(dtype):
+    return torch.float32 if dtype == "f32" else torch.float64
+
+
+def npdt(dtype):
+    return np.float32 if dtype == "f32" else np.float64
+
+
+def dev(a, dtype=None):
+    a = np.ascontiguousarray(a)
+    t = torch.from_numpy(a)
+    if dtype is not None:
+        t = t.to(tdt(dtype))
+    return t.cuda()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+# -------------------------------------------------------- batched solves ----
+def dd_systems(rng, size):
+    a = rng.uniform(-1, 1, size)
+    c = rng.uniform(-1, 1, size)
+    b = (np.abs(a) + np.abs(c) + rng.uniform(0.05, 1.0, size)) * rng.choice([-1.0, 1.0], size)
+    d = rng.standard_normal(size)
+    return a, b, c, d
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,batch", [(1, 5), (2, 9), (3, 33), (37, 33), (64, 7), (128, 5),
+                                     (129, 5), (1000, 4), (4097, 3), (8192, 3)])
+def test_tridiag_contiguous(adw, oracle_lib, dtype, n, batch):
+    say(f"tridiag contiguous {dtype} n={n} batch={batch}")
+    rng = np.random.default_rng(n * 31 + batch)
+    a, b, c, d = (v.astype(npdt(dtype)) for v in dd_systems(rng, n * batch))
+    ref = oracle_lib.tridiag_batched(a, b, c, d, n, batch, n, 1)
+    A, B, C, D = (dev(v) for v in (a, b, c, d))
+    adw.tridiag_solve_batched(A, B, C, D, n, batch, n, 1)
+    torch.cuda.synchronize()
+    assert rel_l2(D.cpu().numpy(), ref) <= TOL_ONE[dtype]
+    assert np.array_equal(A.cpu().numpy(), a)        # coefficients untouched
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("layout", ["interleaved", "padded", "long"])
+def test_tridiag_strided(adw, oracle_lib, dtype, layout):
+    n, batch = {"interleaved": (300, 257), "padded": (77, 19), "long": (20000, 3)}[layout]
+    ss, es = {"interleaved": (1, batch), "padded": (3 * n + 5, 3), "long": (n, 1)}[layout]
+    say(f"tridiag {layout} {dtype} n={n} batch={batch}")
+    size = (batch - 1) * ss + (n - 1) * es + 1
+    rng = np.random.default_rng(5)
+    a, b, c, d = (v.astype(npdt(dtype)) for v in dd_systems(rng, size))
+    ref = oracle_lib.tridiag_batched(a, b, c, d, n, batch, ss, es)
+    A, B, C, D = (dev(v) for v in (a, b, c, d))
+    adw.tridiag_solve_batched(A, B, C, D, n, batch, ss, es)
+    torch.cuda.synchronize()
+    got = D.cpu().numpy()
+    assert rel_l2(got, ref) <= TOL_ONE[dtype]
+    mask = np.ones(size, bool)
+    for s in range(batch):
+        mask[s * ss + np.arange(n) * es] = False
+    assert np.array_equal(got[mask], d[mask])        # gaps untouched
+
+
+# ------------------------------------------------------------- one step ----
+SHAPES = [(1, 1), (1, 5), (5, 1), (2, 3), (7, 5), (64, 64), (100, 37), (129, 257),
+          (513, 70), (1000, 33), (2049, 40), (4096, 12), (8192, 9)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_single_step_increment(adw, oracle_lib, dtype, nx, ny):
+    """u_prev = 2 u_curr makes u^{n+1} equal the ADI increment d exactly."""
+    say(f"single step {dtype} {nx}x{ny}")
+    rng = np.random.default_rng(nx * 7 + ny)
+    h = 1.0 / (max(nx, ny) + 1)
+    dt = 0.8 * h
+    c = rng.uniform(1.0, 3.0, (ny, nx)).astype(npdt(dtype))
+    uc = rng.standard_normal((ny, nx)).astype(npdt(dtype))
+    up = (2 * uc.astype(np.float64)).astype(npdt(dtype))
+    src_idx = np.array([(ny // 2) * nx + nx // 3], np.int32)
+    amp = np.array([[1.0 / (h * h)]], npdt(dtype))
+    ref = oracle_lib.step_parts(c.astype(np.float64) ** 2, up, uc, h, dt,
+                                f=np.bincount(src_idx, weights=amp[0].astype(np.float64),
+                                              minlength=nx * ny).reshape(ny, nx))["d"]
+    wave = adw.Wave(nx, ny, h, dt, c=dev(c), dtype=tdt(dtype))
+    a, b = dev(up), dev(uc)
+    a, b = wave.step(a, b, 1, src_idx=dev(src_idx), src_amp=dev(amp))
+    torch.cuda.synchronize()
+    assert rel_l2(b.cpu().numpy(), ref) <= TOL_ONE[dtype]
+
+
+# ------------------------------------------------------------ full runs ----
+def gpu_run(adw, prob, nsteps=None, rec=False):
+    nsteps = prob.nsteps if nsteps is None else nsteps
+    t = tdt(prob.dtype)
+    wave = adw.Wave(prob.nx, prob.ny, prob.h, prob.dt, dtype=t,
+                    c=dev(prob.c) if prob.c is not None else prob.c_scalar,
+                    kappa=dev(prob.kappa) if prob.kappa is not None else None)
+    if prob.u_curr is not None:
+        a, b = dev(prob.u_prev), dev(prob.u_curr)
+    else:
+        a = dev(prob.u0)
+        b = wave.start(a, psi=None if prob.psi is None else dev(prob.psi), mode=prob.start_mode)
+    kw = {}
+    if prob.src_amp is not None:
+        kw.update(src_idx=dev(prob.src_idx), src_amp=dev(np.asarray(prob.src_amp)[:nsteps]))
+    traces = None
+    if rec and prob.rec_idx.size:
+        traces = torch.zeros((nsteps, prob.rec_idx.size), dtype=t, device="cuda")
+        kw.update(rec_idx=dev(prob.rec_idx), traces=traces)
+    a, b = wave.step(a, b, nsteps, **kw)
+    torch.cuda.synchronize()
+    out = (a.cpu().numpy(), b.cpu().numpy(), None if traces is None else traces.cpu().numpy())
+    wave.close()
+    return out
+
+
+def test_c1_standing_wave(adw, oracle_lib):
+    """C1: 128^2, FP64, ghost start, 200 steps: oracle and discrete closed form."""
+    p = wl.config_c1()
+    say("C1 f64 128^2 200 steps")
+    _, got, _ = gpu_run(adw, p)
+    _, ref, _ = oracle_lib.run_problem(p)
+    assert rel_l2(got, ref) <= TOL_RUN["f64"]
+    lam = 4 * math.sin(math.pi * p.h / 2) ** 2 / p.h ** 2
+    beta = p.dt ** 2 / 2
+    g = p.dt ** 2 * 2 * lam / (1 + beta * lam) ** 2
+    theta = math.acos(1 - g / 2)
+    assert rel_l2(got, math.cos((p.nsteps + 1) * theta) * wl.sine_mode(p.nx, p.ny)) <= TOL_RUN["f64"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c1_paper_start(adw, oracle_lib, dtype):
+    p = wl.config_c1(dtype=dtype, nsteps=50, start_mode="paper")
+    say(f"C1 paper start {dtype}")
+    _, got, _ = gpu_run(adw, p)
+    _, ref, _ = oracle_lib.run_problem(p)
+    assert rel_l2(got, ref) <= TOL_RUN[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c2_gaussian_pulse_cut(adw, oracle_lib, dtype):
+    """C2 shape (2048^2, c = 1, Gaussian pulse, dt = h/2), cut to 200 steps."""
+    p = wl.config_c2(dtype=dtype, nsteps=200)
+    say(f"C2 {dtype} 2048^2 200 steps")
+    _, got, _ = gpu_run(adw, p)
+    _, ref, _ = oracle_lib.run_problem(p)
+    assert rel_l2(got, ref) <= TOL_RUN[dtype]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_c2_gaussian_pulse_full(adw, oracle_lib, dtype):
+    """C2 in full: 2048^2, 1000 steps."""
+    p = wl.config_c2(dtype=dtype)
+    say(f"C2 {dtype} 2048^2 1000 steps")
+    _, got, _ = gpu_run(adw, p)
+    _, ref, _ = oracle_lib.run_problem(p)
+    assert rel_l2(got, ref) <= TOL_RUN[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("variant", ["ricker", "pulse"])
+def test_c3_shape_at_1024(adw, oracle_lib, dtype, variant):
+    """C3's recipe (speed in [1, 3], dt = 0.4 h / max c) at 1024^2 for 300 steps."""
+    mk = wl.config_c3 if variant == "ricker" else wl.config_c3p
+    p = mk(dtype=dtype, nsteps=300, n=1024)
+    say(f"C3-shape {variant} {dtype} 1024^2 300 steps")
+    _, got, _ = gpu_run(adw, p)
+    _, ref, _ = oracle_lib.run_problem(p)
+    assert np.linalg.norm(ref) > 0
+    assert rel_l2(got, ref) <= TOL_RUN[dtype]
+
+
+def test_c3_full_size_steps(adw, oracle_lib):
+    """C3 at its full size (8192^2 FP32, the benchmark's launch plan): 3 steps from a
+    Gaussian pulse, compared node by node with the oracle."""
+    p = wl.config_c3p(dtype="f32", nsteps=3)
+    say("C3p f32 8192^2 3 steps")
+    _, got, _ = gpu_run(adw, p)
+    _, ref, _ = oracle_lib.run_problem(p)
+    assert rel_l2(got, ref) <= TOL_RUN["f32"]
+
+
+# ------------------------------------------------ starts, sources, traces ----
+@pytest.mark.parametrize("mode", ["paper", "ghost"])
+def test_start_with_velocity_and_source(adw, oracle_lib, mode):
+    n = 77
+    h = wl.grid_h(n)
+    dt = 0.6 * h
+    rng = np.random.default_rng(2)
+    c = wl.smooth_field(n, n, 1.0, 2.0, seed=9)
+    u0 = wl.gaussian_pulse(n, n, sigma=0.1)
+    psi = rng.standard_normal((n, n))
+    si = np.array([10 * n + 20, 40 * n + 3], np.int32)
+    amp0 = np.array([[3.0, -2.0]])
+    say(f"start {mode}")
+    wave = adw.Wave(n, n, h, dt, c=dev(c), dtype=torch.float64)
+    u1 = wave.start(dev(u0), psi=dev(psi), src_idx=dev(si), src_amp0=dev(amp0), mode=mode)
+    torch.cuda.synchronize()
+    ref = oracle_lib.start(c * c, u0, h, dt, psi=psi, mode=mode, src_idx=si, src_amp0=amp0)
+    assert rel_l2(u1.cpu().numpy(), ref) <= TOL_ONE["f64"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c5_shape_receivers(adw, oracle_lib, dtype):
+    """C5's recipe (kappa in [1, 9], Ricker, 64 receivers) at 256^2 for 400 steps."""
+    p, _ = wl.config_c5(dtype=dtype, nsteps=400, n=256)
+    say(f"C5-shape {dtype} receivers")
+    _, got, tr = gpu_run(adw, p, rec=True)
+    _, ref, tref = oracle_lib.run_problem(p)
+    assert rel_l2(got, ref) <= TOL_RUN[dtype]
+    assert np.abs(tref).max() > 0
+    assert rel_l2(tr, tref) <= TOL_RUN[dtype]
+
+
+def test_step_rotation_and_determinism(adw):
+    """nsteps in one call equals one-step calls (bitwise); repeated runs are bitwise equal."""
+    p = wl.config_c3p(dtype="f32", nsteps=7, n=300)
+    say("rotation/determinism")
+    wave = adw.Wave(p.nx, p.ny, p.h, p.dt, c=dev(p.c), dtype=torch.float32)
+    u0 = dev(p.u0)
+    u1 = wave.start(u0)
+    a, b = wave.step(u0.clone(), u1.clone(), 7)
+    c_, d_ = u0.clone(), u1.clone()
+    for _ in range(7):
+        c_, d_ = wave.step(c_, d_, 1)
+    e, f = wave.step(u0.clone(), u1.clone(), 7)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c_) and torch.equal(b, d_)
+    assert torch.equal(b, f) and torch.equal(a, e)
+    # zero steps: nothing changes
+    g, h_ = u0.clone(), u1.clone()
+    g2, h2 = wave.step(g, h_, 0)
+    assert g2 is g and h2 is h_ and torch.equal(h2, u1)
+
+
+@pytest.mark.parametrize("tr,s,m", [(64, 8, 16), (256, 2, 32), (256, 4, 16), (1024, 2, 32),
+                                    (64, 16, 32), (256, 16, 16)])
+def test_launch_plans(adw, oracle_lib, tr, s, m):
+    """Every admissible launch plan reaches the same answer (FP64, 10 steps, 300 x 211)."""
+    nx, ny = 300, 211
+    h = 1.0 / 301
+    dt = 0.5 * h
+    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=21)
+    u0 = wl.gaussian_pulse(nx, ny, sigma=0.1)
+    say(f"plan tr={tr} s={s} m={m}")
+    if s == 16:
+        pytest.skip("16 nodes per thread is f32-only")
+    if tr * s < nx:
+        pytest.skip("plan does not cover the row")
+    wave = adw.Wave(nx, ny, h, dt, c=dev(c), dtype=torch.float64)
+    wave.set_tuning(tr, s, 3, m)
+    inf = wave.info()
+    assert (inf["x_threads_per_line"], inf["x_elems_per_thread"], inf["y_chunk_rows"]) == (tr, s, m)
+    a = dev(u0)
+    b = wave.start(a)
+    a, b = wave.step(a, b, 10)
+    torch.cuda.synchronize()
+    u1 = oracle_lib.start(c * c, u0, h, dt)
+    _, ref, _ = oracle_lib.run(c * c, u0, u1, h, dt, 10)
+    assert rel_l2(b.cpu().numpy(), ref) <= TOL_RUN["f64"]
+
+
+def test_invalid_calls_raise(adw):
+    wave = adw.Wave(16, 16, 1 / 17, 0.5 / 17, dtype=torch.float32)
+    u = torch.zeros((16, 16), device="cuda")
+    with pytest.raises(adw.AdiError):
+        wave.step(u, u, 1)                    # same buffer twice
+    with pytest.raises(ValueError):
+        wave.step(u, torch.zeros((16, 15), device="cuda"), 1)
+    with pytest.raises(TypeError):
+        wave.step(u, torch.zeros((16, 16), device="cuda", dtype=torch.float64), 1)
+    with pytest.raises(adw.AdiError):
+        wave.set_tuning(64, 2, 1, 16)         # 64*2 < 16? no: 128 >= 16 is fine; chunk ok
+        wave.set_tuning(64, 2, 1, 24)         # chunk rows must be 16 or 32
+    with pytest.raises(adw.AdiError):
+        wave.start(u, mode="paper", out=u)    # u1 aliases u0
+
+
+def test_stream_copy(adw):
+    x = torch.randn(1 << 20, device="cuda")
+    y = torch.empty_like(x)
+    adw.stream_copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
