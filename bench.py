@@ -31,8 +31,10 @@ HBM_PEAK_GBPS = 8000.0
 #   x_sweep_rhs     reads u^n and r, writes w                      3E
 #   y_solve_update  reads w, r, u^n, u^{n-1}, writes u^{n+1}       5E
 #   y_reduce        reads w and r                                  2E
+#   x_sweep_rhs_y_reduce  the x-sweep with the y-chunk elimination fused: 3E
 # The whole step's two-pass minimum is 8E (32 B/node in FP32).
-ALG_BYTES_PER_NODE = {"x_sweep_rhs": 3, "y_solve_update": 5, "y_reduce": 2}
+ALG_BYTES_PER_NODE = {"x_sweep_rhs": 3, "x_sweep_rhs_y_reduce": 3, "y_solve_update": 5,
+                      "y_reduce": 2}
 STEP_BYTES_PER_NODE = 8
 
 WORKLOADS = {
@@ -44,7 +46,7 @@ WORKLOADS = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp"):
+    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp", "xsweep.hpp"):
         with open(os.path.join(ROOT, "paper_2006_10142_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

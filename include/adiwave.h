@@ -96,7 +96,7 @@ typedef struct {
  * The per-node coefficient r = dt^2 speed^2 / (2 h^2) is computed on the
  * device in the handle's type and kept in the workspace.
  * hip_stream: hipStream_t the handle queues on (NULL = default stream).
- * Limits: 1 <= nx <= 16384 (8192 for ADI_F64), 1 <= ny, nx*ny < 2^31.
+ * Limits: 1 <= nx <= 8192, 1 <= ny, nx*ny < 2^31.
  * Synchronises the stream before returning (the workspace is ready). */
 adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
                            const void* speed, double speed_scalar, adi_dtype dtype,
@@ -150,9 +150,9 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
 typedef struct {
     int nx, ny;
     int dtype;
-    int x_threads_per_line;   /* x-sweep: threads cooperating on one x-line */
-    int x_elems_per_thread;   /* x-sweep: contiguous nodes per thread */
+    int x_threads_per_line;   /* x-sweep: threads cooperating on one x-line (8 nodes each) */
     int x_rows_per_strip;     /* x-sweep: consecutive rows per thread group */
+    int y_fused;              /* 1: y-chunk elimination fused into the x-sweep */
     int y_chunk_rows;         /* y-lines are split in chunks of this many rows */
     int y_chunks;             /* number of chunks per y-line */
     int kernels_per_step;     /* launches queued per ADI step */
@@ -165,9 +165,9 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
  * Any field <= 0 keeps the current value.  Reallocates chunk workspace if the
  * chunk size changes (synchronises the stream). */
 typedef struct {
-    int x_threads_per_line;   /* 64, 256 or 1024 */
-    int x_elems_per_thread;   /* 2, 4, 8 or 16 (f64: up to 8) */
-    int x_rows_per_strip;     /* >= 1 */
+    int x_threads_per_line;   /* 64, 256 or 1024, with 8 * threads >= nx */
+    int x_rows_per_strip;     /* >= 1 (unfused plans; a fused strip is one y-chunk) */
+    int y_fused;              /* 1 = fuse the y-chunk elimination into the x-sweep, 2 = separate */
     int y_chunk_rows;         /* 16 or 32 */
 } adi_tuning;
 adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t);

@@ -185,10 +185,12 @@ class Wave:
         _lib.check(_lib.load().adi_wave_get_info(self._h, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in _lib.AdiWaveInfo._fields_}
 
-    def set_tuning(self, x_threads_per_line=0, x_elems_per_thread=0, x_rows_per_strip=0,
+    def set_tuning(self, x_threads_per_line=0, x_rows_per_strip=0, y_fused=None,
                    y_chunk_rows=0):
+        """Override the launch plan (0 / None keeps the current value)."""
         self._sync_stream()
-        t = _lib.AdiTuning(x_threads_per_line, x_elems_per_thread, x_rows_per_strip, y_chunk_rows)
+        f = 0 if y_fused is None else (1 if y_fused else 2)
+        t = _lib.AdiTuning(x_threads_per_line, x_rows_per_strip, f, y_chunk_rows)
         _lib.check(_lib.load().adi_wave_set_tuning(self._h, ctypes.byref(t)))
 
     def close(self):

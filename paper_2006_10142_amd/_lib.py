@@ -31,15 +31,15 @@ class AdiReceivers(ctypes.Structure):
 
 class AdiWaveInfo(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dtype", ctypes.c_int),
-                ("x_threads_per_line", ctypes.c_int), ("x_elems_per_thread", ctypes.c_int),
-                ("x_rows_per_strip", ctypes.c_int), ("y_chunk_rows", ctypes.c_int),
+                ("x_threads_per_line", ctypes.c_int), ("x_rows_per_strip", ctypes.c_int),
+                ("y_fused", ctypes.c_int), ("y_chunk_rows", ctypes.c_int),
                 ("y_chunks", ctypes.c_int), ("kernels_per_step", ctypes.c_int),
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
 class AdiTuning(ctypes.Structure):
-    _fields_ = [("x_threads_per_line", ctypes.c_int), ("x_elems_per_thread", ctypes.c_int),
-                ("x_rows_per_strip", ctypes.c_int), ("y_chunk_rows", ctypes.c_int)]
+    _fields_ = [("x_threads_per_line", ctypes.c_int), ("x_rows_per_strip", ctypes.c_int),
+                ("y_fused", ctypes.c_int), ("y_chunk_rows", ctypes.c_int)]
 
 
 _SIGNATURES = {

@@ -47,28 +47,46 @@ size_t esize(adi_dtype t) { return t == ADI_F64 ? 8 : 4; }
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // ---------------------------------------------------------- launch plans ----
-struct XPlan { int tr, s, rs; };
+struct XPlan { int tr, rs, fuse; };
 
-// Smallest (threads per line, nodes per thread) whose product covers nx.
-bool choose_x(int nx, adi_dtype dt, XPlan& p)
+// x-sweep: smallest line group whose 8 * tr nodes cover nx
+bool choose_x(int nx, adi_dtype, XPlan& p)
+{
+    static const int cand[] = {64, 256, 1024};
+    for (int tr : cand)
+        if (8LL * tr >= nx) { p.tr = tr; return true; }
+    return false;
+}
+
+// the fused y-chunk state (4 values per column) must fit in LDS next to the rest
+bool fuse_fits(int tr, adi_dtype dt)
+{
+    const size_t es = dt == ADI_F64 ? 8 : 4;
+    const size_t lds = (4 * 8 * (size_t)std::max(tr, 256) + 4 * (size_t)std::max(tr, 256)) * es;
+    return lds <= 150 * 1024;
+}
+
+// batched solve: smallest (threads per line, nodes per thread) covering n
+struct TPlan { int tr, s; };
+bool choose_tri(int n, adi_dtype dt, TPlan& p)
 {
     static const int cand[][2] = {{64, 2}, {64, 4}, {64, 8}, {64, 16}, {256, 8},
                                   {256, 16}, {1024, 8}, {1024, 16}};
     for (auto& c : cand) {
         if (dt == ADI_F64 && c[1] > 8) continue;
-        if ((long long)c[0] * c[1] >= nx) { p.tr = c[0]; p.s = c[1]; return true; }
+        if ((long long)c[0] * c[1] >= n) { p.tr = c[0]; p.s = c[1]; return true; }
     }
     return false;
 }
 
 int x_groups_per_wg(int tr) { return tr >= 256 ? 1 : 256 / tr; }
 
-// rows per strip: enough workgroups to cover 256 CUs twice, at most 32 rows
+// rows per strip: enough workgroups to cover 256 CUs twice, 2..32 rows
 int choose_rows(int ny, int tr)
 {
     const int g = x_groups_per_wg(tr);
     int rs = ny / (512 * g);
-    return std::max(1, std::min(32, rs));
+    return std::max(2, std::min(32, rs));
 }
 
 struct YScanPlan { int sk, p; };
@@ -83,34 +101,31 @@ bool choose_yscan(int K, YScanPlan& q)
 }
 
 // ---------------------------------------------------- template dispatch ----
-template <typename T, int S, int TR>
+template <typename T, int TR, bool FUSE>
 void launch_x1(int grid, const XArgs<T>& a, hipStream_t st)
 {
     constexpr int NT = TR >= 256 ? TR : 256;
-    hipLaunchKernelGGL((k_xsweep<T, S, TR>), dim3(grid), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((k_xsweep<T, TR, FUSE>), dim3(grid), dim3(NT), 0, st, a);
 }
 
 template <typename T, int TR>
-bool launch_x_s(int s, int grid, const XArgs<T>& a, hipStream_t st)
+bool launch_x_f(bool fuse, int grid, const XArgs<T>& a, hipStream_t st)
 {
-    switch (s) {
-        case 2: launch_x1<T, 2, TR>(grid, a, st); return true;
-        case 4: launch_x1<T, 4, TR>(grid, a, st); return true;
-        case 8: launch_x1<T, 8, TR>(grid, a, st); return true;
-        case 16:
-            if constexpr (sizeof(T) == 4) { launch_x1<T, 16, TR>(grid, a, st); return true; }
-            return false;
+    if (fuse) {
+        if constexpr (sizeof(T) == 8 && TR > 256) return false;
+        else { launch_x1<T, TR, true>(grid, a, st); return true; }
     }
-    return false;
+    launch_x1<T, TR, false>(grid, a, st);
+    return true;
 }
 
 template <typename T>
 bool launch_x(const XPlan& p, int grid, const XArgs<T>& a, hipStream_t st)
 {
     switch (p.tr) {
-        case 64: return launch_x_s<T, 64>(p.s, grid, a, st);
-        case 256: return launch_x_s<T, 256>(p.s, grid, a, st);
-        case 1024: return launch_x_s<T, 1024>(p.s, grid, a, st);
+        case 64: return launch_x_f<T, 64>(p.fuse != 0, grid, a, st);
+        case 256: return launch_x_f<T, 256>(p.fuse != 0, grid, a, st);
+        case 1024: return launch_x_f<T, 1024>(p.fuse != 0, grid, a, st);
     }
     return false;
 }
@@ -174,7 +189,7 @@ bool launch_tri_s(int s, long long batch, const TriArgs<T>& a, hipStream_t st)
 }
 
 template <typename T>
-bool launch_tri(const XPlan& p, long long batch, const TriArgs<T>& a, hipStream_t st)
+bool launch_tri(const TPlan& p, long long batch, const TriArgs<T>& a, hipStream_t st)
 {
     switch (p.tr) {
         case 64: return launch_tri_s<T, 64>(p.s, batch, a, st);
@@ -197,6 +212,8 @@ struct adi_wave_s {
     void* w = nullptr;     // nx*ny
     void* sum = nullptr;   // 8 * K * nx
     void* X = nullptr;     // K * nx
+    void* qin = nullptr;   // ny * nseg entry pivots of the x-line segments
+    int nseg = 0;
     XPlan xp{};
     int M = 32, K = 0;
     YScanPlan yq{};
@@ -211,7 +228,8 @@ void free_ws(adi_wave_s* w)
     if (w->w) (void)hipFree(w->w);
     if (w->sum) (void)hipFree(w->sum);
     if (w->X) (void)hipFree(w->X);
-    w->r = w->w = w->sum = w->X = nullptr;
+    if (w->qin) (void)hipFree(w->qin);
+    w->r = w->w = w->sum = w->X = w->qin = nullptr;
 }
 
 adi_status alloc_chunks(adi_wave_s* w)
@@ -229,7 +247,7 @@ adi_status alloc_chunks(adi_wave_s* w)
         (void)hipGetLastError();
         return fail(ADI_ENOMEM, "hipMalloc of y-chunk workspace failed");
     }
-    w->bytes = 2 * (size_t)w->nx * w->ny * es + (nsum + nX) * es;
+    w->bytes = (2 * (size_t)w->nx * w->ny + (size_t)w->ny * w->nseg + nsum + nX) * es;
     return ADI_OK;
 }
 
@@ -266,12 +284,16 @@ XArgs<T> make_x(const adi_wave_s* w, const void* u, const adi_source* f, int k, 
     XArgs<T> a{};
     a.u = static_cast<const T*>(u);
     a.r = static_cast<const T*>(w->r);
+    a.qin = static_cast<const T*>(w->qin);
     a.w = static_cast<T*>(w->w);
     a.nx = w->nx;
     a.ny = w->ny;
-    a.rows_per_strip = w->xp.rs;
-    a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && ((size_t)w->xp.s * sizeof(T)) % 16 == 0 &&
-            aligned16(u) && aligned16(w->r) && aligned16(w->w);
+    a.nseg = w->nseg;
+    a.rows_per_strip = w->xp.fuse ? w->M : w->xp.rs;
+    a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && aligned16(u) && aligned16(w->r) &&
+            aligned16(w->w);
+    a.sum = static_cast<T*>(w->sum);
+    a.K = w->K;
     a.rho_scale = rho_scale;
     a.tau2 = (T)(w->dt * w->dt);
     if (f && f->count > 0) {
@@ -305,7 +327,8 @@ YArgs<T> make_y(const adi_wave_s* w, const void* u, const void* v, void* out, T 
 int x_grid(const adi_wave_s* w)
 {
     const int g = x_groups_per_wg(w->xp.tr);
-    const int strips = (w->ny + w->xp.rs - 1) / w->xp.rs;
+    const int rs = w->xp.fuse ? w->M : w->xp.rs;
+    const int strips = (w->ny + rs - 1) / rs;
     return (strips + g - 1) / g;
 }
 
@@ -325,8 +348,10 @@ adi_status queue_solve(adi_wave_s* w, const void* u, const void* v, void* out, T
     if (ev) ADI_HIP(hipEventRecord(ev[1], st));
     YArgs<T> ya = make_y<T>(w, u, v, out, alpha, beta);
     const dim3 yg((w->nx + 255) / 256, w->K);
-    hipLaunchKernelGGL((k_yreduce<T>), yg, dim3(256), 0, st, ya);
-    ADI_LAUNCHED("y_reduce");
+    if (!w->xp.fuse) {
+        hipLaunchKernelGGL((k_yreduce<T>), yg, dim3(256), 0, st, ya);
+        ADI_LAUNCHED("y_reduce");
+    }
     if (ev) ADI_HIP(hipEventRecord(ev[2], st));
     if (!launch_yscan<T>(w->yq, w->nx, ya, st))
         return fail(ADI_EUNSUPPORTED, "no y-interface kernel for this configuration");
@@ -336,6 +361,20 @@ adi_status queue_solve(adi_wave_s* w, const void* u, const void* v, void* out, T
         return fail(ADI_EUNSUPPORTED, "no y-solve kernel for this chunk size");
     ADI_LAUNCHED("y_solve_update");
     if (ev) ADI_HIP(hipEventRecord(ev[4], st));
+    return ADI_OK;
+}
+
+// The y-chunk summary planes that depend on r only (Lf, Rf, Ll, Rl, rI): one
+// chunk reduction of a zero right-hand side.  The fused x-sweep then rewrites
+// only the data-dependent planes (Pf, Pl, wI) every step.
+template <typename T>
+adi_status static_planes(adi_wave_s* w)
+{
+    ADI_HIP(hipMemsetAsync(w->w, 0, (size_t)w->nx * w->ny * sizeof(T), w->stream));
+    YArgs<T> ya = make_y<T>(w, nullptr, nullptr, nullptr, T(0), T(0));
+    const dim3 yg((w->nx + 255) / 256, w->K);
+    hipLaunchKernelGGL((k_yreduce<T>), yg, dim3(256), 0, w->stream, ya);
+    ADI_LAUNCHED("y_reduce (static planes)");
     return ADI_OK;
 }
 
@@ -349,7 +388,10 @@ adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared
                        static_cast<const T*>(field), (T)scalar, squared, (T)s,
                        static_cast<T*>(w->r), n);
     ADI_LAUNCHED("coef");
-    return ADI_OK;
+    hipLaunchKernelGGL((k_xpivots<T>), dim3((w->ny + 255) / 256), dim3(256), 0, w->stream,
+                       static_cast<const T*>(w->r), static_cast<T*>(w->qin), w->nx, w->ny, w->nseg);
+    ADI_LAUNCHED("x_pivots");
+    return static_planes<T>(w);
 }
 
 template <typename T>
@@ -408,22 +450,24 @@ adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
         return fail(ADI_EINVAL, "speed_scalar must be finite and > 0 when speed is NULL");
     XPlan xp{};
     if (!choose_x(nx, dtype, xp))
-        return fail(ADI_EUNSUPPORTED, dtype == ADI_F64 ? "nx > 8192 is not supported for f64"
-                                                       : "nx > 16384 is not supported");
+        return fail(ADI_EUNSUPPORTED, "nx > 8192 is not supported");
     xp.rs = choose_rows(ny, xp.tr);
+    xp.fuse = fuse_fits(xp.tr, dtype) ? 1 : 0;
 
     adi_wave_s* w = new adi_wave_s();
     w->nx = nx; w->ny = ny; w->h = h; w->dt = dt; w->dtype = dtype;
     w->stream = static_cast<hipStream_t>(hip_stream);
     w->xp = xp;
-    w->M = 32;
+    w->M = dtype == ADI_F64 ? 16 : 32;   // keeps the chunk solve of FP64 in registers
     if (hipGetDevice(&w->device) != hipSuccess) {
         delete w;
         return fail(ADI_EHIP, "hipGetDevice failed");
     }
     const size_t es = esize(dtype);
     const size_t npts = (size_t)nx * ny;
-    if (hipMalloc(&w->r, npts * es) != hipSuccess || hipMalloc(&w->w, npts * es) != hipSuccess) {
+    w->nseg = (nx + kSeg - 1) / kSeg;
+    if (hipMalloc(&w->r, npts * es) != hipSuccess || hipMalloc(&w->w, npts * es) != hipSuccess ||
+        hipMalloc(&w->qin, (size_t)ny * w->nseg * es) != hipSuccess) {
         (void)hipGetLastError();
         free_ws(w);
         delete w;
@@ -502,11 +546,11 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->ny = w->ny;
     info->dtype = (int)w->dtype;
     info->x_threads_per_line = w->xp.tr;
-    info->x_elems_per_thread = w->xp.s;
-    info->x_rows_per_strip = w->xp.rs;
+    info->x_rows_per_strip = w->xp.fuse ? w->M : w->xp.rs;
+    info->y_fused = w->xp.fuse;
     info->y_chunk_rows = w->M;
     info->y_chunks = w->K;
-    info->kernels_per_step = 4;
+    info->kernels_per_step = w->xp.fuse ? 3 : 4;
     info->workspace_bytes = w->bytes;
     return ADI_OK;
 }
@@ -517,14 +561,14 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
     if (!t) return fail(ADI_EINVAL, "tuning is null");
     XPlan xp = w->xp;
     if (t->x_threads_per_line > 0) xp.tr = t->x_threads_per_line;
-    if (t->x_elems_per_thread > 0) xp.s = t->x_elems_per_thread;
     if (t->x_rows_per_strip > 0) xp.rs = t->x_rows_per_strip;
+    if (t->y_fused == 1) xp.fuse = 1;
+    if (t->y_fused == 2) xp.fuse = 0;
     if (xp.tr != 64 && xp.tr != 256 && xp.tr != 1024)
         return fail(ADI_EINVAL, "x_threads_per_line must be 64, 256 or 1024");
-    if (xp.s != 2 && xp.s != 4 && xp.s != 8 && !(xp.s == 16 && w->dtype == ADI_F32))
-        return fail(ADI_EINVAL, "x_elems_per_thread must be 2, 4, 8 (or 16 for f32)");
-    if ((long long)xp.tr * xp.s < w->nx)
-        return fail(ADI_EINVAL, "x_threads_per_line * x_elems_per_thread must cover nx");
+    if (8LL * xp.tr < w->nx) return fail(ADI_EINVAL, "8 * x_threads_per_line must cover nx");
+    if (xp.fuse && !fuse_fits(xp.tr, w->dtype))
+        return fail(ADI_EUNSUPPORTED, "fused y-reduction does not fit in LDS for this plan");
     const int M = t->y_chunk_rows > 0 ? t->y_chunk_rows : w->M;
     if (M != 16 && M != 32) return fail(ADI_EINVAL, "y_chunk_rows must be 16 or 32");
     w->xp = xp;
@@ -532,7 +576,8 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
         if (hipStreamSynchronize(w->stream) != hipSuccess)
             return fail(ADI_EHIP, "stream synchronise failed");
         w->M = M;
-        return alloc_chunks(w);
+        if (adi_status s = alloc_chunks(w)) return s;
+        return w->dtype == ADI_F32 ? static_planes<float>(w) : static_planes<double>(w);
     }
     return ADI_OK;
 }
@@ -572,11 +617,16 @@ adi_status adi_wave_profile(adi_wave_t w, void** u_prev, void** u_curr, const ad
                 acc[q] += ms;
             }
         if (st == ADI_OK) {
+            // a fused plan has no separate y_reduce launch: its x-sweep does that work
+            static const char* kFusedX = "x_sweep_rhs_y_reduce";
+            int n = 0;
             for (int q = 0; q < 4; ++q) {
-                ms_per_kernel[q] = acc[q] / nsteps;
-                if (names) names[q] = kNames[q];
+                if (q == 1 && w->xp.fuse) continue;
+                ms_per_kernel[n] = acc[q] / nsteps;
+                if (names) names[n] = (q == 0 && w->xp.fuse) ? kFusedX : kNames[q];
+                ++n;
             }
-            *nkinds = 4;
+            *nkinds = n;
         }
     }
     for (auto& e : ev)
@@ -614,8 +664,8 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
     if (elem_stride < 1) return fail(ADI_EINVAL, "elem_stride must be >= 1");
     if (batch > 1 && sys_stride < 1) return fail(ADI_EINVAL, "sys_stride must be >= 1 when batch > 1");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    XPlan p{};
-    const bool wg_path = elem_stride == 1 && choose_x(n, dtype, p);
+    TPlan p{};
+    const bool wg_path = elem_stride == 1 && choose_tri(n, dtype, p);
     const size_t es = esize(dtype);
     if (wg_path) {
         const bool vec = aligned16(a) && aligned16(b) && aligned16(c) && aligned16(d) &&

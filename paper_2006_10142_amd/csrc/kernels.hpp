@@ -3,7 +3,7 @@
 // One step (the delta form of the Sec. 2 scheme, eq. (CN1) factored as in
 // eqs. (fr1)-(fr2), x-lines first):
 //   k_xsweep   rho = 2 r (5-point sum - 4 u) + dt^2 f, fused into the load of
-//              u^n, then every x-line solved on chip -> w            (row strips)
+//              u^n, then every x-line solved on chip -> w  (row strips; xsweep.hpp)
 //   k_yreduce  every y-line cut into chunks of M rows; per chunk and column the
 //              interior is eliminated top-down in one pass over w      (lane/column)
 //   k_yscan    the chunk-interface system of every column (one unknown per
@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "line_solver.hpp"
+#include "xsweep.hpp"
 
 namespace adw {
 
@@ -84,112 +85,6 @@ __global__ void __launch_bounds__(256) k_coef(const T* __restrict__ src, T scala
     }
 }
 
-// ---------------------------------------------------------------- x-sweep ----
-template <typename T>
-struct XArgs {
-    const T* u;          // u^n, (ny, nx)
-    const T* r;          // r, (ny, nx)
-    T* w;                // out: x-sweep result, (ny, nx)
-    int nx, ny;
-    int rows_per_strip;  // consecutive rows handled by one thread group
-    int vec;             // 16-byte vector access legal for full segments
-    T rho_scale;         // 1 for a step, 1/2 for the ghost start
-    T tau2;              // dt^2
-    int nsrc;            // point sources of this step
-    const int* src_idx;
-    const T* src_amp;    // nsrc values of f for this step
-};
-
-// Workgroup: NT = max(TR, 256) threads = G groups of TR threads; a group owns
-// rows_per_strip consecutive rows and solves them one after the other, thread
-// t holding nodes [t*S, t*S + S) of the row.  The rolling registers up/uc/un
-// hold rows j-1, j, j+1 of u^n, so each row of u^n is read once per strip.
-template <typename T, int S, int TR>
-__global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
-{
-    constexpr int NT = TR >= 256 ? TR : 256;
-    constexpr int G = NT / TR;
-    constexpr int PER = partition_lds_slots<TR>() + 2 * TR;
-    __shared__ T lds_all[G * PER];
-    const int g = threadIdx.x / TR;
-    const int t = threadIdx.x - g * TR;
-    T* lds = lds_all + g * PER;
-    T* halo = lds + partition_lds_slots<TR>();
-
-    const int nx = A.nx, ny = A.ny;
-    const int lo = t * S;
-    const int L = max(0, min(S, nx - lo));
-    const int nact = (nx + S - 1) / S;
-    const bool vec = A.vec != 0;
-    const int j0 = (blockIdx.x * G + g) * A.rows_per_strip;
-
-    T up[S], uc[S], un[S], rr[S], d[S];
-    if (j0 - 1 >= 0 && j0 - 1 < ny) load_seg<T, S>(A.u + (size_t)(j0 - 1) * nx + lo, L, vec, up);
-    else {
-#pragma unroll
-        for (int k = 0; k < S; ++k) up[k] = T(0);
-    }
-    if (j0 < ny) load_seg<T, S>(A.u + (size_t)j0 * nx + lo, L, vec, uc);
-    else {
-#pragma unroll
-        for (int k = 0; k < S; ++k) uc[k] = T(0);
-    }
-
-    for (int it = 0; it < A.rows_per_strip; ++it) {
-        const int j = j0 + it;
-        const bool live = j < ny;
-        if (live && j + 1 < ny) load_seg<T, S>(A.u + (size_t)(j + 1) * nx + lo, L, vec, un);
-        else {
-#pragma unroll
-            for (int k = 0; k < S; ++k) un[k] = T(0);
-        }
-        if (live) load_seg<T, S>(A.r + (size_t)j * nx + lo, L, vec, rr);
-        else {
-#pragma unroll
-            for (int k = 0; k < S; ++k) rr[k] = T(0);
-        }
-
-        // west/east neighbours across segment ends
-        if (L >= 1) {
-            halo[t] = uc[0];
-            T last = uc[0];
-#pragma unroll
-            for (int k = 1; k < S; ++k)
-                if (k == L - 1) last = uc[k];
-            halo[TR + t] = last;
-        }
-        __syncthreads();
-        const T west0 = (t > 0 && L >= 1) ? halo[TR + t - 1] : T(0);
-        const T eastS = (t + 1 < nact) ? halo[t + 1] : T(0);
-
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const T uw = (k == 0) ? west0 : uc[k - 1];
-            const T ue = (k == S - 1) ? eastS : uc[k + 1];
-            d[k] = A.rho_scale * (T(2) * rr[k] * (((uw + ue) + (up[k] + un[k])) - T(4) * uc[k]));
-        }
-        if (live) {
-            for (int s = 0; s < A.nsrc; ++s) {
-                const int id = A.src_idx[s];
-                const int sj = id / nx;
-                if (sj == j) {
-                    const int si = id - sj * nx - lo;
-                    const T add = A.rho_scale * A.tau2 * A.src_amp[s];
-#pragma unroll
-                    for (int k = 0; k < S; ++k)
-                        if (k == si && k < L) d[k] += add;
-                }
-            }
-        }
-
-        partition_solve<T, S, TR>(d, CoefR<T, S>{rr}, L, t, nact, lds, 1);
-
-        if (live) store_seg<T, S>(A.w + (size_t)j * nx + lo, L, vec, d);
-#pragma unroll
-        for (int k = 0; k < S; ++k) { up[k] = uc[k]; uc[k] = un[k]; }
-    }
-}
-
 // ---------------------------------------------------------------- y-lines ----
 // Chunk c of a y-line covers rows [c*M, c*M + Lc), Lc = min(M, ny - c*M).  Its
 // interface unknown is the last row; its interior the Lc - 1 rows above.
@@ -216,6 +111,35 @@ struct YArgs {
 };
 
 // One thread per (column, chunk): interior elimination streamed top-down.
+// Interior rows k = 0..L-2 are eliminated with pivots started afresh at the
+// chunk (q = 0); P = values with X_{c-1} = X_c = 0, L = response to X_{c-1},
+// R = response to X_c.  First values come from the back-substitution written
+// as a running sum (first = sum_k prod_{i<k} q_i * forward_k).
+template <typename T, bool FULL>
+__device__ __forceinline__ void yreduce_chunk(const T* __restrict__ wp, const T* __restrict__ rp,
+                                              size_t nx, int L, T (&o)[8])
+{
+    T Pf = T(0), Lf = T(0), Rf = T(1), Pl = T(0), Ll = T(1), Rl = T(0);
+    if (L >= 2) {
+        T q = T(0), dpv = T(0), dlv = T(1), pi = T(1), yP = T(0), yL = T(0);
+        for (int k = 0; k < (FULL ? 31 : L - 1); ++k) {
+            const T rk = rp[(size_t)k * nx];
+            const T wk = wp[(size_t)k * nx];
+            const T m = pivot_step<T>(rk, q);
+            dpv = fma_rn(rk, dpv, wk) * m;
+            dlv = q * dlv;
+            yP = fma_rn(pi, dpv, yP);
+            yL = fma_rn(pi, dlv, yL);
+            pi = pi * q;
+        }
+        Pf = yP; Lf = yL; Rf = pi;
+        Pl = dpv; Ll = dlv; Rl = q;
+    }
+    o[0] = Pf; o[1] = Lf; o[2] = Rf; o[3] = Pl; o[4] = Ll; o[5] = Rl;
+    o[6] = rp[(size_t)(L - 1) * nx];
+    o[7] = wp[(size_t)(L - 1) * nx];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_yreduce(YArgs<T> A)
 {
@@ -225,34 +149,15 @@ __global__ void __launch_bounds__(256) k_yreduce(YArgs<T> A)
     const size_t nx = (size_t)A.nx;
     const int lo = c * A.M;
     const int L = min(A.M, A.ny - lo);
-    const T* wp = A.w + (size_t)lo * nx + i;
-    const T* rp = A.r + (size_t)lo * nx + i;
-    T Pf = T(0), Lf = T(0), Rf = T(1), Pl = T(0), Ll = T(1), Rl = T(0);
-    if (L >= 2) {
-        T cpv = T(0), dpv = T(0), dlv = T(0), pi = T(1), yP = T(0), yL = T(0);
-        for (int k = 0; k < L - 1; ++k) {
-            const T rk = rp[(size_t)k * nx];
-            const T wk = wp[(size_t)k * nx];
-            // a = c = -r, b = 1 + 2r: pivot b - a cp = 1 + 2r + r cp
-            const T m = T(1) / (T(1) + T(2) * rk + rk * cpv);
-            const T cpn = -rk * m;
-            const T dpn = (wk + rk * dpv) * m;
-            const T dln = (k == 0) ? rk * m : (rk * dlv) * m;
-            yP += pi * dpn;
-            yL += pi * dln;
-            pi *= -cpn;
-            cpv = cpn; dpv = dpn; dlv = dln;
-        }
-        Pf = yP; Lf = yL; Rf = pi;
-        Pl = dpv; Ll = dlv; Rl = -cpv;
-    }
-    const T rI = rp[(size_t)(L - 1) * nx];
-    const T wI = wp[(size_t)(L - 1) * nx];
+    const T* __restrict__ wp = A.w + (size_t)lo * nx + i;
+    const T* __restrict__ rp = A.r + (size_t)lo * nx + i;
+    T o[8];
+    if (L == 32 && A.M == 32) yreduce_chunk<T, true>(wp, rp, nx, L, o);
+    else yreduce_chunk<T, false>(wp, rp, nx, L, o);
     const size_t plane = (size_t)A.K * nx;
-    T* o = A.sum + (size_t)c * nx + i;
-    o[0 * plane] = Pf; o[1 * plane] = Lf; o[2 * plane] = Rf;
-    o[3 * plane] = Pl; o[4 * plane] = Ll; o[5 * plane] = Rl;
-    o[6 * plane] = rI; o[7 * plane] = wI;
+    T* __restrict__ out = A.sum + (size_t)c * nx + i;
+#pragma unroll
+    for (int v = 0; v < kSummaryPlanes; ++v) out[v * plane] = o[v];
 }
 
 // Chunk-interface system of every column, solved with the partition solver:
@@ -303,7 +208,47 @@ __global__ void __launch_bounds__(256) k_yscan(YArgs<T> A)
 }
 
 // One thread per (column, chunk): the chunk's interior re-solved with X_{c-1}
-// and X_c known, then the update of every row of the chunk.
+// and X_c known, then the update out = alpha u + beta v + d of every row.
+template <typename T, int M, bool FULL>
+__device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, size_t nx, int L, T Xp, T Xc)
+{
+    const T* __restrict__ w = A.w;
+    const T* __restrict__ r = A.r;
+    const T* __restrict__ u = A.u;
+    const T* __restrict__ v = A.v;
+    T* __restrict__ out = A.out;
+    T qa[M], da[M];
+    T q = T(0), dpv = T(0);
+#pragma unroll
+    for (int k = 0; k < M - 1; ++k) {
+        qa[k] = T(0); da[k] = T(0);
+        if (FULL || k < L - 1) {
+            const T rk = r[base + (size_t)k * nx];
+            T rhs = w[base + (size_t)k * nx];
+            if (k == 0) rhs = fma_rn(rk, Xp, rhs);
+            const T m = pivot_step<T>(rk, q);
+            dpv = fma_rn(rk, dpv, rhs) * m;
+            qa[k] = q; da[k] = dpv;
+        }
+    }
+    const bool hasv = v != nullptr;
+    {
+        const size_t p = base + (size_t)(L - 1) * nx;
+        const T vv = hasv ? v[p] : T(0);
+        out[p] = fma_rn(A.beta, vv, A.alpha * u[p]) + Xc;
+    }
+    T x = Xc;
+#pragma unroll
+    for (int k = M - 2; k >= 0; --k) {
+        if (FULL || k < L - 1) {
+            x = fma_rn(qa[k], x, da[k]);
+            const size_t p = base + (size_t)k * nx;
+            const T vv = hasv ? v[p] : T(0);
+            out[p] = fma_rn(A.beta, vv, A.alpha * u[p]) + x;
+        }
+    }
+}
+
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_ysolve(YArgs<T> A)
 {
@@ -316,37 +261,8 @@ __global__ void __launch_bounds__(256) k_ysolve(YArgs<T> A)
     const T Xp = (c > 0) ? A.X[(size_t)(c - 1) * nx + i] : T(0);
     const T Xc = A.X[(size_t)c * nx + i];
     const size_t base = (size_t)lo * nx + i;
-    T cp[M], dp[M];
-    T cpv = T(0), dpv = T(0);
-#pragma unroll
-    for (int k = 0; k < M - 1; ++k) {
-        cp[k] = T(0); dp[k] = T(0);
-        if (k < L - 1) {
-            const T rk = A.r[base + (size_t)k * nx];
-            T rhs = A.w[base + (size_t)k * nx];
-            if (k == 0) rhs += rk * Xp;
-            const T m = T(1) / (T(1) + T(2) * rk + rk * cpv);
-            cpv = -rk * m;
-            dpv = (rhs + rk * dpv) * m;
-            cp[k] = cpv; dp[k] = dpv;
-        }
-    }
-    const bool hasv = A.v != nullptr;
-    {
-        const size_t p = base + (size_t)(L - 1) * nx;
-        const T vv = hasv ? A.v[p] : T(0);
-        A.out[p] = (A.alpha * A.u[p] + A.beta * vv) + Xc;
-    }
-    T x = Xc;
-#pragma unroll
-    for (int k = M - 2; k >= 0; --k) {
-        if (k < L - 1) {
-            x = dp[k] - cp[k] * x;
-            const size_t p = base + (size_t)k * nx;
-            const T vv = hasv ? A.v[p] : T(0);
-            A.out[p] = (A.alpha * A.u[p] + A.beta * vv) + x;
-        }
-    }
+    if (L == M) ysolve_chunk<T, M, true>(A, base, nx, L, Xp, Xc);
+    else ysolve_chunk<T, M, false>(A, base, nx, L, Xp, Xc);
 }
 
 // traces[r] = out[idx[r]]; an offset outside [0, npts) records NaN

@@ -269,31 +269,34 @@ def test_step_rotation_and_determinism(adw):
     assert g2 is g and h2 is h_ and torch.equal(h2, u1)
 
 
-@pytest.mark.parametrize("tr,s,m", [(64, 8, 16), (256, 2, 32), (256, 4, 16), (1024, 2, 32),
-                                    (64, 16, 32), (256, 16, 16)])
-def test_launch_plans(adw, oracle_lib, tr, s, m):
-    """Every admissible launch plan reaches the same answer (FP64, 10 steps, 300 x 211)."""
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("tr,rs,fused,m", [(64, 3, False, 16), (64, 1, True, 32), (256, 2, False, 32),
+                                           (256, 5, True, 16), (1024, 32, False, 32),
+                                           (1024, 7, True, 16), (1024, 1, False, 16)])
+def test_launch_plans(adw, oracle_lib, dtype, tr, rs, fused, m):
+    """Every admissible launch plan reaches the same answer (10 steps, 300 x 211)."""
     nx, ny = 300, 211
     h = 1.0 / 301
     dt = 0.5 * h
-    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=21)
-    u0 = wl.gaussian_pulse(nx, ny, sigma=0.1)
-    say(f"plan tr={tr} s={s} m={m}")
-    if s == 16:
-        pytest.skip("16 nodes per thread is f32-only")
-    if tr * s < nx:
-        pytest.skip("plan does not cover the row")
-    wave = adw.Wave(nx, ny, h, dt, c=dev(c), dtype=torch.float64)
-    wave.set_tuning(tr, s, 3, m)
+    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=21).astype(npdt(dtype))
+    u0 = wl.gaussian_pulse(nx, ny, sigma=0.1).astype(npdt(dtype))
+    say(f"plan {dtype} tr={tr} rs={rs} fused={fused} m={m}")
+    if fused and dtype == "f64" and tr == 1024:
+        pytest.skip("the fused FP64 state does not fit in LDS at 1024 threads per line")
+    wave = adw.Wave(nx, ny, h, dt, c=dev(c), dtype=tdt(dtype))
+    wave.set_tuning(tr, rs, fused, m)
     inf = wave.info()
-    assert (inf["x_threads_per_line"], inf["x_elems_per_thread"], inf["y_chunk_rows"]) == (tr, s, m)
+    assert (inf["x_threads_per_line"], inf["y_fused"], inf["y_chunk_rows"]) == (tr, int(fused), m)
+    assert inf["x_rows_per_strip"] == (m if fused else rs)
+    assert inf["kernels_per_step"] == (3 if fused else 4)
     a = dev(u0)
     b = wave.start(a)
     a, b = wave.step(a, b, 10)
     torch.cuda.synchronize()
-    u1 = oracle_lib.start(c * c, u0, h, dt)
-    _, ref, _ = oracle_lib.run(c * c, u0, u1, h, dt, 10)
-    assert rel_l2(b.cpu().numpy(), ref) <= TOL_RUN["f64"]
+    kap = c.astype(np.float64) ** 2
+    u1 = oracle_lib.start(kap, u0, h, dt)
+    _, ref, _ = oracle_lib.run(kap, u0, u1, h, dt, 10)
+    assert rel_l2(b.cpu().numpy(), ref) <= TOL_RUN[dtype]
 
 
 def test_invalid_calls_raise(adw):
@@ -306,8 +309,7 @@ def test_invalid_calls_raise(adw):
     with pytest.raises(TypeError):
         wave.step(u, torch.zeros((16, 16), device="cuda", dtype=torch.float64), 1)
     with pytest.raises(adw.AdiError):
-        wave.set_tuning(64, 2, 1, 16)         # 64*2 < 16? no: 128 >= 16 is fine; chunk ok
-        wave.set_tuning(64, 2, 1, 24)         # chunk rows must be 16 or 32
+        wave.set_tuning(64, 2, False, 24)     # chunk rows must be 16 or 32
     with pytest.raises(adw.AdiError):
         wave.start(u, mode="paper", out=u)    # u1 aliases u0
 
