@@ -96,7 +96,7 @@ typedef struct {
  * The per-node coefficient r = dt^2 speed^2 / (2 h^2) is computed on the
  * device in the handle's type and kept in the workspace.
  * hip_stream: hipStream_t the handle queues on (NULL = default stream).
- * Limits: 1 <= nx <= 8192, 1 <= ny, nx*ny < 2^31.
+ * Limits: 1 <= nx <= 8192, 1 <= ny <= 16384.
  * Synchronises the stream before returning (the workspace is ready). */
 adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
                            const void* speed, double speed_scalar, adi_dtype dtype,

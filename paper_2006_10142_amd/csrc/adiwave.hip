@@ -92,13 +92,14 @@ int choose_rows(int ny, int tr)
 struct YScanPlan { int sk, p; };
 bool choose_yscan(int K, YScanPlan& q)
 {
-    static const int ps[] = {16, 64, 256};
-    static const int sks[] = {2, 4, 8, 16};
-    for (int p : ps)
-        for (int sk : sks)
-            if ((long long)p * sk >= K) { q.p = p; q.sk = sk; return true; }
+    static const int cand[][2] = {{16, 2}, {16, 4}, {16, 8}, {64, 4}, {64, 8}};
+    for (auto& c : cand)
+        if ((long long)c[0] * c[1] >= K) { q.p = c[0]; q.sk = c[1]; return true; }
     return false;
 }
+
+// fused strips hold whole y-chunks: 32 rows, or one chunk when chunks are longer
+int fused_rows(int M) { return M * std::max(1, 32 / M); }
 
 // ---------------------------------------------------- template dispatch ----
 template <typename T, int TR, bool FUSE>
@@ -133,11 +134,11 @@ bool launch_x(const XPlan& p, int grid, const XArgs<T>& a, hipStream_t st)
 template <typename T, int P>
 bool launch_yscan_sk(int sk, int grid, const YArgs<T>& a, hipStream_t st)
 {
+    const dim3 blk(kPB * P);
     switch (sk) {
-        case 2: hipLaunchKernelGGL((k_yscan<T, 2, P>), dim3(grid), dim3(256), 0, st, a); return true;
-        case 4: hipLaunchKernelGGL((k_yscan<T, 4, P>), dim3(grid), dim3(256), 0, st, a); return true;
-        case 8: hipLaunchKernelGGL((k_yscan<T, 8, P>), dim3(grid), dim3(256), 0, st, a); return true;
-        case 16: hipLaunchKernelGGL((k_yscan<T, 16, P>), dim3(grid), dim3(256), 0, st, a); return true;
+        case 2: hipLaunchKernelGGL((k_yscan<T, 2, P>), dim3(grid), blk, 0, st, a); return true;
+        case 4: hipLaunchKernelGGL((k_yscan<T, 4, P>), dim3(grid), blk, 0, st, a); return true;
+        case 8: hipLaunchKernelGGL((k_yscan<T, 8, P>), dim3(grid), blk, 0, st, a); return true;
     }
     return false;
 }
@@ -145,12 +146,10 @@ bool launch_yscan_sk(int sk, int grid, const YArgs<T>& a, hipStream_t st)
 template <typename T>
 bool launch_yscan(const YScanPlan& q, int nx, const YArgs<T>& a, hipStream_t st)
 {
-    const int cb = 256 / q.p;
-    const int grid = (nx + cb - 1) / cb;
+    const int grid = (nx + kPB - 1) / kPB;
     switch (q.p) {
         case 16: return launch_yscan_sk<T, 16>(q.sk, grid, a, st);
         case 64: return launch_yscan_sk<T, 64>(q.sk, grid, a, st);
-        case 256: return launch_yscan_sk<T, 256>(q.sk, grid, a, st);
     }
     return false;
 }
@@ -159,8 +158,8 @@ template <typename T>
 bool launch_ysolve(int M, dim3 grid, const YArgs<T>& a, hipStream_t st)
 {
     switch (M) {
-        case 16: hipLaunchKernelGGL((k_ysolve<T, 16>), grid, dim3(256), 0, st, a); return true;
-        case 32: hipLaunchKernelGGL((k_ysolve<T, 32>), grid, dim3(256), 0, st, a); return true;
+        case 16: hipLaunchKernelGGL((k_ysolve<T, 16, 16>), grid, dim3(256), 0, st, a); return true;
+        case 32: hipLaunchKernelGGL((k_ysolve<T, 32, 8>), grid, dim3(256), 0, st, a); return true;
     }
     return false;
 }
@@ -214,6 +213,8 @@ struct adi_wave_s {
     void* X = nullptr;     // K * nx
     void* qin = nullptr;   // ny * nseg entry pivots of the x-line segments
     int nseg = 0;
+    int nxp = 0;           // nx rounded up to the summary-plane column block
+    size_t w_cap = 0;      // elements of w (also create-time scratch of 5*K*nx)
     XPlan xp{};
     int M = 32, K = 0;
     YScanPlan yq{};
@@ -239,15 +240,28 @@ adi_status alloc_chunks(adi_wave_s* w)
     if (w->X) (void)hipFree(w->X);
     w->sum = w->X = nullptr;
     w->K = (w->ny + w->M - 1) / w->M;
+    w->nxp = (w->nx + kPB - 1) / kPB * kPB;
     if (!choose_yscan(w->K, w->yq))
-        return fail(ADI_EUNSUPPORTED, "too many y-chunks for the interface solver");
-    const size_t nsum = (size_t)kSummaryPlanes * w->K * w->nx;
+        return fail(ADI_EUNSUPPORTED, "too many y-chunks for the interface solver (ny too large)");
+    const size_t nsum = (size_t)kSummaryPlanes * w->K * w->nxp;
     const size_t nX = (size_t)w->K * w->nx;
+    const size_t wneed = std::max((size_t)w->nx * w->ny, (size_t)5 * w->K * w->nx);
+    if (wneed > w->w_cap) {
+        if (w->w) (void)hipFree(w->w);
+        w->w = nullptr;
+        w->w_cap = 0;
+        if (hipMalloc(&w->w, wneed * es) != hipSuccess) {
+            (void)hipGetLastError();
+            w->w = nullptr;
+            return fail(ADI_ENOMEM, "hipMalloc of the x-sweep field failed");
+        }
+        w->w_cap = wneed;
+    }
     if (hipMalloc(&w->sum, nsum * es) != hipSuccess || hipMalloc(&w->X, nX * es) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ADI_ENOMEM, "hipMalloc of y-chunk workspace failed");
     }
-    w->bytes = (2 * (size_t)w->nx * w->ny + (size_t)w->ny * w->nseg + nsum + nX) * es;
+    w->bytes = ((size_t)w->nx * w->ny + w->w_cap + (size_t)w->ny * w->nseg + nsum + nX) * es;
     return ADI_OK;
 }
 
@@ -289,11 +303,13 @@ XArgs<T> make_x(const adi_wave_s* w, const void* u, const adi_source* f, int k, 
     a.nx = w->nx;
     a.ny = w->ny;
     a.nseg = w->nseg;
-    a.rows_per_strip = w->xp.fuse ? w->M : w->xp.rs;
+    a.rows_per_strip = w->xp.fuse ? fused_rows(w->M) : w->xp.rs;
     a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && aligned16(u) && aligned16(w->r) &&
             aligned16(w->w);
     a.sum = static_cast<T*>(w->sum);
     a.K = w->K;
+    a.M = w->M;
+    a.nxp = w->nxp;
     a.rho_scale = rho_scale;
     a.tau2 = (T)(w->dt * w->dt);
     if (f && f->count > 0) {
@@ -314,6 +330,8 @@ YArgs<T> make_y(const adi_wave_s* w, const void* u, const void* v, void* out, T 
     a.ny = w->ny;
     a.M = w->M;
     a.K = w->K;
+    a.nxp = w->nxp;
+    a.tmp = static_cast<T*>(w->w);
     a.sum = static_cast<T*>(w->sum);
     a.X = static_cast<T*>(w->X);
     a.u = static_cast<const T*>(u);
@@ -327,7 +345,7 @@ YArgs<T> make_y(const adi_wave_s* w, const void* u, const void* v, void* out, T 
 int x_grid(const adi_wave_s* w)
 {
     const int g = x_groups_per_wg(w->xp.tr);
-    const int rs = w->xp.fuse ? w->M : w->xp.rs;
+    const int rs = w->xp.fuse ? fused_rows(w->M) : w->xp.rs;
     const int strips = (w->ny + rs - 1) / rs;
     return (strips + g - 1) / g;
 }
@@ -364,17 +382,17 @@ adi_status queue_solve(adi_wave_s* w, const void* u, const void* v, void* out, T
     return ADI_OK;
 }
 
-// The y-chunk summary planes that depend on r only (Lf, Rf, Ll, Rl, rI): one
-// chunk reduction of a zero right-hand side.  The fused x-sweep then rewrites
-// only the data-dependent planes (Pf, Pl, wI) every step.
+// The interface-system coefficients of the y-chunks depend on r only: built
+// once (through the w buffer as scratch); every step then writes E and Pf.
 template <typename T>
 adi_status static_planes(adi_wave_s* w)
 {
-    ADI_HIP(hipMemsetAsync(w->w, 0, (size_t)w->nx * w->ny * sizeof(T), w->stream));
     YArgs<T> ya = make_y<T>(w, nullptr, nullptr, nullptr, T(0), T(0));
     const dim3 yg((w->nx + 255) / 256, w->K);
-    hipLaunchKernelGGL((k_yreduce<T>), yg, dim3(256), 0, w->stream, ya);
-    ADI_LAUNCHED("y_reduce (static planes)");
+    hipLaunchKernelGGL((k_ystatic1<T>), yg, dim3(256), 0, w->stream, ya);
+    ADI_LAUNCHED("y_static (pass 1)");
+    hipLaunchKernelGGL((k_ystatic2<T>), yg, dim3(256), 0, w->stream, ya);
+    ADI_LAUNCHED("y_static (pass 2)");
     return ADI_OK;
 }
 
@@ -445,6 +463,7 @@ adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
     if (dtype != ADI_F32 && dtype != ADI_F64) return fail(ADI_EINVAL, "unknown dtype");
     if (nx < 1 || ny < 1) return fail(ADI_EINVAL, "nx and ny must be >= 1");
     if ((long long)nx * ny >= (1LL << 31)) return fail(ADI_EUNSUPPORTED, "nx*ny must be < 2^31");
+    if (ny > 16384) return fail(ADI_EUNSUPPORTED, "ny > 16384 is not supported");
     if (!finite_pos(h) || !finite_pos(dt)) return fail(ADI_EINVAL, "h and dt must be finite and > 0");
     if (!speed && !finite_pos(speed_scalar))
         return fail(ADI_EINVAL, "speed_scalar must be finite and > 0 when speed is NULL");
@@ -458,7 +477,7 @@ adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
     w->nx = nx; w->ny = ny; w->h = h; w->dt = dt; w->dtype = dtype;
     w->stream = static_cast<hipStream_t>(hip_stream);
     w->xp = xp;
-    w->M = dtype == ADI_F64 ? 16 : 32;   // keeps the chunk solve of FP64 in registers
+    w->M = 32;                       // chunk rows
     if (hipGetDevice(&w->device) != hipSuccess) {
         delete w;
         return fail(ADI_EHIP, "hipGetDevice failed");
@@ -466,7 +485,7 @@ adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
     const size_t es = esize(dtype);
     const size_t npts = (size_t)nx * ny;
     w->nseg = (nx + kSeg - 1) / kSeg;
-    if (hipMalloc(&w->r, npts * es) != hipSuccess || hipMalloc(&w->w, npts * es) != hipSuccess ||
+    if (hipMalloc(&w->r, npts * es) != hipSuccess ||
         hipMalloc(&w->qin, (size_t)ny * w->nseg * es) != hipSuccess) {
         (void)hipGetLastError();
         free_ws(w);
@@ -546,7 +565,7 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->ny = w->ny;
     info->dtype = (int)w->dtype;
     info->x_threads_per_line = w->xp.tr;
-    info->x_rows_per_strip = w->xp.fuse ? w->M : w->xp.rs;
+    info->x_rows_per_strip = w->xp.fuse ? fused_rows(w->M) : w->xp.rs;
     info->y_fused = w->xp.fuse;
     info->y_chunk_rows = w->M;
     info->y_chunks = w->K;

@@ -87,59 +87,65 @@ __global__ void __launch_bounds__(256) k_coef(const T* __restrict__ src, T scala
 
 // ---------------------------------------------------------------- y-lines ----
 // Chunk c of a y-line covers rows [c*M, c*M + Lc), Lc = min(M, ny - c*M).  Its
-// interface unknown is the last row; its interior the Lc - 1 rows above.
-// Summary planes (each K*nx values, index c*nx + i):
-//   0 Pf, 1 Lf, 2 Rf : first interior value = Pf + Lf X_{c-1} + Rf X_c
-//   3 Pl, 4 Ll, 5 Rl : last interior value  = Pl + Ll X_{c-1} + Rl X_c
-//   6 rI, 7 wI       : r and w of the interface row
-constexpr int kSummaryPlanes = 8;
+// interface unknown X_c is the last row; its interior the Lc - 1 rows above.
+// Eliminating the interior with X_{c-1} and X_c left open gives
+//   first interior value = Pf + Lf X_{c-1} + Rf X_c
+//   last interior value  = Pl + Ll X_{c-1} + Rl X_c
+// (P: data part; L, R: responses to the two interface values, r only).  The
+// interface row (coefficients -rI, 1 + 2 rI, -rI, right-hand side wI) then reads
+//   A_c X_{c-1} + B_c X_c + C_c X_{c+1} = D_c
+//   A_c = -rI Ll_c,  B_c = 1 + 2 rI - rI Rl_c - rI Lf_{c+1},  C_c = -rI Rf_{c+1},
+//   D_c = E_c + rI Pf_{c+1},  E_c = wI + rI Pl_c,
+// the chunk c+1 terms being absent for the last chunk.  A, B, C and rI depend
+// on r only and are built once; every step writes E and Pf.
+//
+// Summary planes are blocked by kPB columns so that one column block's whole
+// interface system is contiguous: plane v, chunk c, column i at
+//   v*K*nxp + ((i / kPB) * K + c) * kPB + i % kPB,   nxp = nx rounded up to kPB.
+enum SumPlane { kPlaneA = 0, kPlaneB = 1, kPlaneC = 2, kPlaneRI = 3, kPlaneE = 4, kPlanePf = 5 };
+constexpr int kSummaryPlanes = 6;
+
+__host__ __device__ __forceinline__ size_t plane_at(int v, int c, int i, int K, int nxp)
+{
+    return (size_t)v * K * nxp + ((size_t)(i / kPB) * K + c) * kPB + (i % kPB);
+}
 
 template <typename T>
 struct YArgs {
     const T* w;          // x-sweep result
     const T* r;
-    int nx, ny, M, K;
-    T* sum;              // summary planes
-    T* X;                // K*nx interface values
+    int nx, ny, M, K, nxp;
+    T* sum;              // summary planes (blocked, see above)
+    T* X;                // K*nx interface values, index c*nx + i
     const T* u;          // update: out = alpha*u + beta*v + d
     const T* v;          // may be null when beta == 0
     T* out;
     T alpha, beta;
-    int nrec;            // receivers recorded from out after the update
-    const int* rec_idx;
-    T* traces;           // nrec values for this step
+    T* tmp;              // create-time scratch for the static planes (5*K*nx)
 };
 
-// One thread per (column, chunk): interior elimination streamed top-down.
-// Interior rows k = 0..L-2 are eliminated with pivots started afresh at the
-// chunk (q = 0); P = values with X_{c-1} = X_c = 0, L = response to X_{c-1},
-// R = response to X_c.  First values come from the back-substitution written
-// as a running sum (first = sum_k prod_{i<k} q_i * forward_k).
-template <typename T, bool FULL>
-__device__ __forceinline__ void yreduce_chunk(const T* __restrict__ wp, const T* __restrict__ rp,
-                                              size_t nx, int L, T (&o)[8])
+// Data part of one chunk's interior elimination (top-down, pivots started
+// afresh at the chunk): P forward value at the last interior row (Pl) and the
+// first interior value of the P solution (Pf, as a running sum of
+// prod_{i<k} q_i * forward_k).
+template <typename T, bool FULL, int M>
+__device__ __forceinline__ void ychunk_data(const T* __restrict__ wp, const T* __restrict__ rp,
+                                            size_t nx, int L, T& Pf, T& Pl)
 {
-    T Pf = T(0), Lf = T(0), Rf = T(1), Pl = T(0), Ll = T(1), Rl = T(0);
-    if (L >= 2) {
-        T q = T(0), dpv = T(0), dlv = T(1), pi = T(1), yP = T(0), yL = T(0);
-        for (int k = 0; k < (FULL ? 31 : L - 1); ++k) {
-            const T rk = rp[(size_t)k * nx];
-            const T wk = wp[(size_t)k * nx];
-            const T m = pivot_step<T>(rk, q);
-            dpv = fma_rn(rk, dpv, wk) * m;
-            dlv = q * dlv;
-            yP = fma_rn(pi, dpv, yP);
-            yL = fma_rn(pi, dlv, yL);
-            pi = pi * q;
-        }
-        Pf = yP; Lf = yL; Rf = pi;
-        Pl = dpv; Ll = dlv; Rl = q;
+    T q = T(0), dpv = T(0), pi = T(1), yP = T(0);
+    for (int k = 0; k < (FULL ? M - 1 : L - 1); ++k) {
+        const T rk = rp[(size_t)k * nx];
+        const T wk = wp[(size_t)k * nx];
+        const T m = pivot_step<T>(rk, q);
+        dpv = fma_rn(rk, dpv, wk) * m;
+        yP = fma_rn(pi, dpv, yP);
+        pi = pi * q;
     }
-    o[0] = Pf; o[1] = Lf; o[2] = Rf; o[3] = Pl; o[4] = Ll; o[5] = Rl;
-    o[6] = rp[(size_t)(L - 1) * nx];
-    o[7] = wp[(size_t)(L - 1) * nx];
+    Pf = yP;
+    Pl = dpv;
 }
 
+// Unfused chunk reduction: one thread per (column, chunk) writes E and Pf.
 template <typename T>
 __global__ void __launch_bounds__(256) k_yreduce(YArgs<T> A)
 {
@@ -151,35 +157,82 @@ __global__ void __launch_bounds__(256) k_yreduce(YArgs<T> A)
     const int L = min(A.M, A.ny - lo);
     const T* __restrict__ wp = A.w + (size_t)lo * nx + i;
     const T* __restrict__ rp = A.r + (size_t)lo * nx + i;
-    T o[8];
-    if (L == 32 && A.M == 32) yreduce_chunk<T, true>(wp, rp, nx, L, o);
-    else yreduce_chunk<T, false>(wp, rp, nx, L, o);
-    const size_t plane = (size_t)A.K * nx;
-    T* __restrict__ out = A.sum + (size_t)c * nx + i;
-#pragma unroll
-    for (int v = 0; v < kSummaryPlanes; ++v) out[v * plane] = o[v];
+    T Pf = T(0), Pl = T(0);
+    if (L == 16 && A.M == 16) ychunk_data<T, true, 16>(wp, rp, nx, L, Pf, Pl);
+    else if (L == 32 && A.M == 32) ychunk_data<T, true, 32>(wp, rp, nx, L, Pf, Pl);
+    else if (L >= 2) ychunk_data<T, false, 1>(wp, rp, nx, L, Pf, Pl);
+    const T rI = rp[(size_t)(L - 1) * nx];
+    const T wI = wp[(size_t)(L - 1) * nx];
+    A.sum[plane_at(kPlaneE, c, i, A.K, A.nxp)] = fma_rn(rI, Pl, wI);
+    A.sum[plane_at(kPlanePf, c, i, A.K, A.nxp)] = Pf;
 }
 
-// Chunk-interface system of every column, solved with the partition solver:
-// CB columns per workgroup, P threads per column, SK consecutive chunks per
-// thread.  The equation of chunk c (interface row coefficients -rI, 1+2rI, -rI):
-//   A_c = -rI Ll_c, B_c = 1 + 2rI - rI Rl_c - rI Lf_{c+1}, C_c = -rI Rf_{c+1},
-//   D_c = wI + rI Pl_c + rI Pf_{c+1}      (terms of chunk c+1 absent for the last)
-template <typename T, int SK, int P>
-__global__ void __launch_bounds__(256) k_yscan(YArgs<T> A)
+// Static planes, pass 1: the r-only responses of every chunk (Lf, Rf, Ll, Rl, rI)
+// into A.tmp (5 planes of K*nx, index v*K*nx + c*nx + i).
+template <typename T>
+__global__ void __launch_bounds__(256) k_ystatic1(YArgs<T> A)
 {
-    constexpr int CB = 256 / P;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= A.nx) return;
+    const size_t nx = (size_t)A.nx;
+    const int lo = c * A.M;
+    const int L = min(A.M, A.ny - lo);
+    const T* __restrict__ rp = A.r + (size_t)lo * nx + i;
+    T Lf = T(0), Rf = T(1), Ll = T(1), Rl = T(0);      // one-row chunk
+    if (L >= 2) {
+        T q = T(0), dlv = T(1), pi = T(1), yL = T(0);
+        for (int k = 0; k < L - 1; ++k) {
+            (void)pivot_step<T>(rp[(size_t)k * nx], q);
+            dlv = q * dlv;                 // response to X_{c-1}: prod of q
+            yL = fma_rn(pi, dlv, yL);
+            pi = pi * q;
+        }
+        Lf = yL; Rf = pi; Ll = dlv; Rl = q;
+    }
+    const size_t plane = (size_t)A.K * nx;
+    T* o = A.tmp + (size_t)c * nx + i;
+    o[0 * plane] = Lf; o[1 * plane] = Rf; o[2 * plane] = Ll; o[3 * plane] = Rl;
+    o[4 * plane] = rp[(size_t)(L - 1) * nx];
+}
+
+// Static planes, pass 2: interface-system coefficients A, B, C and rI.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ystatic2(YArgs<T> A)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= A.nx) return;
+    const size_t nx = (size_t)A.nx;
+    const size_t plane = (size_t)A.K * nx;
+    const T* t = A.tmp + (size_t)c * nx + i;
+    const T Ll = t[2 * plane], Rl = t[3 * plane], rI = t[4 * plane];
+    T nLf = T(0), nRf = T(0);
+    if (c + 1 < A.K) { nLf = t[nx]; nRf = t[plane + nx]; }
+    A.sum[plane_at(kPlaneA, c, i, A.K, A.nxp)] = (c == 0) ? T(0) : -rI * Ll;
+    A.sum[plane_at(kPlaneB, c, i, A.K, A.nxp)] = T(1) + T(2) * rI - rI * Rl - rI * nLf;
+    A.sum[plane_at(kPlaneC, c, i, A.K, A.nxp)] = -rI * nRf;
+    A.sum[plane_at(kPlaneRI, c, i, A.K, A.nxp)] = rI;
+}
+
+// Interface system of every column, solved with the partition solver: a
+// workgroup owns one block of kPB columns, P threads per column, SK consecutive
+// chunks per thread.
+template <typename T, int SK, int P>
+__global__ void __launch_bounds__(kPB * P) k_yscan(YArgs<T> A)
+{
+    constexpr int CB = kPB;
     __shared__ T lds[partition_lds_slots<P>() * CB];
     const int col = threadIdx.x % CB;
     const int t = threadIdx.x / CB;
     const int i = blockIdx.x * CB + col;
     const bool live = i < A.nx;
     const int K = A.K;
-    const size_t nx = (size_t)A.nx;
-    const size_t plane = (size_t)K * nx;
     const int c0 = t * SK;
     const int L = live ? max(0, min(SK, K - c0)) : 0;
     const int nact = live ? (K + SK - 1) / SK : 0;
+    const size_t pl = (size_t)K * A.nxp;
+    const T* __restrict__ base = A.sum + ((size_t)blockIdx.x * K) * kPB + col;
 
     T a[SK], b[SK], cc[SK], d[SK];
 #pragma unroll
@@ -187,29 +240,26 @@ __global__ void __launch_bounds__(256) k_yscan(YArgs<T> A)
         a[k] = T(0); b[k] = T(1); cc[k] = T(0); d[k] = T(0);
         const int c = c0 + k;
         if (k < L) {
-            const T* s = A.sum + (size_t)c * nx + i;
-            const T Pl = s[3 * plane], Ll = s[4 * plane], Rl = s[5 * plane];
-            const T rI = s[6 * plane], wI = s[7 * plane];
-            T nPf = T(0), nLf = T(0), nRf = T(0);
-            if (c + 1 < K) {
-                const T* sn = s + nx;
-                nPf = sn[0]; nLf = sn[plane]; nRf = sn[2 * plane];
-            }
-            a[k] = -rI * Ll;
-            b[k] = T(1) + T(2) * rI - rI * Rl - rI * nLf;
-            cc[k] = -rI * nRf;
-            d[k] = wI + rI * Pl + rI * nPf;
+            const T* s = base + (size_t)c * kPB;
+            a[k] = s[kPlaneA * pl];
+            b[k] = s[kPlaneB * pl];
+            cc[k] = s[kPlaneC * pl];
+            const T nPf = (c + 1 < K) ? s[kPlanePf * pl + kPB] : T(0);
+            d[k] = fma_rn(s[kPlaneRI * pl], nPf, s[kPlaneE * pl]);
         }
     }
     partition_solve<T, SK, P>(d, CoefABC<T, SK>{a, b, cc}, L, t, nact, lds + col, CB);
 #pragma unroll
     for (int k = 0; k < SK; ++k)
-        if (k < L) A.X[(size_t)(c0 + k) * nx + i] = d[k];
+        if (k < L) A.X[(size_t)(c0 + k) * A.nx + i] = d[k];
 }
 
 // One thread per (column, chunk): the chunk's interior re-solved with X_{c-1}
 // and X_c known, then the update out = alpha u + beta v + d of every row.
-template <typename T, int M, bool FULL>
+// Rows are loaded in groups of GR (a scheduling barrier between groups keeps
+// the compiler from hoisting every load of the chunk, which would cost
+// occupancy); FULL = the chunk has all M rows.
+template <typename T, int M, int GR, bool FULL>
 __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, size_t nx, int L, T Xp, T Xc)
 {
     const T* __restrict__ w = A.w;
@@ -220,36 +270,57 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
     T qa[M], da[M];
     T q = T(0), dpv = T(0);
 #pragma unroll
-    for (int k = 0; k < M - 1; ++k) {
-        qa[k] = T(0); da[k] = T(0);
-        if (FULL || k < L - 1) {
-            const T rk = r[base + (size_t)k * nx];
-            T rhs = w[base + (size_t)k * nx];
-            if (k == 0) rhs = fma_rn(rk, Xp, rhs);
-            const T m = pivot_step<T>(rk, q);
-            dpv = fma_rn(rk, dpv, rhs) * m;
-            qa[k] = q; da[k] = dpv;
+    for (int g0 = 0; g0 < M - 1; g0 += GR) {
+        T rr[GR], ww[GR];
+#pragma unroll
+        for (int k = g0; k < g0 + GR && k < M - 1; ++k) {
+            rr[k - g0] = T(0); ww[k - g0] = T(0);
+            if (FULL || k < L - 1) {
+                rr[k - g0] = r[base + (size_t)k * nx];
+                ww[k - g0] = w[base + (size_t)k * nx];
+            }
         }
+#pragma unroll
+        for (int k = g0; k < g0 + GR && k < M - 1; ++k) {
+            qa[k] = T(0); da[k] = T(0);
+            if (FULL || k < L - 1) {
+                const T rk = rr[k - g0];
+                T rhs = ww[k - g0];
+                if (k == 0) rhs = fma_rn(rk, Xp, rhs);
+                const T m = pivot_step<T>(rk, q);
+                dpv = fma_rn(rk, dpv, rhs) * m;
+                qa[k] = q; da[k] = dpv;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
     const bool hasv = v != nullptr;
-    {
-        const size_t p = base + (size_t)(L - 1) * nx;
-        const T vv = hasv ? v[p] : T(0);
-        out[p] = fma_rn(A.beta, vv, A.alpha * u[p]) + Xc;
-    }
     T x = Xc;
 #pragma unroll
-    for (int k = M - 2; k >= 0; --k) {
-        if (FULL || k < L - 1) {
-            x = fma_rn(qa[k], x, da[k]);
-            const size_t p = base + (size_t)k * nx;
-            const T vv = hasv ? v[p] : T(0);
-            out[p] = fma_rn(A.beta, vv, A.alpha * u[p]) + x;
+    for (int g1 = M - 1; g1 >= 0; g1 -= GR) {
+        T uu[GR], vv[GR];
+#pragma unroll
+        for (int k = g1; k > g1 - GR && k >= 0; --k) {
+            uu[g1 - k] = T(0); vv[g1 - k] = T(0);
+            if (FULL || k < L) {
+                const size_t p = base + (size_t)k * nx;
+                uu[g1 - k] = u[p];
+                vv[g1 - k] = hasv ? v[p] : T(0);
+            }
         }
+#pragma unroll
+        for (int k = g1; k > g1 - GR && k >= 0; --k) {
+            if (FULL || k < L) {
+                if (k < L - 1) x = fma_rn(qa[k], x, da[k]);
+                else x = Xc;
+                out[base + (size_t)k * nx] = fma_rn(A.beta, vv[g1 - k], A.alpha * uu[g1 - k]) + x;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-template <typename T, int M>
+template <typename T, int M, int GR>
 __global__ void __launch_bounds__(256) k_ysolve(YArgs<T> A)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -261,8 +332,8 @@ __global__ void __launch_bounds__(256) k_ysolve(YArgs<T> A)
     const T Xp = (c > 0) ? A.X[(size_t)(c - 1) * nx + i] : T(0);
     const T Xc = A.X[(size_t)c * nx + i];
     const size_t base = (size_t)lo * nx + i;
-    if (L == M) ysolve_chunk<T, M, true>(A, base, nx, L, Xp, Xc);
-    else ysolve_chunk<T, M, false>(A, base, nx, L, Xp, Xc);
+    if (L == M) ysolve_chunk<T, M, GR, true>(A, base, nx, L, Xp, Xc);
+    else ysolve_chunk<T, M, GR, false>(A, base, nx, L, Xp, Xc);
 }
 
 // traces[r] = out[idx[r]]; an offset outside [0, npts) records NaN

@@ -159,12 +159,13 @@ struct XArgs {
     int nsrc;            // point sources of this step
     const int* src_idx;
     const T* src_amp;    // nsrc values of f
-    // fused y-chunk elimination (strips are the y-chunks): planes of K*nx
-    T* sum;              // summary planes (see kernels.hpp)
-    int K;
+    // fused y-chunk elimination: a strip is a whole number of y-chunks of M rows
+    T* sum;              // summary planes (blocked by 16 columns, see kernels.hpp)
+    int K, M, nxp;
 };
 
 constexpr int kSeg = 8;   // nodes per x-line segment (one segment per thread)
+constexpr int kPB = 16;   // column block width of the y-chunk summary planes
 
 // pivot entering every segment of every row: one thread per row, sequential
 template <typename T>
@@ -230,11 +231,12 @@ __device__ __forceinline__ void store8(T* __restrict__ row, int i0, int nx, bool
 // rows_per_strip consecutive rows and solves them in turn; rows j+2 (u) and
 // j+1 (r, entry pivots) are loaded while row j is being solved.
 //
-// FUSE: the strip is a y-chunk (rows_per_strip = chunk rows M, strips aligned
-// to chunks) and, as each row of w is produced, every column's interior
-// elimination of the chunk (the data-dependent part of the y-chunk summary,
-// see k_yreduce) is advanced; its running state lives in LDS.  At the end of
-// the strip the summary planes Pf (0), Pl (3) and wI (7) are written.
+// FUSE: a strip is a whole number of y-chunks (rows_per_strip a multiple of the
+// chunk rows M, strips aligned to chunks) and, as each row of w is produced,
+// every column's interior elimination of its chunk (the data-dependent part of
+// the y-chunk summary, see k_yreduce) is advanced; the running state lives in
+// LDS.  At each chunk's interface row the planes E and Pf are written and the
+// state restarts.
 template <typename T, int TR, bool FUSE>
 __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
 {
@@ -294,9 +296,7 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
     };
 
     T* ys = FUSE ? s_y + (size_t)g * 4 * E * TR : nullptr;
-    int Lc = 0;
-    if constexpr (FUSE) {
-        Lc = max(0, min(RS, ny - j0));
+    auto ystate_reset = [&]() {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             ys[(0 * E + e) * TR + t] = T(0);   // q
@@ -304,7 +304,8 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
             ys[(2 * E + e) * TR + t] = T(1);   // running product of q
             ys[(3 * E + e) * TR + t] = T(0);   // first-value sum
         }
-    }
+    };
+    if constexpr (FUSE) ystate_reset();
 
     load_u(j0 - 1, um);
     load_u(j0, uc);
@@ -430,7 +431,10 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
         }
 
         if constexpr (FUSE) {
-            if (act && it < Lc - 1) {
+            const int c = j / A.M;
+            const int kk = j - c * A.M;
+            const int Lc = live ? min(A.M, ny - c * A.M) : 0;
+            if (act && kk < Lc - 1) {
                 // interior row of the y-chunk: advance every column's elimination
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
@@ -447,17 +451,17 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
                     ys[(2 * E + e) * TR + t] = pi;
                     ys[(3 * E + e) * TR + t] = yp;
                 }
-            } else if (act && it == Lc - 1) {
-                // interface row of the chunk
-                const size_t plane = (size_t)A.K * nx;
-                T* o = A.sum + (size_t)(j0 / RS) * nx;
+            } else if (act && kk == Lc - 1) {
+                // interface row of the chunk: E = wI + rI Pl and Pf, then restart
+                const size_t pl = (size_t)A.K * A.nxp;
+                const size_t o = ((size_t)(i0 / kPB) * A.K + c) * kPB + (i0 % kPB);
 #pragma unroll
                 for (int e = 0; e < E; ++e)
                     if (e < L) {
-                        o[7 * plane + i0 + e] = wout[e];
-                        o[0 * plane + i0 + e] = ys[(3 * E + e) * TR + t];
-                        o[3 * plane + i0 + e] = ys[(1 * E + e) * TR + t];
+                        A.sum[4 * pl + o + e] = fma_rn(rc[e], ys[(1 * E + e) * TR + t], wout[e]);
+                        A.sum[5 * pl + o + e] = ys[(3 * E + e) * TR + t];
                     }
+                ystate_reset();
             }
         }
 

@@ -31,6 +31,7 @@ def test_library_exports_every_header_symbol():
     (4, 4, 0.1, 0.1, -2.0, _lib.ADI_EINVAL),
     (20000, 4, 0.1, 0.1, 1.0, _lib.ADI_EUNSUPPORTED),
     (46341, 46341, 0.1, 0.1, 1.0, _lib.ADI_EUNSUPPORTED),
+    (64, 16385, 0.1, 0.1, 1.0, _lib.ADI_EUNSUPPORTED),
 ])
 def test_create_rejects_bad_arguments_before_device_work(nx, ny, h, dt, speed, code):
     lib = _lib.load()

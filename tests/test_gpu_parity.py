@@ -272,7 +272,8 @@ def test_step_rotation_and_determinism(adw):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("tr,rs,fused,m", [(64, 3, False, 16), (64, 1, True, 32), (256, 2, False, 32),
                                            (256, 5, True, 16), (1024, 32, False, 32),
-                                           (1024, 7, True, 16), (1024, 1, False, 16)])
+                                           (1024, 7, True, 16), (1024, 1, False, 16),
+                                           (1024, 1, True, 32)])
 def test_launch_plans(adw, oracle_lib, dtype, tr, rs, fused, m):
     """Every admissible launch plan reaches the same answer (10 steps, 300 x 211)."""
     nx, ny = 300, 211
@@ -287,7 +288,7 @@ def test_launch_plans(adw, oracle_lib, dtype, tr, rs, fused, m):
     wave.set_tuning(tr, rs, fused, m)
     inf = wave.info()
     assert (inf["x_threads_per_line"], inf["y_fused"], inf["y_chunk_rows"]) == (tr, int(fused), m)
-    assert inf["x_rows_per_strip"] == (m if fused else rs)
+    assert inf["x_rows_per_strip"] == ((32 if m == 16 else 32) if fused else rs)
     assert inf["kernels_per_step"] == (3 if fused else 4)
     a = dev(u0)
     b = wave.start(a)
