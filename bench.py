@@ -46,7 +46,7 @@ WORKLOADS = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp", "xsweep.hpp"):
+    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp", "xsweep.hpp", "batch.hpp"):
         with open(os.path.join(ROOT, "paper_2006_10142_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -99,6 +99,46 @@ def cpu_baseline(prob, steps: int):
                       f"{t:.1f} s wall"}
 
 
+def bench_batched(adw, torch, steps: int, warmup: int, plain_value: float):
+    """C4: 256 independent FP32 simulations (N in 256..1024), one launch per kernel per
+    step for the whole batch, autotuned plan, replayed hipGraph."""
+    import numpy as np
+    from paper_2006_10142_amd import workloads as wl
+    probs = wl.config_c4(dtype="f32", nsteps=steps)
+    dev = torch.device("cuda:0")
+    b = adw.Batch([(p.nx, p.ny) for p in probs], [p.h for p in probs], [p.dt for p in probs],
+                  [torch.from_numpy(p.c).to(dev) for p in probs], dtype=torch.float32)
+    u0 = [torch.from_numpy(np.ascontiguousarray(p.u0)).to(dev) for p in probs]
+    u1 = [torch.zeros_like(x) for x in u0]
+    tuned_ms = b.autotune(trial_steps=5)
+    b.bind(u0, u1)
+    b.start("ghost")
+    b.graph(True)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    _, curr = b.levels()
+    finite = all(bool(torch.isfinite(x).all()) for x in curr)
+    plan = b.plan()
+    nodes = plan["nodes"]
+    value = nodes * steps / (ms / 1e3) / 1e6
+    b.close()
+    return {"workload": "c4_batch_256_sims_256_to_1024_f32", "value": round(value, 1),
+            "unit": "Mpts/s", "ms_per_step": round(ms / steps, 5), "sims": len(probs),
+            "nodes_per_step": nodes, "steps": steps, "graph": True,
+            "plan": {k: plan[k] for k in ("x_threads_per_line", "x_grid", "yscan_grid",
+                                          "ysolve_grid")},
+            "autotune_ms_per_step": round(tuned_ms, 5),
+            "step_algorithmic_GBps": round(STEP_BYTES_PER_NODE * 4 * nodes * steps / (ms / 1e3) / 1e9, 1),
+            "vs_plain": round(value / plain_value, 4), "finite": finite}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +148,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -220,9 +261,13 @@ def main():
         "create_ms": round(create_ms, 2),
         "wall_s_timed": round(wall, 4),
     }
+    wave.close()
+    del a, b
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = bench_batched(adw, torch, args.steps, args.warmup, value)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
-    wave.close()
     print(json.dumps(out), flush=True)
 
 

@@ -127,6 +127,66 @@ adi_status adi_wave_step(adi_wave_t w, void** u_prev, void** u_curr,
 /* Free the handle and its workspace (synchronises the handle's stream). */
 adi_status adi_wave_destroy(adi_wave_t w);
 
+/* ------------------------------------------------------ batched simulations -- */
+
+/* Many independent simulations of uneven grid sizes advanced together: each
+ * step of the batch advances every simulation by one ADI step (the scheme
+ * above on its own grid, spacing, time step and coefficient), with one
+ * launch per kernel for the whole batch over a work list of (simulation,
+ * tile) items.  No sources or receivers. */
+typedef struct adi_batch_s* adi_batch_t;
+
+/* count simulations; nx, ny, h, dt: host arrays of count entries.
+ * speed: host array of count device pointers to speed fields (nx[s]*ny[s]
+ * values) with NULL entries meaning "use speed_scalar[s]"; speed may be NULL
+ * (then speed_scalar is required).  Limits as for adi_wave_create, and the
+ * widest grid fixes the launch plan.  Synchronises the stream. */
+adi_status adi_batch_create(adi_batch_t* out, int count, const int* nx, const int* ny,
+                            const double* h, const double* dt, const void* const* speed,
+                            const double* speed_scalar, adi_dtype dtype, void* hip_stream);
+
+/* Bind the two time levels of every simulation (host arrays of count device
+ * pointers, u^{n-1} and u^n); uploads the descriptor table and synchronises
+ * the stream.  Resets the step parity and drops a captured graph. */
+adi_status adi_batch_bind(adi_batch_t b, void* const* u_prev, void* const* u_curr);
+
+/* u^1 from u^0 for every simulation (psi = 0): reads the bound u_prev[s]
+ * as u^0 and writes u_curr[s].  Only before the first step after a bind. */
+adi_status adi_batch_start(adi_batch_t b, int mode);
+
+/* nsteps steps of every simulation; the roles of the two bound levels rotate
+ * (adi_batch_levels reports them).  Replays the captured graph when present. */
+adi_status adi_batch_step(adi_batch_t b, int nsteps);
+
+/* Current roles after the steps so far: fills u_prev[s], u_curr[s]. */
+adi_status adi_batch_levels(adi_batch_t b, void** u_prev, void** u_curr);
+
+/* enable = 1: capture two steps (both level parities) in a hipGraph that
+ * adi_batch_step replays; enable = 0: drop it. */
+adi_status adi_batch_graph(adi_batch_t b, int enable);
+
+typedef struct {
+    int x_threads_per_line;   /* line-group width of the x-sweep */
+    int x_grid;               /* workgroups of each persistent launch (0 = one per work unit) */
+    int yscan_grid;
+    int ysolve_grid;
+    int graph;                /* 1 if a captured graph is replayed (read-only) */
+    int count;                /* simulations (read-only) */
+    long long nodes;          /* total grid nodes (read-only) */
+    size_t workspace_bytes;   /* device bytes owned by the batch (read-only) */
+    int x_items, yscan_items, ysolve_items;   /* work-list lengths (read-only) */
+} adi_batch_plan;
+adi_status adi_batch_get_plan(adi_batch_t b, adi_batch_plan* p);
+adi_status adi_batch_set_plan(adi_batch_t b, const adi_batch_plan* p);
+
+/* Autotuner: times candidate plans (line-group width, then each launch's
+ * persistent grid size) for trial_steps steps on scratch levels it allocates
+ * and frees, keeps the fastest plan and returns its milliseconds per step.
+ * The bound levels are not touched.  Synchronises the stream. */
+adi_status adi_batch_autotune(adi_batch_t b, int trial_steps, double* best_ms_per_step);
+
+adi_status adi_batch_destroy(adi_batch_t b);
+
 /* ------------------------------------------------------- batched line solve -- */
 
 /* Solve `batch` independent tridiagonal systems of size n:
@@ -165,7 +225,7 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
  * Any field <= 0 keeps the current value.  Reallocates chunk workspace if the
  * chunk size changes (synchronises the stream). */
 typedef struct {
-    int x_threads_per_line;   /* 64, 256 or 1024, with 8 * threads >= nx */
+    int x_threads_per_line;   /* 64, 128, 256 or 1024, with 8 * threads >= nx */
     int x_rows_per_strip;     /* >= 1 (unfused plans; a fused strip is one y-chunk) */
     int y_fused;              /* 1 = fuse the y-chunk elimination into the x-sweep, 2 = separate */
     int y_chunk_rows;         /* 16 or 32 */

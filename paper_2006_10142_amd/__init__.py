@@ -18,7 +18,7 @@ from typing import Optional, Tuple
 from . import _lib
 from ._lib import AdiError
 
-__all__ = ["Wave", "tridiag_solve_batched", "stream_copy", "AdiError", "lib_path"]
+__all__ = ["Wave", "Batch", "tridiag_solve_batched", "stream_copy", "AdiError", "lib_path"]
 
 lib_path = _lib.LIB_PATH
 
@@ -196,6 +196,135 @@ class Wave:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check(_lib.load().adi_wave_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent simulations of uneven grid sizes advanced together.
+
+    sizes: list of (nx, ny); h, dt: per-simulation lists; c: per-simulation
+    speed (scalar or (ny, nx) device tensor).  One launch per kernel covers the
+    whole batch each step; optionally captured in a hipGraph.
+    """
+
+    def __init__(self, sizes, h, dt, c, dtype=None):
+        torch = _torch()
+        dtype = torch.float32 if dtype is None else dtype
+        self.dtype = dtype
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        n = len(self.sizes)
+        if not (len(h) == len(dt) == len(c) == n):
+            raise ValueError("sizes, h, dt and c must have one entry per simulation")
+        self.count = n
+        self._code = _dtype_code(dtype)
+        nxa = (ctypes.c_int * n)(*[s[0] for s in self.sizes])
+        nya = (ctypes.c_int * n)(*[s[1] for s in self.sizes])
+        ha = (ctypes.c_double * n)(*[float(v) for v in h])
+        dta = (ctypes.c_double * n)(*[float(v) for v in dt])
+        sp = (ctypes.c_void_p * n)()
+        sc = (ctypes.c_double * n)()
+        self._keep = []
+        for k, ck in enumerate(c):
+            if isinstance(ck, torch.Tensor):
+                sp[k] = _field(ck, dtype, (self.sizes[k][1], self.sizes[k][0]), f"c[{k}]").value
+                sc[k] = 1.0
+                self._keep.append(ck)
+            else:
+                sp[k] = None
+                sc[k] = float(ck)
+        self._stream = torch.cuda.current_stream().cuda_stream
+        handle = ctypes.c_void_p()
+        _lib.check(_lib.load().adi_batch_create(ctypes.byref(handle), n, nxa, nya, ha, dta, sp, sc,
+                                                self._code, ctypes.c_void_p(self._stream)))
+        self._h = handle
+        self._levels = None
+
+    def bind(self, u_prev, u_curr):
+        """Bind the two levels of every simulation (lists of (ny, nx) device tensors)."""
+        n = self.count
+        a = (ctypes.c_void_p * n)()
+        b = (ctypes.c_void_p * n)()
+        for k in range(n):
+            shp = (self.sizes[k][1], self.sizes[k][0])
+            a[k] = _field(u_prev[k], self.dtype, shp, f"u_prev[{k}]").value
+            b[k] = _field(u_curr[k], self.dtype, shp, f"u_curr[{k}]").value
+        _lib.check(_lib.load().adi_batch_bind(self._h, a, b))
+        self._levels = {t.data_ptr(): t for t in list(u_prev) + list(u_curr)}
+
+    def start(self, mode: str = "ghost"):
+        m = {"paper": _lib.ADI_START_PAPER, "ghost": _lib.ADI_START_GHOST}[mode]
+        _lib.check(_lib.load().adi_batch_start(self._h, m))
+
+    def step(self, nsteps: int = 1):
+        _lib.check(_lib.load().adi_batch_step(self._h, int(nsteps)))
+
+    def levels(self):
+        """(u_prev list, u_curr list) as the bound tensors, in their current roles."""
+        n = self.count
+        a = (ctypes.c_void_p * n)()
+        b = (ctypes.c_void_p * n)()
+        _lib.check(_lib.load().adi_batch_levels(self._h, a, b))
+        return [self._levels[a[k]] for k in range(n)], [self._levels[b[k]] for k in range(n)]
+
+    def graph(self, enable: bool = True):
+        _lib.check(_lib.load().adi_batch_graph(self._h, 1 if enable else 0))
+
+    def plan(self) -> dict:
+        p = _lib.AdiBatchPlan()
+        _lib.check(_lib.load().adi_batch_get_plan(self._h, ctypes.byref(p)))
+        return {f: getattr(p, f) for f, _ in _lib.AdiBatchPlan._fields_}
+
+    def set_plan(self, x_threads_per_line=0, x_grid=0, yscan_grid=0, ysolve_grid=0):
+        p = _lib.AdiBatchPlan()
+        _lib.check(_lib.load().adi_batch_get_plan(self._h, ctypes.byref(p)))
+        if x_threads_per_line:
+            p.x_threads_per_line = x_threads_per_line
+        p.x_grid, p.yscan_grid, p.ysolve_grid = x_grid, yscan_grid, ysolve_grid
+        _lib.check(_lib.load().adi_batch_set_plan(self._h, ctypes.byref(p)))
+
+    def autotune(self, trial_steps: int = 10, cache: Optional[str] = None) -> float:
+        """Pick the fastest plan (or reuse one cached in the JSON file `cache`)."""
+        import json
+        import os
+        key = None
+        if cache:
+            import hashlib
+            key = hashlib.sha256(repr((self._code, self.sizes)).encode()).hexdigest()[:20]
+            if os.path.exists(cache):
+                try:
+                    ent = json.load(open(cache)).get(key)
+                except Exception:
+                    ent = None
+                if ent:
+                    self.set_plan(ent["x_threads_per_line"], ent["x_grid"], ent["yscan_grid"],
+                                  ent["ysolve_grid"])
+                    return float(ent["ms_per_step"])
+        best = ctypes.c_double(0.0)
+        _lib.check(_lib.load().adi_batch_autotune(self._h, int(trial_steps), ctypes.byref(best)))
+        if cache:
+            p = self.plan()
+            data = {}
+            if os.path.exists(cache):
+                try:
+                    data = json.load(open(cache))
+                except Exception:
+                    data = {}
+            data[key] = {k: p[k] for k in ("x_threads_per_line", "x_grid", "yscan_grid",
+                                           "ysolve_grid")}
+            data[key]["ms_per_step"] = best.value
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            json.dump(data, open(cache, "w"), indent=1)
+        return best.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.load().adi_batch_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -42,6 +42,14 @@ class AdiTuning(ctypes.Structure):
                 ("y_fused", ctypes.c_int), ("y_chunk_rows", ctypes.c_int)]
 
 
+class AdiBatchPlan(ctypes.Structure):
+    _fields_ = [("x_threads_per_line", ctypes.c_int), ("x_grid", ctypes.c_int),
+                ("yscan_grid", ctypes.c_int), ("ysolve_grid", ctypes.c_int),
+                ("graph", ctypes.c_int), ("count", ctypes.c_int), ("nodes", ctypes.c_longlong),
+                ("workspace_bytes", ctypes.c_size_t), ("x_items", ctypes.c_int),
+                ("yscan_items", ctypes.c_int), ("ysolve_items", ctypes.c_int)]
+
+
 _SIGNATURES = {
     "adi_wave_create": [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double,
                         ctypes.c_double, _vp, ctypes.c_double, ctypes.c_int, _vp],
@@ -60,6 +68,19 @@ _SIGNATURES = {
                          ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int)],
     "adi_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "adi_last_error": [],
+    "adi_batch_create": [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp),
+                         ctypes.POINTER(ctypes.c_double), ctypes.c_int, _vp],
+    "adi_batch_bind": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
+    "adi_batch_start": [_vp, ctypes.c_int],
+    "adi_batch_step": [_vp, ctypes.c_int],
+    "adi_batch_levels": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
+    "adi_batch_graph": [_vp, ctypes.c_int],
+    "adi_batch_get_plan": [_vp, ctypes.POINTER(AdiBatchPlan)],
+    "adi_batch_set_plan": [_vp, ctypes.POINTER(AdiBatchPlan)],
+    "adi_batch_autotune": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
+    "adi_batch_destroy": [_vp],
 }
 
 _lib = None

@@ -52,7 +52,7 @@ struct XPlan { int tr, rs, fuse; };
 // x-sweep: smallest line group whose 8 * tr nodes cover nx
 bool choose_x(int nx, adi_dtype, XPlan& p)
 {
-    static const int cand[] = {64, 256, 1024};
+    static const int cand[] = {64, 128, 256, 1024};
     for (int tr : cand)
         if (8LL * tr >= nx) { p.tr = tr; return true; }
     return false;
@@ -125,6 +125,7 @@ bool launch_x(const XPlan& p, int grid, const XArgs<T>& a, hipStream_t st)
 {
     switch (p.tr) {
         case 64: return launch_x_f<T, 64>(p.fuse != 0, grid, a, st);
+        case 128: return launch_x_f<T, 128>(p.fuse != 0, grid, a, st);
         case 256: return launch_x_f<T, 256>(p.fuse != 0, grid, a, st);
         case 1024: return launch_x_f<T, 1024>(p.fuse != 0, grid, a, st);
     }
@@ -583,8 +584,8 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
     if (t->x_rows_per_strip > 0) xp.rs = t->x_rows_per_strip;
     if (t->y_fused == 1) xp.fuse = 1;
     if (t->y_fused == 2) xp.fuse = 0;
-    if (xp.tr != 64 && xp.tr != 256 && xp.tr != 1024)
-        return fail(ADI_EINVAL, "x_threads_per_line must be 64, 256 or 1024");
+    if (xp.tr != 64 && xp.tr != 128 && xp.tr != 256 && xp.tr != 1024)
+        return fail(ADI_EINVAL, "x_threads_per_line must be 64, 128, 256 or 1024");
     if (8LL * xp.tr < w->nx) return fail(ADI_EINVAL, "8 * x_threads_per_line must cover nx");
     if (xp.fuse && !fuse_fits(xp.tr, w->dtype))
         return fail(ADI_EUNSUPPORTED, "fused y-reduction does not fit in LDS for this plan");
@@ -739,3 +740,5 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
 }
 
 }  // extern "C"
+
+#include "batch.hpp"

@@ -219,20 +219,19 @@ __global__ void __launch_bounds__(256) k_ystatic2(YArgs<T> A)
 // workgroup owns one block of kPB columns, P threads per column, SK consecutive
 // chunks per thread.
 template <typename T, int SK, int P>
-__global__ void __launch_bounds__(kPB * P) k_yscan(YArgs<T> A)
+__device__ __forceinline__ void yscan_block(const YArgs<T>& A, const int blk, T* lds)
 {
     constexpr int CB = kPB;
-    __shared__ T lds[partition_lds_slots<P>() * CB];
     const int col = threadIdx.x % CB;
     const int t = threadIdx.x / CB;
-    const int i = blockIdx.x * CB + col;
+    const int i = blk * CB + col;
     const bool live = i < A.nx;
     const int K = A.K;
     const int c0 = t * SK;
     const int L = live ? max(0, min(SK, K - c0)) : 0;
     const int nact = live ? (K + SK - 1) / SK : 0;
     const size_t pl = (size_t)K * A.nxp;
-    const T* __restrict__ base = A.sum + ((size_t)blockIdx.x * K) * kPB + col;
+    const T* __restrict__ base = A.sum + ((size_t)blk * K) * kPB + col;
 
     T a[SK], b[SK], cc[SK], d[SK];
 #pragma unroll
@@ -252,6 +251,13 @@ __global__ void __launch_bounds__(kPB * P) k_yscan(YArgs<T> A)
 #pragma unroll
     for (int k = 0; k < SK; ++k)
         if (k < L) A.X[(size_t)(c0 + k) * A.nx + i] = d[k];
+}
+
+template <typename T, int SK, int P>
+__global__ void __launch_bounds__(kPB * P) k_yscan(YArgs<T> A)
+{
+    __shared__ T lds[partition_lds_slots<P>() * kPB];
+    yscan_block<T, SK, P>(A, blockIdx.x, lds);
 }
 
 // One thread per (column, chunk): the chunk's interior re-solved with X_{c-1}
@@ -320,12 +326,10 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
     }
 }
 
+// column i, chunk c (i < nx)
 template <typename T, int M, int GR>
-__global__ void __launch_bounds__(256) k_ysolve(YArgs<T> A)
+__device__ __forceinline__ void ysolve_item(const YArgs<T>& A, const int i, const int c)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y;
-    if (i >= A.nx) return;
     const size_t nx = (size_t)A.nx;
     const int lo = c * M;
     const int L = min(M, A.ny - lo);
@@ -334,6 +338,13 @@ __global__ void __launch_bounds__(256) k_ysolve(YArgs<T> A)
     const size_t base = (size_t)lo * nx + i;
     if (L == M) ysolve_chunk<T, M, GR, true>(A, base, nx, L, Xp, Xc);
     else ysolve_chunk<T, M, GR, false>(A, base, nx, L, Xp, Xc);
+}
+
+template <typename T, int M, int GR>
+__global__ void __launch_bounds__(256) k_ysolve(YArgs<T> A)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < A.nx) ysolve_item<T, M, GR>(A, i, blockIdx.y);
 }
 
 // traces[r] = out[idx[r]]; an offset outside [0, npts) records NaN

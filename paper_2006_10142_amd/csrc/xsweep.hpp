@@ -237,28 +237,31 @@ __device__ __forceinline__ void store8(T* __restrict__ row, int i0, int nx, bool
 // the y-chunk summary, see k_yreduce) is advanced; the running state lives in
 // LDS.  At each chunk's interface row the planes E and Pf are written and the
 // state restarts.
+// LDS of one line group
 template <typename T, int TR, bool FUSE>
-__global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
+struct XShared {
+    T halo[2][2][TR];                        // segment edges of two rows: [row parity][first/last][seg]
+    T tot[2][TR / 64][2];                    // wavefront scan totals: [fwd/bwd][wave][value]
+    T y[FUSE ? 4 * kSeg * TR : 1];           // fused y-chunk state per column
+};
+
+// One strip (rows_per_strip rows from strip * rows_per_strip) of one line group.
+// Every thread of the workgroup must call this with the same rows_per_strip
+// (it synchronises the workgroup twice per row).
+template <typename T, int TR, bool FUSE>
+__device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip, const int t,
+                                             XShared<T, TR, FUSE>& sh)
 {
     constexpr int E = kSeg;
-    constexpr int NT = TR >= 256 ? TR : 256;
-    constexpr int G = NT / TR;
     constexpr int NW = TR / 64;
-    // segment edge values of two rows in flight: [group][row parity][first/last][segment]
-    __shared__ T s_halo[G][2][2][TR];
-    // per-wavefront scan totals: [group][forward/backward][wave][value]
-    __shared__ T s_tot[G][2][NW][2];
-    // fused y-chunk state per column: q, forward value, running product, first-value sum
-    __shared__ T s_y[FUSE ? G * 4 * E * TR : 1];
-
-    const int g = threadIdx.x / TR;
-    const int t = threadIdx.x - g * TR;
+    auto& s_halo = sh.halo;
+    auto& s_tot = sh.tot;
     const int lane = t & 63;
     const int wv = t >> 6;
     const int nx = A.nx, ny = A.ny, nseg = A.nseg;
     const bool vec = A.vec != 0;
     const int RS = A.rows_per_strip;
-    const int j0 = (blockIdx.x * G + g) * RS;
+    const int j0 = strip * RS;
     const int i0 = E * t;
     const bool act = t < nseg;
     const int L = act ? min(E, nx - i0) : 0;
@@ -290,12 +293,12 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
 #pragma unroll
             for (int e = 1; e < E; ++e)
                 if (e == L - 1) last = v[e];
-            s_halo[g][row & 1][0][t] = v[0];
-            s_halo[g][row & 1][1][t] = last;
+            s_halo[row & 1][0][t] = v[0];
+            s_halo[row & 1][1][t] = last;
         }
     };
 
-    T* ys = FUSE ? s_y + (size_t)g * 4 * E * TR : nullptr;
+    T* ys = sh.y;
     auto ystate_reset = [&]() {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -326,8 +329,8 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
         T rho[E];
         {
             const int p = j & 1;
-            const T west0 = (act && t > 0) ? s_halo[g][p][1][t - 1] : T(0);
-            const T eastL = (t + 1 < nseg) ? s_halo[g][p][0][t + 1] : T(0);
+            const T west0 = (act && t > 0) ? s_halo[p][1][t - 1] : T(0);
+            const T eastL = (t + 1 < nseg) ? s_halo[p][0][t + 1] : T(0);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T uw = (e == 0) ? west0 : uc[e - 1];
@@ -374,15 +377,15 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
         {
             T a = fG, b = fQ;
             wave_scan_fwd(a, b);
-            if (lane == 63) { s_tot[g][0][wv][0] = a; s_tot[g][0][wv][1] = b; }
+            if (lane == 63) { s_tot[0][wv][0] = a; s_tot[0][wv][1] = b; }
             const T xa = dpp<kWaveShr1>(T(0), a);
             const T xb = dpp<kWaveShr1>(T(1), b);
             __syncthreads();
             if (live && j + 2 < ny) put_halo(j + 2, u2);
             T carry = T(0);
             if constexpr (NW > 1) {
-                T ta = (lane < NW) ? s_tot[g][0][lane < NW ? lane : 0][0] : T(0);
-                T tb = (lane < NW) ? s_tot[g][0][lane < NW ? lane : 0][1] : T(1);
+                T ta = (lane < NW) ? s_tot[0][lane < NW ? lane : 0][0] : T(0);
+                T tb = (lane < NW) ? s_tot[0][lane < NW ? lane : 0][1] : T(1);
                 compose_dpp<kRowShr + 1, 0xf>(ta, tb);
                 compose_dpp<kRowShr + 2, 0xf>(ta, tb);
                 compose_dpp<kRowShr + 4, 0xf>(ta, tb);
@@ -398,14 +401,14 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
             T a = fma_rn(Ev, gin, H), b = fQ;
             if (!act) { a = T(0); b = T(1); }
             wave_scan_bwd(a, b, lane);
-            if (lane == 0) { s_tot[g][1][wv][0] = a; s_tot[g][1][wv][1] = b; }
+            if (lane == 0) { s_tot[1][wv][0] = a; s_tot[1][wv][1] = b; }
             const T ya = dpp<kWaveShl1>(T(0), a);
             const T yb = dpp<kWaveShl1>(T(1), b);
             __syncthreads();
             T carry = T(0);
             if constexpr (NW > 1) {
-                T ta = (lane < NW) ? s_tot[g][1][lane < NW ? lane : 0][0] : T(0);
-                T tb = (lane < NW) ? s_tot[g][1][lane < NW ? lane : 0][1] : T(1);
+                T ta = (lane < NW) ? s_tot[1][lane < NW ? lane : 0][0] : T(0);
+                T tb = (lane < NW) ? s_tot[1][lane < NW ? lane : 0][1] : T(1);
                 compose_dpp<kRowShl + 1, 0xf>(ta, tb);
                 compose_dpp<kRowShl + 2, 0xf>(ta, tb);
                 compose_dpp<kRowShl + 4, 0xf>(ta, tb);
@@ -471,6 +474,15 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
             um[e] = uc[e]; uc[e] = u1[e]; u1[e] = u2[e]; rc[e] = rn[e];
         }
     }
+}
+
+template <typename T, int TR, bool FUSE>
+__global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
+{
+    constexpr int G = (TR >= 256 ? TR : 256) / TR;
+    __shared__ XShared<T, TR, FUSE> sh[G];
+    const int g = threadIdx.x / TR;
+    xsweep_strip<T, TR, FUSE>(A, blockIdx.x * G + g, threadIdx.x - g * TR, sh[g]);
 }
 
 }  // namespace adw

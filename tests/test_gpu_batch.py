@@ -1,0 +1,140 @@
+"""Batched simulations (many uneven grids in one launch per kernel) against the
+FP64 oracle, and the graph / persistent-grid / autotuned plans against the
+direct plan (bitwise: they change scheduling only)."""
+import numpy as np
+import pytest
+
+from tests.conftest import rel_l2
+from paper_2006_10142_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def adw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2006_10142_amd as m
+    m._lib.load()
+    return m
+
+
+def tdt(d):
+    return torch.float32 if d == "f32" else torch.float64
+
+
+def npdt(d):
+    return np.float32 if d == "f32" else np.float64
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+SIZES = [(64, 64), (100, 37), (1, 9), (9, 1), (256, 256), (300, 211), (1000, 50), (33, 517)]
+
+
+def make_batch(dtype, sizes=SIZES, seed=0):
+    sims = []
+    for s, (nx, ny) in enumerate(sizes):
+        h = 1.0 / (max(nx, ny) + 1)
+        c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=100 + s + seed).astype(npdt(dtype))
+        dt = 0.45 * h / float(c.max())
+        u0 = wl.gaussian_pulse(nx, ny, sigma=0.1).astype(npdt(dtype))
+        sims.append(dict(nx=nx, ny=ny, h=h, dt=dt, c=c, u0=u0))
+    return sims
+
+
+def run_batch(adw, sims, dtype, nsteps, graph=False, plan=None, autotune=False):
+    t = tdt(dtype)
+    b = adw.Batch([(s["nx"], s["ny"]) for s in sims], [s["h"] for s in sims],
+                  [s["dt"] for s in sims], [torch.from_numpy(s["c"]).cuda() for s in sims], dtype=t)
+    if plan:
+        b.set_plan(**plan)
+    if autotune:
+        b.autotune(trial_steps=3)
+    u0 = [torch.from_numpy(s["u0"]).cuda() for s in sims]
+    u1 = [torch.zeros_like(x) for x in u0]
+    b.bind(u0, u1)
+    b.start("ghost")
+    if graph:
+        b.graph(True)
+    b.step(nsteps)
+    prev, curr = b.levels()
+    torch.cuda.synchronize()
+    out = [x.cpu().numpy() for x in curr]
+    info = b.plan()
+    b.close()
+    return out, info
+
+
+def oracle_run(oracle_lib, s, nsteps):
+    kap = s["c"].astype(np.float64) ** 2
+    u1 = oracle_lib.start(kap, s["u0"], s["h"], s["dt"])
+    _, ref, _ = oracle_lib.run(kap, s["u0"], u1, s["h"], s["dt"], nsteps)
+    return ref
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_matches_oracle(adw, oracle_lib, dtype):
+    sims = make_batch(dtype)
+    say(f"batch {dtype} {len(sims)} sims, 25 steps")
+    got, info = run_batch(adw, sims, dtype, 25)
+    assert info["count"] == len(sims)
+    for s, g in zip(sims, got):
+        assert rel_l2(g, oracle_run(oracle_lib, s, 25)) <= TOL[dtype], (s["nx"], s["ny"])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_graph_and_grids_are_bitwise_equal(adw, dtype):
+    sims = make_batch(dtype, seed=7)
+    say(f"batch graph/grids {dtype}")
+    base, _ = run_batch(adw, sims, dtype, 9)
+    with_graph, info = run_batch(adw, sims, dtype, 9, graph=True)
+    assert info["graph"] == 1
+    persistent, _ = run_batch(adw, sims, dtype, 9, plan=dict(x_grid=5, yscan_grid=3, ysolve_grid=11))
+    for a, b, c in zip(base, with_graph, persistent):
+        assert np.array_equal(a, b)
+        assert np.array_equal(a, c)
+
+
+def test_batch_autotune_keeps_results(adw, oracle_lib):
+    sims = make_batch("f64", sizes=[(128, 96), (511, 64), (77, 300)], seed=3)
+    say("batch autotune")
+    got, info = run_batch(adw, sims, "f64", 12, autotune=True, graph=True)
+    for s, g in zip(sims, got):
+        assert rel_l2(g, oracle_run(oracle_lib, s, 12)) <= TOL["f64"]
+
+
+def test_batch_c4_sample(adw, oracle_lib):
+    """Eight simulations drawn by C4's recipe (N in 256..1024, FP32), 40 steps, graph replay."""
+    probs = wl.config_c4(dtype="f32", nsteps=40, count=8)
+    sims = [dict(nx=p.nx, ny=p.ny, h=p.h, dt=p.dt, c=p.c, u0=p.u0) for p in probs]
+    say("batch C4 sample")
+    got, _ = run_batch(adw, sims, "f32", 40, graph=True)
+    for s, g in zip(sims, got):
+        assert rel_l2(g, oracle_run(oracle_lib, s, 40)) <= TOL["f32"]
+
+
+def test_batch_levels_rotate_and_errors(adw):
+    sims = make_batch("f32", sizes=[(40, 30), (20, 50)])
+    b = adw.Batch([(s["nx"], s["ny"]) for s in sims], [s["h"] for s in sims],
+                  [s["dt"] for s in sims], [1.5, 2.0], dtype=torch.float32)
+    u0 = [torch.from_numpy(s["u0"]).cuda() for s in sims]
+    u1 = [torch.zeros_like(x) for x in u0]
+    with pytest.raises(adw.AdiError):
+        b.step(1)                                   # not bound yet
+    b.bind(u0, u1)
+    b.start("paper")
+    b.step(3)
+    prev, curr = b.levels()
+    assert all(c is a for c, a in zip(curr, u0))    # odd count: roles swapped
+    b.step(1)
+    prev, curr = b.levels()
+    assert all(c is a for c, a in zip(curr, u1))
+    with pytest.raises(adw.AdiError):
+        b.start("ghost")                            # only before the first step
+    b.close()
