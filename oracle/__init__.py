@@ -13,9 +13,12 @@ Parity status of each function (what pins it; see tests/test_oracle_pins.py):
                               the discrete energy invariant; x<->y symmetry.
   start                    -- PAPER mode: eq. (CN2) verbatim; GHOST mode: the
                               discrete standing-wave closed form from step 0.
+  adjoint                  -- central finite differences of the forward loss on
+                              random cells; the source-to-trace dot-product
+                              identity <F f, d> = <f, F^T d>.
 """
 from .oracle import (build, lib, max_threads, thomas, tridiag_batched, step_parts, run,
-                     start, initial_levels, run_problem)
+                     start, initial_levels, run_problem, adjoint)
 
 __all__ = ["build", "lib", "max_threads", "thomas", "tridiag_batched", "step_parts", "run",
-           "start", "initial_levels", "run_problem"]
+           "start", "initial_levels", "run_problem", "adjoint"]

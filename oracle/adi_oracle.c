@@ -323,3 +323,146 @@ int oracle_adi_start(int nx, int ny, double h, double dt, const double *kappa,
     free(tmp);
     return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint of oracle_adi_run (not in the paper; derived from the
+ * scheme above).  With A_x = I - beta K Lxx, A_y = I - beta K Lyy, one step is
+ *   u^{k+1} = 2u^k - u^{k-1} + A_y^{-1} A_x^{-1} dt^2 (K Lap u^k + f^k),
+ * and the traces are tr_{k-1} = P u^{k+1} (P samples the receiver nodes).
+ * For a scalar J of the traces with g^m = P^T dJ/dtr_{m-2}, the adjoint
+ * levels lambda^m = dJ/du^m obey, backwards from lambda^{S+2} = 0:
+ *   nu      = A_y^{-T} lambda^{k+1}       (transposed y-line solves)
+ *   mu      = A_x^{-T} nu                 (transposed x-line solves)
+ *   dJ/dkappa += dt^2 mu (Lap u^k) + beta mu (Lxx w^k) + beta nu (Lyy d^k)
+ *   dJ/df^k    = dt^2 mu                  (at the source nodes)
+ *   lambda^k = g^k + 2 lambda^{k+1} - lambda^{k+2} + dt^2 Lap(kappa mu)
+ * where w^k, d^k are the forward intermediates of step k.  The initial levels
+ * are taken as independent of kappa.  The transposed line systems are solved
+ * by Thomas on the transposed coefficients (row i: -r_{i-1}, 1 + 2 r_i,
+ * -r_{i+1}).  Everything is kept in memory: meant for small grids.
+ * ------------------------------------------------------------------------ */
+static void apply_lap(int nx, int ny, double h, const double *v, double *out)
+{
+    const double inv_h2 = 1.0 / (h * h);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t p = (size_t)j * nx + i;
+            double c = v[p];
+            double w_ = i > 0 ? v[p - 1] : 0.0, e_ = i < nx - 1 ? v[p + 1] : 0.0;
+            double s_ = j > 0 ? v[p - nx] : 0.0, n_ = j < ny - 1 ? v[p + nx] : 0.0;
+            out[p] = (w_ - 2.0 * c + e_) * inv_h2 + (s_ - 2.0 * c + n_) * inv_h2;
+        }
+}
+
+static void apply_lxx(int nx, int ny, double h, const double *v, double *out)
+{
+    const double inv_h2 = 1.0 / (h * h);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t p = (size_t)j * nx + i;
+            double w_ = i > 0 ? v[p - 1] : 0.0, e_ = i < nx - 1 ? v[p + 1] : 0.0;
+            out[p] = (w_ - 2.0 * v[p] + e_) * inv_h2;
+        }
+}
+
+static void apply_lyy(int nx, int ny, double h, const double *v, double *out)
+{
+    const double inv_h2 = 1.0 / (h * h);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t p = (size_t)j * nx + i;
+            double s_ = j > 0 ? v[p - nx] : 0.0, n_ = j < ny - 1 ? v[p + nx] : 0.0;
+            out[p] = (s_ - 2.0 * v[p] + n_) * inv_h2;
+        }
+}
+
+/* transposed line solves: along x (rows) or y (columns) */
+static int transposed_solves(int nx, int ny, double h, double dt, const double *kappa,
+                             int along_y, const double *rhs, double *out)
+{
+    const double s = 0.5 * dt * dt / (h * h);
+    const int n = along_y ? ny : nx, lines = along_y ? nx : ny;
+    double *buf = malloc(sizeof(double) * 6 * (size_t)n);
+    if (!buf) return ORACLE_ENOMEM;
+    double *la = buf, *lb = buf + n, *lc = buf + 2 * n, *ld = buf + 3 * n;
+    double *cp = buf + 4 * n, *dp = buf + 5 * n;
+    for (int l = 0; l < lines; ++l) {
+        for (int k = 0; k < n; ++k) {
+            size_t p = along_y ? (size_t)k * nx + l : (size_t)l * nx + k;
+            size_t pm = along_y ? p - nx : p - 1, pp = along_y ? p + nx : p + 1;
+            la[k] = k > 0 ? -s * kappa[pm] : 0.0;
+            lb[k] = 1.0 + 2.0 * s * kappa[p];
+            lc[k] = k < n - 1 ? -s * kappa[pp] : 0.0;
+            ld[k] = rhs[p];
+        }
+        thomas(n, la, lb, lc, ld, ld, cp, dp);
+        for (int k = 0; k < n; ++k) {
+            size_t p = along_y ? (size_t)k * nx + l : (size_t)l * nx + k;
+            out[p] = ld[k];
+        }
+    }
+    free(buf);
+    return ORACLE_OK;
+}
+
+int oracle_adjoint(int nx, int ny, double h, double dt, const double *kappa,
+                   const double *u_prev0, const double *u_curr0,
+                   int nsrc, const int *src_idx, const double *src_amp,
+                   int nrec, const int *rec_idx, const double *grad_traces,
+                   int nsteps, double *grad_kappa, double *grad_amp, int nthreads)
+{
+    if (check_grid(nx, ny, h, dt) || nsteps < 1 || nsrc < 0 || nrec < 0) return ORACLE_EINVAL;
+    set_threads(nthreads);
+    const size_t npts = (size_t)nx * ny;
+    const double beta = 0.5 * dt * dt;
+    const int S = nsteps;
+    /* forward: levels U[0..S+1], x-sweep results W[1..S], increments D[1..S] */
+    double *U = malloc(sizeof(double) * (size_t)(S + 2) * npts);
+    double *W = malloc(sizeof(double) * (size_t)(S + 1) * npts);
+    double *D = malloc(sizeof(double) * (size_t)(S + 1) * npts);
+    double *tmp = malloc(sizeof(double) * 8 * npts);
+    if (!U || !W || !D || !tmp) { free(U); free(W); free(D); free(tmp); return ORACLE_ENOMEM; }
+    double *f = tmp, *rho = tmp + npts, *lam1 = tmp + 2 * npts, *lam2 = tmp + 3 * npts;
+    double *nu = tmp + 4 * npts, *mu = tmp + 5 * npts, *a1 = tmp + 6 * npts, *a2 = tmp + 7 * npts;
+    memcpy(U, u_prev0, sizeof(double) * npts);
+    memcpy(U + npts, u_curr0, sizeof(double) * npts);
+    int rc = ORACLE_OK;
+    for (int k = 1; k <= S && rc == ORACLE_OK; ++k) {
+        const double *fk = NULL;
+        if (nsrc > 0) { scatter_sources(npts, f, nsrc, src_idx, src_amp + (size_t)(k - 1) * nsrc); fk = f; }
+        assemble_rhs(nx, ny, h, dt, kappa, U + (size_t)k * npts, fk, rho);
+        rc = adi_solves(nx, ny, h, dt, kappa, rho, W + (size_t)k * npts, D + (size_t)k * npts);
+        for (size_t p = 0; p < npts; ++p)
+            U[(size_t)(k + 1) * npts + p] = 2.0 * U[(size_t)k * npts + p] - U[(size_t)(k - 1) * npts + p] +
+                                           D[(size_t)k * npts + p];
+    }
+    /* reverse */
+    memset(grad_kappa, 0, sizeof(double) * npts);
+    memset(lam2, 0, sizeof(double) * npts);             /* lambda^{k+2} */
+    memset(lam1, 0, sizeof(double) * npts);             /* lambda^{k+1} */
+    for (int r = 0; r < nrec; ++r) lam1[rec_idx[r]] += grad_traces[(size_t)(S - 1) * nrec + r];
+    for (int k = S; k >= 1 && rc == ORACLE_OK; --k) {
+        rc = transposed_solves(nx, ny, h, dt, kappa, 1, lam1, nu);
+        if (rc == ORACLE_OK) rc = transposed_solves(nx, ny, h, dt, kappa, 0, nu, mu);
+        if (rc != ORACLE_OK) break;
+        apply_lap(nx, ny, h, U + (size_t)k * npts, a1);
+        for (size_t p = 0; p < npts; ++p) grad_kappa[p] += dt * dt * mu[p] * a1[p];
+        apply_lxx(nx, ny, h, W + (size_t)k * npts, a1);
+        apply_lyy(nx, ny, h, D + (size_t)k * npts, a2);
+        for (size_t p = 0; p < npts; ++p) grad_kappa[p] += beta * (mu[p] * a1[p] + nu[p] * a2[p]);
+        if (grad_amp)
+            for (int s = 0; s < nsrc; ++s) grad_amp[(size_t)(k - 1) * nsrc + s] = dt * dt * mu[src_idx[s]];
+        /* lambda^k = g^k + 2 lambda^{k+1} - lambda^{k+2} + dt^2 Lap(kappa mu) */
+        for (size_t p = 0; p < npts; ++p) a2[p] = kappa[p] * mu[p];
+        apply_lap(nx, ny, h, a2, a1);
+        for (size_t p = 0; p < npts; ++p) {
+            double lk = 2.0 * lam1[p] - lam2[p] + dt * dt * a1[p];
+            lam2[p] = lam1[p];
+            lam1[p] = lk;
+        }
+        if (k >= 2)
+            for (int r = 0; r < nrec; ++r) lam1[rec_idx[r]] += grad_traces[(size_t)(k - 2) * nrec + r];
+    }
+    free(U); free(W); free(D); free(tmp);
+    return rc;
+}

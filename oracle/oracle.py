@@ -55,9 +55,12 @@ def lib():
         l.oracle_adi_start.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double, _dp, _dp, _dp, ctypes.c_int, _ip,
                                        _dp, ctypes.c_int, _dp, ctypes.c_int]
+        l.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     _dp, _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.c_int, _ip,
+                                     _dp, ctypes.c_int, _dp, _dp, ctypes.c_int]
         l.oracle_max_threads.argtypes = []
         for f in (l.oracle_thomas, l.oracle_tridiag_batched, l.oracle_adi_step_parts,
-                  l.oracle_adi_run, l.oracle_adi_start, l.oracle_max_threads):
+                  l.oracle_adi_run, l.oracle_adi_start, l.oracle_max_threads, l.oracle_adjoint):
             f.restype = ctypes.c_int
         _lib = l
     return _lib
@@ -181,3 +184,24 @@ def run_problem(prob, nsteps: Optional[int] = None, threads: int = 0):
     return run(prob.kappa_field(), up, uc, prob.h, prob.dt, nsteps,
                src_idx=prob.src_idx if prob.src_idx.size else None, src_amp=amp,
                rec_idx=prob.rec_idx if prob.rec_idx.size else None, threads=threads)
+
+
+def adjoint(kappa, u_prev, u_curr, h: float, dt: float, nsteps: int, grad_traces,
+            rec_idx, src_idx=None, src_amp=None, threads: int = 0):
+    """Reverse pass of `run`: given dJ/d(traces) (nsteps x nrec), returns
+    (dJ/dkappa (ny, nx), dJ/d(source values) (nsteps, nsrc) or None)."""
+    up, uc = _f64(u_prev), _f64(u_curr)
+    ny, nx = uc.shape
+    k = _kappa(kappa, nx, ny)
+    nsrc = 0 if src_idx is None else int(np.asarray(src_idx).size)
+    si = None if nsrc == 0 else np.ascontiguousarray(np.asarray(src_idx, dtype=np.int32))
+    sa = None if nsrc == 0 else _f64(src_amp).reshape(-1)
+    ri = np.ascontiguousarray(np.asarray(rec_idx, dtype=np.int32))
+    gt = _f64(grad_traces).reshape(-1)
+    assert gt.size == nsteps * ri.size
+    gk = np.zeros((ny, nx))
+    ga = None if nsrc == 0 else np.zeros((nsteps, nsrc))
+    _check(lib().oracle_adjoint(nx, ny, h, dt, _ptr(k), _ptr(up), _ptr(uc), nsrc, _iptr(si),
+                                _ptr(sa), int(ri.size), _iptr(ri), _ptr(gt), nsteps, _ptr(gk),
+                                _ptr(ga), threads), "adjoint")
+    return gk, ga

@@ -306,3 +306,61 @@ def test_point_source_and_receivers(oracle_lib):
         assert rel_l2(tr[k], b[rec_idx]) < 1e-13
     assert rel_l2(uc.ravel(), b) < 1e-13
     assert rel_l2(up.ravel(), a) < 1e-13
+
+
+# ------------------------------------------------------------------ adjoint ----
+def _adjoint_case(seed=4, nx=14, ny=11, nsteps=30, nonzero_start=False):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / 15.0
+    dt = 0.6 * h
+    kappa = rng.uniform(1.0, 4.0, (ny, nx))
+    if nonzero_start:
+        up = 0.1 * rng.standard_normal((ny, nx))
+        uc = up + 0.01 * rng.standard_normal((ny, nx))
+    else:
+        up = np.zeros((ny, nx))
+        uc = np.zeros((ny, nx))
+    src_idx = np.array([5 * nx + 6, 2 * nx + 9], np.int32)
+    amp = rng.standard_normal((nsteps, 2)) * 50.0
+    rec_idx = np.array([1 * nx + 2, 1 * nx + 7, 9 * nx + 3, 6 * nx + 12], np.int32)
+    target = rng.standard_normal((nsteps, 4)) * 1e-3
+    return h, dt, kappa, up, uc, src_idx, amp, rec_idx, target
+
+
+def _misfit(oracle_lib, kappa, case):
+    h, dt, _, up, uc, si, amp, ri, target = case
+    _, _, tr = oracle_lib.run(kappa, up, uc, h, dt, amp.shape[0], src_idx=si, src_amp=amp, rec_idx=ri)
+    return float(np.sum((tr - target) ** 2)), tr
+
+
+@pytest.mark.parametrize("nonzero_start", [False, True])
+def test_adjoint_gradient_matches_finite_differences(oracle_lib, nonzero_start):
+    """dJ/dkappa from the reverse pass against central differences of J (FP64)."""
+    case = _adjoint_case(nonzero_start=nonzero_start)
+    h, dt, kappa, up, uc, si, amp, ri, target = case
+    J0, tr = _misfit(oracle_lib, kappa, case)
+    gk, _ = oracle_lib.adjoint(kappa, up, uc, h, dt, amp.shape[0], 2.0 * (tr - target), ri,
+                               src_idx=si, src_amp=amp)
+    rng = np.random.default_rng(9)
+    cells = [(int(rng.integers(0, kappa.shape[0])), int(rng.integers(0, kappa.shape[1])))
+             for _ in range(10)]
+    cells.append((5, 6))                      # at a source
+    for (j, i) in cells:
+        eps = 1e-5 * kappa[j, i]
+        kp = kappa.copy(); kp[j, i] += eps
+        km = kappa.copy(); km[j, i] -= eps
+        fd = (_misfit(oracle_lib, kp, case)[0] - _misfit(oracle_lib, km, case)[0]) / (2 * eps)
+        assert abs(fd - gk[j, i]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(gk).max()), (j, i, fd, gk[j, i])
+
+
+def test_adjoint_dot_product_identity(oracle_lib):
+    """<F f, d> = <f, F^T d> for the linear map source values -> traces (zero start)."""
+    case = _adjoint_case(seed=12)
+    h, dt, kappa, up, uc, si, amp, ri, _ = case
+    rng = np.random.default_rng(13)
+    d = rng.standard_normal((amp.shape[0], ri.size))
+    _, _, Ff = oracle_lib.run(kappa, up, uc, h, dt, amp.shape[0], src_idx=si, src_amp=amp, rec_idx=ri)
+    _, Ftd = oracle_lib.adjoint(kappa, up, uc, h, dt, amp.shape[0], d, ri, src_idx=si, src_amp=amp)
+    lhs = float(np.sum(Ff * d))
+    rhs = float(np.sum(amp * Ftd))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300)
