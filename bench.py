@@ -46,7 +46,7 @@ WORKLOADS = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp", "xsweep.hpp", "batch.hpp"):
+    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp", "xsweep.hpp", "batch.hpp", "adjoint.hpp"):
         with open(os.path.join(ROOT, "paper_2006_10142_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -127,6 +127,35 @@ adi_status adi_wave_step(adi_wave_t w, void** u_prev, void** u_curr,
 /* Free the handle and its workspace (synchronises the handle's stream). */
 adi_status adi_wave_destroy(adi_wave_t w);
 
+/* ----------------------------------------------------------------- adjoint -- */
+
+/* Gradients of a scalar function J of the receiver traces with respect to
+ * the per-node coefficient kappa (and the source values), by the discrete
+ * adjoint of the step above run backwards in time (not in the paper).
+ * With lambda^m = dJ/du^m, A_x = I - beta K Lxx, A_y = I - beta K Lyy:
+ *   nu = A_y^{-T} lambda^{k+1}, mu = A_x^{-T} nu,
+ *   dJ/dkappa += dt^2 mu Lap(u^k) + beta (mu Lxx w^k + nu Lyy d^k),
+ *   dJ/df^k = dt^2 mu at the source nodes,
+ *   lambda^k = g^k + 2 lambda^{k+1} - lambda^{k+2} + dt^2 Lap(kappa mu).
+ * The initial levels are treated as independent of kappa. */
+
+/* Forward run of nsteps steps from (u_prev, u_curr) (not modified) with
+ * sources and receivers exactly as adi_wave_step, keeping the level pair every
+ * checkpoint_every steps in handle-owned device memory (allocated here on
+ * first use or growth: 2 * ceil(nsteps / checkpoint_every) + 6 fields). */
+adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_curr,
+                               const adi_source* f, const adi_receivers* rec, int nsteps,
+                               int checkpoint_every);
+
+/* Reverse pass of the last adi_adjoint_forward (same f and rec).
+ * grad_traces: device, nsteps x rec->count values of dJ/d(trace).
+ * grad_kappa: device nx*ny, overwritten with dJ/dkappa.
+ * grad_amp: device nsteps x f->count, overwritten with dJ/d(source value),
+ * or NULL.  Each segment between checkpoints is recomputed once (allocates
+ * 2 * checkpoint_every fields on first use or growth). */
+adi_status adi_adjoint_backward(adi_wave_t w, const adi_source* f, const adi_receivers* rec,
+                                const void* grad_traces, void* grad_kappa, void* grad_amp);
+
 /* ------------------------------------------------------ batched simulations -- */
 
 /* Many independent simulations of uneven grid sizes advanced together: each

@@ -18,7 +18,8 @@ from typing import Optional, Tuple
 from . import _lib
 from ._lib import AdiError
 
-__all__ = ["Wave", "Batch", "tridiag_solve_batched", "stream_copy", "AdiError", "lib_path"]
+__all__ = ["Wave", "Batch", "ADIWaveFunction", "simulate_traces", "tridiag_solve_batched",
+           "stream_copy", "AdiError", "lib_path"]
 
 lib_path = _lib.LIB_PATH
 
@@ -180,6 +181,52 @@ class Wave:
         levels = (u_prev, u_curr) if pb.value == b.value else (u_curr, u_prev)
         return levels, out
 
+    def _receivers(self, rec_idx, traces, nsteps):
+        if rec_idx is None or rec_idx.numel() == 0:
+            return None
+        _index(rec_idx, "rec_idx")
+        if traces is None or traces.dtype != self.dtype or not traces.is_contiguous() \
+                or traces.numel() < nsteps * rec_idx.numel():
+            raise ValueError("traces must be a contiguous (nsteps, count) tensor of the handle dtype")
+        return _lib.AdiReceivers(rec_idx.numel(), rec_idx.data_ptr(), traces.data_ptr())
+
+    def adjoint_forward(self, u_prev, u_curr, nsteps: int, src_idx=None, src_amp=None,
+                        rec_idx=None, checkpoint_every: int = 100):
+        """Forward run keeping checkpoints for adjoint_backward; returns the traces
+        (nsteps, nrec) (u_prev and u_curr are not modified)."""
+        torch = _torch()
+        self._sync_stream()
+        a = _field(u_prev, self.dtype, self._shape(), "u_prev")
+        b = _field(u_curr, self.dtype, self._shape(), "u_curr")
+        src = self._sources(src_idx, src_amp, nsteps)
+        nrec = 0 if rec_idx is None else rec_idx.numel()
+        traces = torch.zeros((nsteps, nrec), dtype=self.dtype, device=u_curr.device)
+        rec = self._receivers(rec_idx, traces, nsteps)
+        _lib.check(_lib.load().adi_adjoint_forward(self._h, a, b, ctypes.byref(src) if src else None,
+                                                   ctypes.byref(rec) if rec else None, int(nsteps),
+                                                   int(checkpoint_every)))
+        self._adj_steps = int(nsteps)
+        return traces
+
+    def adjoint_backward(self, grad_traces, src_idx=None, src_amp=None, rec_idx=None,
+                         want_amp: bool = False):
+        """Reverse pass of the last adjoint_forward: returns (dJ/dkappa, dJ/d source values or None)."""
+        torch = _torch()
+        self._sync_stream()
+        nsteps = self._adj_steps
+        src = self._sources(src_idx, src_amp, nsteps)
+        gt = grad_traces.contiguous().to(self.dtype)
+        rec = self._receivers(rec_idx, gt, nsteps)
+        gk = torch.empty(self._shape(), dtype=self.dtype, device=gt.device)
+        ga = None
+        if want_amp and src is not None:
+            ga = torch.zeros((nsteps, src_idx.numel()), dtype=self.dtype, device=gt.device)
+        _lib.check(_lib.load().adi_adjoint_backward(
+            self._h, ctypes.byref(src) if src else None, ctypes.byref(rec) if rec else None,
+            ctypes.c_void_p(gt.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
+            None if ga is None else ctypes.c_void_p(ga.data_ptr())))
+        return gk, ga
+
     def info(self) -> dict:
         inf = _lib.AdiWaveInfo()
         _lib.check(_lib.load().adi_wave_get_info(self._h, ctypes.byref(inf)))
@@ -332,6 +379,56 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class ADIWaveFunction:
+    """torch.autograd.Function: traces = ADIWaveFunction.apply(kappa, src_amp, wave, u_prev,
+    u_curr, nsteps, src_idx, rec_idx, checkpoint_every).
+
+    Forward: set the handle's coefficient to kappa, run nsteps steps with
+    checkpoints, return the receiver traces (nsteps, nrec).  Backward: the
+    adjoint reverse pass gives dJ/dkappa (and dJ/d src_amp).  One forward per
+    handle may be pending a backward at a time.
+    """
+    _fn = None
+
+    @classmethod
+    def apply(cls, *args):
+        return cls._function().apply(*args)
+
+    @classmethod
+    def _function(cls):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, kappa, src_amp, wave, u_prev, u_curr, nsteps, src_idx, rec_idx,
+                            checkpoint_every):
+                    wave.set_kappa(kappa.detach().contiguous())
+                    amp = None if src_amp is None else src_amp.detach().contiguous()
+                    tr = wave.adjoint_forward(u_prev, u_curr, nsteps, src_idx=src_idx, src_amp=amp,
+                                              rec_idx=rec_idx, checkpoint_every=checkpoint_every)
+                    ctx.wave, ctx.src_idx, ctx.rec_idx, ctx.amp = wave, src_idx, rec_idx, amp
+                    return tr
+
+                @staticmethod
+                def backward(ctx, grad_traces):
+                    want_amp = ctx.amp is not None and ctx.needs_input_grad[1]
+                    gk, ga = ctx.wave.adjoint_backward(grad_traces, src_idx=ctx.src_idx,
+                                                       src_amp=ctx.amp, rec_idx=ctx.rec_idx,
+                                                       want_amp=want_amp)
+                    return gk, ga, None, None, None, None, None, None, None
+
+            cls._fn = _F
+        return cls._fn
+
+
+def simulate_traces(wave, kappa, u_prev, u_curr, nsteps, src_idx, src_amp, rec_idx,
+                    checkpoint_every: int = 100):
+    """Differentiable receiver traces of a run (see ADIWaveFunction)."""
+    return ADIWaveFunction.apply(kappa, src_amp, wave, u_prev, u_curr, nsteps, src_idx, rec_idx,
+                                 checkpoint_every)
 
 
 def tridiag_solve_batched(a, b, c, d, n: int, batch: int, sys_stride: int, elem_stride: int = 1):

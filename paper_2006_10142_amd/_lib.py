@@ -81,6 +81,10 @@ _SIGNATURES = {
     "adi_batch_set_plan": [_vp, ctypes.POINTER(AdiBatchPlan)],
     "adi_batch_autotune": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
     "adi_batch_destroy": [_vp],
+    "adi_adjoint_forward": [_vp, _vp, _vp, ctypes.POINTER(AdiSource), ctypes.POINTER(AdiReceivers),
+                            ctypes.c_int, ctypes.c_int],
+    "adi_adjoint_backward": [_vp, ctypes.POINTER(AdiSource), ctypes.POINTER(AdiReceivers), _vp, _vp,
+                             _vp],
 }
 
 _lib = None

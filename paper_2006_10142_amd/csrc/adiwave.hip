@@ -202,6 +202,8 @@ bool launch_tri(const TPlan& p, long long batch, const TriArgs<T>& a, hipStream_
 }  // namespace
 
 // --------------------------------------------------------------- handle ----
+struct adi_adjoint_s;   // adjoint checkpoint and work storage (adjoint.hpp)
+
 struct adi_wave_s {
     int nx = 0, ny = 0;
     double h = 0, dt = 0;
@@ -220,9 +222,12 @@ struct adi_wave_s {
     int M = 32, K = 0;
     YScanPlan yq{};
     size_t bytes = 0;
+    adi_adjoint_s* adj = nullptr;   // created by the first adjoint forward run
 };
 
 namespace {
+
+void adjoint_free(adi_adjoint_s* a);   // adjoint.hpp
 
 void free_ws(adi_wave_s* w)
 {
@@ -554,6 +559,7 @@ adi_status adi_wave_destroy(adi_wave_t w)
     if (!w) return ADI_OK;
     (void)hipStreamSynchronize(w->stream);
     free_ws(w);
+    adjoint_free(w->adj);
     delete w;
     return ADI_OK;
 }
@@ -742,3 +748,4 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
 }  // extern "C"
 
 #include "batch.hpp"
+#include "adjoint.hpp"

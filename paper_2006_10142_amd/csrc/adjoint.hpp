@@ -1,0 +1,334 @@
+// adjoint.hpp -- reverse-time adjoint of the ADI run: gradients of a function
+// of the receiver traces with respect to the per-node coefficient kappa (and
+// the source values).  Included at the end of adiwave.hip.
+//
+// With A_x = I - beta K Lxx, A_y = I - beta K Lyy and lambda^m = dJ/du^m, step
+// k (u^{k-1}, u^k -> u^{k+1}) contributes, backwards in time,
+//   nu = A_y^{-T} lambda^{k+1},  mu = A_x^{-T} nu,
+//   dJ/dkappa += dt^2 mu Lap(u^k) + beta (mu Lxx w^k + nu Lyy d^k),
+//   lambda^k = g^k + 2 lambda^{k+1} - lambda^{k+2} + dt^2 Lap(kappa mu),
+// with g^m the direct derivative through the traces of level m.
+// A_x = K (K^{-1} - beta Lxx) with a symmetric second factor, hence
+//   A_x^{-T} v = R^{-1} A_x^{-1} (R v),   R = diag(r), r = beta kappa / h^2,
+// and likewise for A_y: the transposed solves are the forward line solves in
+// the other order (y first, then x) on R lambda, divided by r afterwards:
+//   z = A_y^{-1} (R lambda^{k+1}),  t = A_x^{-1} z,  nu = z / r,  mu = t / r,
+// and dt^2 Lap(kappa mu) = 2 (5-point sum of t - 4 t).  d^k is recovered from
+// the stored levels as u^{k+1} - 2u^k + u^{k-1}; w^k is stored by the
+// recomputation.  Levels are checkpointed every K steps by the forward run;
+// each segment is recomputed once, in reverse segment order.
+
+namespace adw {
+
+template <typename T>
+struct AdjArgs {
+    const T* t;      // A_x^{-1} z
+    const T* z;      // A_y^{-1} (r lambda^{k+1})
+    const T* r;
+    const T* lam1;   // lambda^{k+1}
+    T* lam2;         // in: lambda^{k+2}; out: lambda^k (without g^k)
+    const T* um;     // u^{k-1}
+    const T* uk;     // u^k
+    const T* up;     // u^{k+1}
+    const T* wk;     // w^k
+    T* grad;         // dJ/dkappa, accumulated
+    int nx, ny;
+    T c1, c2;        // dt^2 / h^2, beta / h^2
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adjoint_update(AdjArgs<T> A)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= A.nx || j >= A.ny) return;
+    const int nx = A.nx, ny = A.ny;
+    const size_t p = (size_t)j * nx + i;
+    auto at = [&](const T* a, int ii, int jj) -> T {
+        return (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? a[(size_t)jj * nx + ii] : T(0);
+    };
+    auto dlt = [&](int jj) -> T {   // d^k at (i, jj)
+        return (jj >= 0 && jj < ny) ? (at(A.up, i, jj) - T(2) * at(A.uk, i, jj)) + at(A.um, i, jj) : T(0);
+    };
+    const T tc = A.t[p];
+    const T s5t = ((at(A.t, i - 1, j) + at(A.t, i + 1, j)) + (at(A.t, i, j - 1) + at(A.t, i, j + 1))) - T(4) * tc;
+    const T uc = A.uk[p];
+    const T s5u = ((at(A.uk, i - 1, j) + at(A.uk, i + 1, j)) + (at(A.uk, i, j - 1) + at(A.uk, i, j + 1))) - T(4) * uc;
+    const T sxw = (at(A.wk, i - 1, j) + at(A.wk, i + 1, j)) - T(2) * A.wk[p];
+    const T syd = (dlt(j - 1) + dlt(j + 1)) - T(2) * dlt(j);
+    const T rp = A.r[p];
+    const T mu = tc / rp;
+    const T nu = A.z[p] / rp;
+    A.grad[p] += mu * (A.c1 * s5u + A.c2 * sxw) + nu * (A.c2 * syd);
+    A.lam2[p] = (T(2) * A.lam1[p] - A.lam2[p]) + T(2) * s5t;
+}
+
+// lam[idx[r]] += vals[r], sequentially (receivers may share a node)
+template <typename T>
+__global__ void k_scatter_add(T* __restrict__ lam, const int* __restrict__ idx, const T* __restrict__ vals,
+                              int n, long long npts)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int k = 0; k < n; ++k) {
+            const int id = idx[k];
+            if (id >= 0 && id < npts) lam[id] += vals[k];
+        }
+}
+
+// out[s] = dt^2 t[idx[s]] / r[idx[s]]  (dJ/d source value)
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_src(const T* __restrict__ t, const T* __restrict__ r,
+                                                    const int* __restrict__ idx, T* __restrict__ out, int n,
+                                                    T tau2, long long npts)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) {
+        const int id = idx[k];
+        out[k] = (id >= 0 && id < npts) ? tau2 * t[id] / r[id] : T(0);
+    }
+}
+
+}  // namespace adw
+
+struct adi_adjoint_s {
+    int nsteps = 0, K = 0, ncheck = 0;
+    size_t field = 0;            // bytes of one field
+    void* ck = nullptr;          // 2 * ncheck fields: (u^{k0-1}, u^{k0}) of every segment
+    void* seg = nullptr;         // 2 * K fields: levels u^{k0+1..k0+K}, then w^{k0..k0+K-1}
+    void* work = nullptr;        // 6 fields: forward levels (2), lambda (2), t, z
+    size_t ck_cap = 0, seg_cap = 0, work_cap = 0;
+};
+
+namespace {
+
+void adjoint_free(adi_adjoint_s* a)
+{
+    if (!a) return;
+    if (a->ck) (void)hipFree(a->ck);
+    if (a->seg) (void)hipFree(a->seg);
+    if (a->work) (void)hipFree(a->work);
+    delete a;
+}
+
+adi_status grow(void** p, size_t* cap, size_t need)
+{
+    if (*cap >= need) return ADI_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc(p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(ADI_ENOMEM, "hipMalloc of adjoint storage failed");
+    }
+    *cap = need;
+    return ADI_OK;
+}
+
+template <typename T, int TR>
+void launch_xsolve1(int grid, const XArgs<T>& a, hipStream_t st)
+{
+    constexpr int NT = TR >= 256 ? TR : 256;
+    hipLaunchKernelGGL((k_xsweep<T, TR, false, false>), dim3(grid), dim3(NT), 0, st, a);
+}
+
+// x-line solves of a given field: out = A_x^{-1} rhs
+template <typename T>
+adi_status queue_xsolve(adi_wave_s* w, const void* rhs, void* out)
+{
+    XArgs<T> a = make_x<T>(w, rhs, nullptr, 0, T(1));
+    a.w = static_cast<T*>(out);
+    a.rows_per_strip = w->xp.rs;
+    a.vec = a.vec && aligned16(out);
+    const int g = x_groups_per_wg(w->xp.tr);
+    const int grid = ((w->ny + w->xp.rs - 1) / w->xp.rs + g - 1) / g;
+    switch (w->xp.tr) {
+        case 64: launch_xsolve1<T, 64>(grid, a, w->stream); break;
+        case 128: launch_xsolve1<T, 128>(grid, a, w->stream); break;
+        case 256: launch_xsolve1<T, 256>(grid, a, w->stream); break;
+        case 1024: launch_xsolve1<T, 1024>(grid, a, w->stream); break;
+        default: return fail(ADI_EUNSUPPORTED, "no x-solve kernel for this plan");
+    }
+    ADI_LAUNCHED("x_solve");
+    return ADI_OK;
+}
+
+// y-line solves: out = A_y^{-1} (r * rhs)
+template <typename T>
+adi_status queue_ysolve_scaled(adi_wave_s* w, const void* rhs, void* out)
+{
+    YArgs<T> ya = make_y<T>(w, nullptr, nullptr, out, T(0), T(0));
+    ya.w = static_cast<const T*>(rhs);
+    ya.rhs_times_r = 1;
+    const dim3 yg((w->nx + 255) / 256, w->K);
+    hipLaunchKernelGGL((k_yreduce<T>), yg, dim3(256), 0, w->stream, ya);
+    ADI_LAUNCHED("y_reduce (adjoint)");
+    if (!launch_yscan<T>(w->yq, w->nx, ya, w->stream))
+        return fail(ADI_EUNSUPPORTED, "no y-interface kernel for this configuration");
+    ADI_LAUNCHED("y_scan (adjoint)");
+    if (!launch_ysolve<T>(w->M, yg, ya, w->stream))
+        return fail(ADI_EUNSUPPORTED, "no y-solve kernel for this chunk size");
+    ADI_LAUNCHED("y_solve (adjoint)");
+    return ADI_OK;
+}
+
+adi_source src_at(const adi_source* f, int step0, size_t es)
+{
+    adi_source s{};
+    if (f && f->count > 0) {
+        s = *f;
+        s.amp = static_cast<const char*>(f->amp) + (size_t)step0 * f->count * es;
+    }
+    return s;
+}
+
+template <typename T>
+adi_status adj_forward(adi_wave_s* w, const void* u_prev, const void* u_curr, const adi_source* f,
+                       const adi_receivers* rec, int nsteps, int K)
+{
+    adi_adjoint_s* a = w->adj;
+    const size_t F = (size_t)w->nx * w->ny * sizeof(T);
+    a->field = F;
+    a->nsteps = nsteps;
+    a->K = K;
+    a->ncheck = (nsteps + K - 1) / K;
+    if (adi_status s = grow(&a->ck, &a->ck_cap, 2 * (size_t)a->ncheck * F)) return s;
+    if (adi_status s = grow(&a->work, &a->work_cap, 6 * F)) return s;
+    char* lev = static_cast<char*>(a->work);
+    void* p = lev;
+    void* q = lev + F;
+    ADI_HIP(hipMemcpyAsync(p, u_prev, F, hipMemcpyDeviceToDevice, w->stream));
+    ADI_HIP(hipMemcpyAsync(q, u_curr, F, hipMemcpyDeviceToDevice, w->stream));
+    for (int c = 0; c < a->ncheck; ++c) {
+        char* ck = static_cast<char*>(a->ck) + 2 * (size_t)c * F;
+        ADI_HIP(hipMemcpyAsync(ck, p, F, hipMemcpyDeviceToDevice, w->stream));
+        ADI_HIP(hipMemcpyAsync(ck + F, q, F, hipMemcpyDeviceToDevice, w->stream));
+        const int n = std::min(K, nsteps - c * K);
+        adi_source sc = src_at(f, c * K, sizeof(T));
+        adi_receivers rc{};
+        if (rec && rec->count > 0) {
+            rc = *rec;
+            rc.traces = static_cast<char*>(rec->traces) + (size_t)c * K * rec->count * sizeof(T);
+        }
+        if (adi_status s = do_step<T>(w, &p, &q, f ? &sc : nullptr, rec ? &rc : nullptr, n)) return s;
+    }
+    return ADI_OK;
+}
+
+template <typename T>
+adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers* rec, const void* grad_traces,
+                        void* grad_kappa, void* grad_amp)
+{
+    adi_adjoint_s* a = w->adj;
+    const size_t F = a->field;
+    const int S = a->nsteps, K = a->K;
+    const long long npts = (long long)w->nx * w->ny;
+    if (adi_status s = grow(&a->seg, &a->seg_cap, 2 * (size_t)K * F)) return s;
+    char* work = static_cast<char*>(a->work);
+    T* lam1 = reinterpret_cast<T*>(work + 2 * F);
+    T* lam2 = reinterpret_cast<T*>(work + 3 * F);
+    T* tt = reinterpret_cast<T*>(work + 4 * F);
+    T* zz = reinterpret_cast<T*>(work + 5 * F);
+    char* seg = static_cast<char*>(a->seg);
+    const int nrec = rec ? rec->count : 0;
+    const T* gt = static_cast<const T*>(grad_traces);
+    ADI_HIP(hipMemsetAsync(lam1, 0, F, w->stream));
+    ADI_HIP(hipMemsetAsync(lam2, 0, F, w->stream));
+    ADI_HIP(hipMemsetAsync(grad_kappa, 0, F, w->stream));
+    if (nrec > 0) {
+        hipLaunchKernelGGL((k_scatter_add<T>), dim3(1), dim3(64), 0, w->stream, lam1, rec->idx,
+                           gt + (size_t)(S - 1) * nrec, nrec, npts);
+        ADI_LAUNCHED("scatter_add");
+    }
+    const double beta = 0.5 * w->dt * w->dt;
+    AdjArgs<T> ua{};
+    ua.r = static_cast<const T*>(w->r);
+    ua.grad = static_cast<T*>(grad_kappa);
+    ua.nx = w->nx;
+    ua.ny = w->ny;
+    ua.c1 = (T)(w->dt * w->dt / (w->h * w->h));
+    ua.c2 = (T)(beta / (w->h * w->h));
+    const dim3 ug((w->nx + 63) / 64, (w->ny + 3) / 4);
+    void* wkeep = w->w;
+    for (int c = a->ncheck - 1; c >= 0; --c) {
+        const int k0 = 1 + c * K;
+        const int n = std::min(K, S - c * K);
+        // levels L[0..n+1] = u^{k0-1} .. u^{k0+n}; L[0], L[1] are the checkpoint
+        auto lev = [&](int m) -> void* {
+            if (m < 2) return static_cast<char*>(a->ck) + (2 * (size_t)c + m) * F;
+            return seg + (size_t)(m - 2) * F;
+        };
+        auto wst = [&](int m) -> void* { return seg + ((size_t)K + m) * F; };
+        for (int m = 0; m < n; ++m) {
+            adi_source sc = src_at(f, k0 - 1 + m, sizeof(T));
+            w->w = wst(m);                       // keep w^k of this step
+            adi_status s = queue_solve<T>(w, lev(m + 1), lev(m), lev(m + 2), T(2), T(-1), f ? &sc : nullptr, 0,
+                                          T(1), nullptr);
+            w->w = wkeep;
+            if (s != ADI_OK) return s;
+        }
+        for (int m = n - 1; m >= 0; --m) {
+            const int k = k0 + m;
+            if (adi_status s = queue_ysolve_scaled<T>(w, lam1, zz)) return s;
+            if (adi_status s = queue_xsolve<T>(w, zz, tt)) return s;
+            ua.t = tt; ua.z = zz; ua.lam1 = lam1; ua.lam2 = lam2;
+            ua.um = static_cast<const T*>(lev(m));
+            ua.uk = static_cast<const T*>(lev(m + 1));
+            ua.up = static_cast<const T*>(lev(m + 2));
+            ua.wk = static_cast<const T*>(wst(m));
+            hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
+            ADI_LAUNCHED("adjoint_update");
+            if (nrec > 0 && k >= 2) {
+                hipLaunchKernelGGL((k_scatter_add<T>), dim3(1), dim3(64), 0, w->stream, lam2, rec->idx,
+                                   gt + (size_t)(k - 2) * nrec, nrec, npts);
+                ADI_LAUNCHED("scatter_add");
+            }
+            if (grad_amp && f && f->count > 0) {
+                hipLaunchKernelGGL((k_gather_src<T>), dim3((f->count + 255) / 256), dim3(256), 0, w->stream,
+                                   tt, static_cast<const T*>(w->r), f->idx,
+                                   static_cast<T*>(grad_amp) + (size_t)(k - 1) * f->count, f->count,
+                                   (T)(w->dt * w->dt), npts);
+                ADI_LAUNCHED("gather_src");
+            }
+            std::swap(lam1, lam2);
+        }
+    }
+    return ADI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_curr, const adi_source* f,
+                               const adi_receivers* rec, int nsteps, int checkpoint_every)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!u_prev || !u_curr) return fail(ADI_EINVAL, "null level pointer");
+    if (nsteps < 1) return fail(ADI_EINVAL, "nsteps must be >= 1");
+    if (checkpoint_every < 1) return fail(ADI_EINVAL, "checkpoint_every must be >= 1");
+    if (adi_status s = check_src(f)) return s;
+    if (adi_status s = check_rec(rec)) return s;
+    if (!w->adj) w->adj = new adi_adjoint_s();
+    w->adj->nsteps = 0;
+    adi_status s = w->dtype == ADI_F32
+                       ? adj_forward<float>(w, u_prev, u_curr, f, rec, nsteps, checkpoint_every)
+                       : adj_forward<double>(w, u_prev, u_curr, f, rec, nsteps, checkpoint_every);
+    if (s != ADI_OK) w->adj->nsteps = 0;
+    return s;
+}
+
+adi_status adi_adjoint_backward(adi_wave_t w, const adi_source* f, const adi_receivers* rec,
+                                const void* grad_traces, void* grad_kappa, void* grad_amp)
+{
+    if (adi_status s = check_handle(w)) return s;
+    if (!w->adj || w->adj->nsteps < 1) return fail(ADI_EINVAL, "run adi_adjoint_forward first");
+    if (!grad_kappa) return fail(ADI_EINVAL, "grad_kappa is null");
+    if (adi_status s = check_src(f)) return s;
+    if (adi_status s = check_rec(rec)) return s;
+    if (rec && rec->count > 0 && !grad_traces) return fail(ADI_EINVAL, "grad_traces is null");
+    return w->dtype == ADI_F32 ? adj_backward<float>(w, f, rec, grad_traces, grad_kappa, grad_amp)
+                               : adj_backward<double>(w, f, rec, grad_traces, grad_kappa, grad_amp);
+}
+
+}  // extern "C"

@@ -122,6 +122,7 @@ struct YArgs {
     T* out;
     T alpha, beta;
     T* tmp;              // create-time scratch for the static planes (5*K*nx)
+    int rhs_times_r;     // right-hand side of the y-lines is r * w (adjoint solves)
 };
 
 // Data part of one chunk's interior elimination (top-down, pivots started
@@ -130,12 +131,12 @@ struct YArgs {
 // prod_{i<k} q_i * forward_k).
 template <typename T, bool FULL, int M>
 __device__ __forceinline__ void ychunk_data(const T* __restrict__ wp, const T* __restrict__ rp,
-                                            size_t nx, int L, T& Pf, T& Pl)
+                                            size_t nx, int L, T& Pf, T& Pl, bool scale)
 {
     T q = T(0), dpv = T(0), pi = T(1), yP = T(0);
     for (int k = 0; k < (FULL ? M - 1 : L - 1); ++k) {
         const T rk = rp[(size_t)k * nx];
-        const T wk = wp[(size_t)k * nx];
+        const T wk = scale ? rk * wp[(size_t)k * nx] : wp[(size_t)k * nx];
         const T m = pivot_step<T>(rk, q);
         dpv = fma_rn(rk, dpv, wk) * m;
         yP = fma_rn(pi, dpv, yP);
@@ -158,11 +159,12 @@ __global__ void __launch_bounds__(256) k_yreduce(YArgs<T> A)
     const T* __restrict__ wp = A.w + (size_t)lo * nx + i;
     const T* __restrict__ rp = A.r + (size_t)lo * nx + i;
     T Pf = T(0), Pl = T(0);
-    if (L == 16 && A.M == 16) ychunk_data<T, true, 16>(wp, rp, nx, L, Pf, Pl);
-    else if (L == 32 && A.M == 32) ychunk_data<T, true, 32>(wp, rp, nx, L, Pf, Pl);
-    else if (L >= 2) ychunk_data<T, false, 1>(wp, rp, nx, L, Pf, Pl);
+    const bool sc = A.rhs_times_r != 0;
+    if (L == 16 && A.M == 16) ychunk_data<T, true, 16>(wp, rp, nx, L, Pf, Pl, sc);
+    else if (L == 32 && A.M == 32) ychunk_data<T, true, 32>(wp, rp, nx, L, Pf, Pl, sc);
+    else if (L >= 2) ychunk_data<T, false, 1>(wp, rp, nx, L, Pf, Pl, sc);
     const T rI = rp[(size_t)(L - 1) * nx];
-    const T wI = wp[(size_t)(L - 1) * nx];
+    const T wI = sc ? rI * wp[(size_t)(L - 1) * nx] : wp[(size_t)(L - 1) * nx];
     A.sum[plane_at(kPlaneE, c, i, A.K, A.nxp)] = fma_rn(rI, Pl, wI);
     A.sum[plane_at(kPlanePf, c, i, A.K, A.nxp)] = Pf;
 }
@@ -273,6 +275,7 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
     const T* __restrict__ u = A.u;
     const T* __restrict__ v = A.v;
     T* __restrict__ out = A.out;
+    const bool scale = A.rhs_times_r != 0;
     T qa[M], da[M];
     T q = T(0), dpv = T(0);
 #pragma unroll
@@ -284,6 +287,7 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
             if (FULL || k < L - 1) {
                 rr[k - g0] = r[base + (size_t)k * nx];
                 ww[k - g0] = w[base + (size_t)k * nx];
+                if (scale) ww[k - g0] *= rr[k - g0];
             }
         }
 #pragma unroll
@@ -301,6 +305,7 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
         __builtin_amdgcn_sched_barrier(0);
     }
     const bool hasv = v != nullptr;
+    const bool hasu = u != nullptr;
     T x = Xc;
 #pragma unroll
     for (int g1 = M - 1; g1 >= 0; g1 -= GR) {
@@ -310,7 +315,7 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
             uu[g1 - k] = T(0); vv[g1 - k] = T(0);
             if (FULL || k < L) {
                 const size_t p = base + (size_t)k * nx;
-                uu[g1 - k] = u[p];
+                uu[g1 - k] = hasu ? u[p] : T(0);
                 vv[g1 - k] = hasv ? v[p] : T(0);
             }
         }

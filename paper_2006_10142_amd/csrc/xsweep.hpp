@@ -248,7 +248,9 @@ struct XShared {
 // One strip (rows_per_strip rows from strip * rows_per_strip) of one line group.
 // Every thread of the workgroup must call this with the same rows_per_strip
 // (it synchronises the workgroup twice per row).
-template <typename T, int TR, bool FUSE>
+// STENCIL = false: the right-hand side of row j is rho_scale * (row j of A.u)
+// instead of the 5-point assembly (line solves of a given field).
+template <typename T, int TR, bool FUSE, bool STENCIL = true>
 __device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip, const int t,
                                              XShared<T, TR, FUSE>& sh)
 {
@@ -333,9 +335,13 @@ __device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip,
             const T eastL = (t + 1 < nseg) ? s_halo[p][0][t + 1] : T(0);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const T uw = (e == 0) ? west0 : uc[e - 1];
-                const T ue = (e == E - 1) ? eastL : uc[e + 1];
-                rho[e] = A.rho_scale * (T(2) * rc[e] * (((uw + ue) + (um[e] + u1[e])) - T(4) * uc[e]));
+                if constexpr (STENCIL) {
+                    const T uw = (e == 0) ? west0 : uc[e - 1];
+                    const T ue = (e == E - 1) ? eastL : uc[e + 1];
+                    rho[e] = A.rho_scale * (T(2) * rc[e] * (((uw + ue) + (um[e] + u1[e])) - T(4) * uc[e]));
+                } else {
+                    rho[e] = A.rho_scale * uc[e];
+                }
             }
         }
         if (live) {
@@ -476,13 +482,13 @@ __device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip,
     }
 }
 
-template <typename T, int TR, bool FUSE>
+template <typename T, int TR, bool FUSE, bool STENCIL = true>
 __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
 {
     constexpr int G = (TR >= 256 ? TR : 256) / TR;
     __shared__ XShared<T, TR, FUSE> sh[G];
     const int g = threadIdx.x / TR;
-    xsweep_strip<T, TR, FUSE>(A, blockIdx.x * G + g, threadIdx.x - g * TR, sh[g]);
+    xsweep_strip<T, TR, FUSE, STENCIL>(A, blockIdx.x * G + g, threadIdx.x - g * TR, sh[g]);
 }
 
 }  // namespace adw

@@ -1,0 +1,175 @@
+"""Adjoint (reverse-time) gradients on the GPU against the FP64 oracle's adjoint,
+finite differences of the GPU forward, the dot-product identity, checkpoint
+invariance and the autograd Function.
+
+Tolerances: FP64 gradients <= 1e-10 relative L2 against the oracle; FP32
+gradients <= 2e-3 (the adjoint wave accumulates FP32 rounding like the forward
+run, and the loss is quadratic in traces that carry it)."""
+import numpy as np
+import pytest
+
+from tests.conftest import rel_l2
+from paper_2006_10142_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def adw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2006_10142_amd as m
+    m._lib.load()
+    return m
+
+
+def tdt(d):
+    return torch.float32 if d == "f32" else torch.float64
+
+
+def npdt(d):
+    return np.float32 if d == "f32" else np.float64
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def case(dtype, nx=90, ny=70, nsteps=50, seed=1, nonzero=False):
+    h = 1.0 / (max(nx, ny) + 1)
+    kappa = wl.smooth_field(nx, ny, 1.0, 9.0, seed=seed).astype(npdt(dtype))
+    dt = 0.4 * h / 3.0
+    rng = np.random.default_rng(seed)
+    if nonzero:
+        up = (0.1 * wl.gaussian_pulse(nx, ny, 0.1)).astype(npdt(dtype))
+        uc = (up.astype(np.float64) * 0.999).astype(npdt(dtype))
+    else:
+        up = np.zeros((ny, nx), npdt(dtype))
+        uc = np.zeros((ny, nx), npdt(dtype))
+    src_idx = np.array([(ny // 3) * nx + nx // 2, (2 * ny // 3) * nx + nx // 4], np.int32)
+    amp = (wl.point_source_series(nsteps, dt, h, 1, f0=25.0) * np.array([[1.0, -0.5]])).astype(npdt(dtype))
+    rec_idx = np.array([(ny // 8) * nx + (k * nx) // 8 for k in range(8)], np.int32)
+    target = (rng.standard_normal((nsteps, 8)) * 1e-4).astype(npdt(dtype))
+    return dict(nx=nx, ny=ny, h=h, dt=dt, kappa=kappa, up=up, uc=uc, src_idx=src_idx, amp=amp,
+                rec_idx=rec_idx, target=target, nsteps=nsteps, dtype=dtype)
+
+
+def gpu_grad(adw, c, K, want_amp=True, kappa=None):
+    wave = adw.Wave(c["nx"], c["ny"], c["h"], c["dt"], dtype=tdt(c["dtype"]),
+                    kappa=dev(c["kappa"] if kappa is None else kappa))
+    si, ri = dev(c["src_idx"]), dev(c["rec_idx"])
+    amp = dev(c["amp"])
+    tr = wave.adjoint_forward(dev(c["up"]), dev(c["uc"]), c["nsteps"], src_idx=si, src_amp=amp,
+                              rec_idx=ri, checkpoint_every=K)
+    gtr = 2.0 * (tr - dev(c["target"]))
+    gk, ga = wave.adjoint_backward(gtr, src_idx=si, src_amp=amp, rec_idx=ri, want_amp=want_amp)
+    torch.cuda.synchronize()
+    out = (gk.cpu().numpy(), None if ga is None else ga.cpu().numpy(), tr.cpu().numpy())
+    wave.close()
+    return out
+
+
+def oracle_grad(oracle_lib, c):
+    kap = c["kappa"].astype(np.float64)
+    _, _, tr = oracle_lib.run(kap, c["up"], c["uc"], c["h"], c["dt"], c["nsteps"], src_idx=c["src_idx"],
+                              src_amp=c["amp"], rec_idx=c["rec_idx"])
+    gk, ga = oracle_lib.adjoint(kap, c["up"], c["uc"], c["h"], c["dt"], c["nsteps"],
+                                2.0 * (tr - c["target"]), c["rec_idx"], src_idx=c["src_idx"],
+                                src_amp=c["amp"])
+    return gk, ga, tr
+
+
+@pytest.mark.parametrize("dtype,K,nonzero", [("f64", 1, False), ("f64", 7, True), ("f64", 50, False),
+                                             ("f32", 16, False), ("f32", 50, True)])
+def test_adjoint_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
+    c = case(dtype, nonzero=nonzero)
+    say(f"adjoint {dtype} K={K} nonzero={nonzero}")
+    gk, ga, tr = gpu_grad(adw, c, K)
+    rk, ra, rtr = oracle_grad(oracle_lib, c)
+    tol = 1e-10 if dtype == "f64" else 2e-3
+    assert np.abs(rk).max() > 0
+    assert rel_l2(tr, rtr) <= (1e-12 if dtype == "f64" else 1e-5)
+    assert rel_l2(gk, rk) <= tol
+    assert rel_l2(ga, ra) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_checkpoint_interval_does_not_change_the_gradient(adw, dtype):
+    c = case(dtype, nx=64, ny=48, nsteps=37, seed=4)
+    say(f"checkpoint invariance {dtype}")
+    g1 = gpu_grad(adw, c, 1)
+    g2 = gpu_grad(adw, c, 5)
+    g3 = gpu_grad(adw, c, 37)
+    g4 = gpu_grad(adw, c, 100)
+    for g in (g2, g3, g4):
+        assert np.array_equal(g1[0], g[0]) and np.array_equal(g1[1], g[1])
+
+
+def test_gradient_matches_finite_differences_on_gpu(adw):
+    """C5's recipe at 128^2 (kappa in [1, 9], Ricker, receivers on the row nearest
+    y = 0.1), FP64, 300 steps: central differences of the GPU loss on 16 cells."""
+    p, kt = wl.config_c5(dtype="f64", nsteps=300, n=128, nrec=16)
+    # target: the traces of the run on the second kappa field
+    wave = adw.Wave(p.nx, p.ny, p.h, p.dt, dtype=torch.float64, kappa=dev(kt))
+    si, ri, amp = dev(p.src_idx), dev(p.rec_idx), dev(p.src_amp)
+    zero = dev(p.u_prev)
+    target = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
+                                  checkpoint_every=100)
+    say("C5-shape FD check")
+
+    def loss(kap):
+        wave.set_kappa(dev(kap))
+        tr = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
+                                  checkpoint_every=100)
+        return float(((tr - target) ** 2).sum()), tr
+
+    J0, tr = loss(p.kappa)
+    gk, _ = wave.adjoint_backward(2.0 * (tr - target), src_idx=si, src_amp=amp, rec_idx=ri)
+    g = gk.cpu().numpy()
+    rng = np.random.default_rng(6)
+    cand = np.argwhere(np.abs(g) >= 1e-2 * np.abs(g).max())
+    cells = cand[rng.choice(len(cand), size=16, replace=False)]
+    for (j, i) in cells:
+        eps = 1e-5 * p.kappa[j, i]
+        kp = p.kappa.copy(); kp[j, i] += eps
+        km = p.kappa.copy(); km[j, i] -= eps
+        fd = (loss(kp)[0] - loss(km)[0]) / (2 * eps)
+        assert abs(fd - g[j, i]) <= 1e-5 * abs(fd), (j, i, fd, g[j, i])
+    wave.close()
+
+
+def test_dot_product_identity_on_gpu(adw):
+    """<F f, d> = <f, F^T d> for the map source values -> traces (FP64, zero start)."""
+    c = case("f64", nx=80, ny=60, nsteps=60, seed=8)
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal((c["nsteps"], 8))
+    wave = adw.Wave(c["nx"], c["ny"], c["h"], c["dt"], dtype=torch.float64, kappa=dev(c["kappa"]))
+    si, ri, amp = dev(c["src_idx"]), dev(c["rec_idx"]), dev(c["amp"])
+    Ff = wave.adjoint_forward(dev(c["up"]), dev(c["uc"]), c["nsteps"], src_idx=si, src_amp=amp,
+                              rec_idx=ri, checkpoint_every=13)
+    _, Ftd = wave.adjoint_backward(dev(d), src_idx=si, src_amp=amp, rec_idx=ri, want_amp=True)
+    lhs = float((Ff.cpu().numpy() * d).sum())
+    rhs = float((c["amp"] * Ftd.cpu().numpy()).sum())
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    wave.close()
+
+
+def test_autograd_function(adw, oracle_lib):
+    c = case("f64", nx=48, ny=40, nsteps=30, seed=5)
+    wave = adw.Wave(c["nx"], c["ny"], c["h"], c["dt"], dtype=torch.float64, kappa=dev(c["kappa"]))
+    kap = dev(c["kappa"]).requires_grad_(True)
+    amp = dev(c["amp"]).requires_grad_(True)
+    si, ri = dev(c["src_idx"]), dev(c["rec_idx"])
+    tr = adw.simulate_traces(wave, kap, dev(c["up"]), dev(c["uc"]), c["nsteps"], si, amp, ri,
+                             checkpoint_every=8)
+    loss = ((tr - dev(c["target"])) ** 2).sum()
+    loss.backward()
+    rk, ra, _ = oracle_grad(oracle_lib, c)
+    assert rel_l2(kap.grad.cpu().numpy(), rk) <= 1e-10
+    assert rel_l2(amp.grad.cpu().numpy(), ra) <= 1e-10
+    wave.close()
