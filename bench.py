@@ -139,6 +139,48 @@ def bench_batched(adw, torch, steps: int, warmup: int, plain_value: float):
             "vs_plain": round(value / plain_value, 4), "finite": finite}
 
 
+def bench_adjoint(adw, torch, plain_value: float):
+    """C5: dJ/dkappa of a receiver misfit on 1024^2 FP32, 2000 steps, checkpoints every 100
+    steps, 64 receivers; target traces from the run on the second kappa field."""
+    from paper_2006_10142_amd import workloads as wl
+    p, kt = wl.config_c5(dtype="f32")
+    dev = torch.device("cuda:0")
+    wave = adw.Wave(p.nx, p.ny, p.h, p.dt, dtype=torch.float32, kappa=torch.from_numpy(kt).to(dev))
+    si = torch.from_numpy(p.src_idx).to(dev)
+    ri = torch.from_numpy(p.rec_idx).to(dev)
+    amp = torch.from_numpy(p.src_amp).to(dev)
+    zero = torch.zeros((p.ny, p.nx), dtype=torch.float32, device=dev)
+    target = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
+                                  checkpoint_every=100)
+    wave.set_kappa(torch.from_numpy(p.kappa).to(dev))
+    # warm-up pass (allocates the checkpoint and segment storage)
+    tr = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
+                              checkpoint_every=100)
+    wave.adjoint_backward(2.0 * (tr - target), src_idx=si, src_amp=amp, rec_idx=ri)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    tr = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
+                              checkpoint_every=100)
+    e[1].record()
+    gk, _ = wave.adjoint_backward(2.0 * (tr - target), src_idx=si, src_amp=amp, rec_idx=ri)
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd = e[0].elapsed_time(e[1])
+    bwd = e[1].elapsed_time(e[2])
+    loss = float(((tr - target) ** 2).sum())
+    finite = bool(torch.isfinite(gk).all())
+    nodes = p.nx * p.ny
+    value = nodes * p.nsteps / ((fwd + bwd) / 1e3) / 1e6
+    wave.close()
+    return {"workload": "c5_adjoint_1024x1024_f32_2000_steps_64_receivers", "value": round(value, 1),
+            "unit": "Mpts/s (gradient evaluation: forward with checkpoints + reverse pass)",
+            "forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
+            "ms_per_step_forward": round(fwd / p.nsteps, 5),
+            "ms_per_step_backward": round(bwd / p.nsteps, 5), "checkpoint_every": 100,
+            "loss": loss, "finite": finite, "vs_plain": round(value / plain_value, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +191,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -266,6 +309,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = bench_batched(adw, torch, args.steps, args.warmup, value)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(adw, torch, value)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(out), flush=True)

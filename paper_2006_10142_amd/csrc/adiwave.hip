@@ -47,7 +47,7 @@ size_t esize(adi_dtype t) { return t == ADI_F64 ? 8 : 4; }
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // ---------------------------------------------------------- launch plans ----
-struct XPlan { int tr, rs, fuse; };
+struct XPlan { int tr, rs, fuse, frs; };   // frs: rows of a fused strip (whole chunks)
 
 // x-sweep: smallest line group whose 8 * tr nodes cover nx
 bool choose_x(int nx, adi_dtype, XPlan& p)
@@ -309,7 +309,7 @@ XArgs<T> make_x(const adi_wave_s* w, const void* u, const adi_source* f, int k, 
     a.nx = w->nx;
     a.ny = w->ny;
     a.nseg = w->nseg;
-    a.rows_per_strip = w->xp.fuse ? fused_rows(w->M) : w->xp.rs;
+    a.rows_per_strip = w->xp.fuse ? w->xp.frs : w->xp.rs;
     a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && aligned16(u) && aligned16(w->r) &&
             aligned16(w->w);
     a.sum = static_cast<T*>(w->sum);
@@ -351,7 +351,7 @@ YArgs<T> make_y(const adi_wave_s* w, const void* u, const void* v, void* out, T 
 int x_grid(const adi_wave_s* w)
 {
     const int g = x_groups_per_wg(w->xp.tr);
-    const int rs = w->xp.fuse ? fused_rows(w->M) : w->xp.rs;
+    const int rs = w->xp.fuse ? w->xp.frs : w->xp.rs;
     const int strips = (w->ny + rs - 1) / rs;
     return (strips + g - 1) / g;
 }
@@ -477,13 +477,27 @@ adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
     if (!choose_x(nx, dtype, xp))
         return fail(ADI_EUNSUPPORTED, "nx > 8192 is not supported");
     xp.rs = choose_rows(ny, xp.tr);
-    xp.fuse = fuse_fits(xp.tr, dtype) ? 1 : 0;
+    // chunk rows: 32 unless the y-solve would have fewer than 512 workgroups
+    int M = ((long long)((nx + 255) / 256) * ((ny + 31) / 32) >= 512) ? 32 : 16;
+    // fusing the y-chunk reduction into the x-sweep needs a strip per workgroup
+    // on every CU; fused strips are whole chunks: (chunk rows, strip rows) from
+    // (32, 32), (16, 32), (16, 16), the first that gives enough strips
+    xp.fuse = 0;
+    xp.frs = fused_rows(M);
+    if (fuse_fits(xp.tr, dtype)) {
+        static const int cand[][2] = {{32, 32}, {16, 32}, {16, 16}};
+        for (auto& c : cand) {
+            if (c[0] > M) continue;
+            const long long wgs = ((ny + c[1] - 1) / c[1] + x_groups_per_wg(xp.tr) - 1) / x_groups_per_wg(xp.tr);
+            if (wgs >= 256) { M = c[0]; xp.frs = c[1]; xp.fuse = 1; break; }
+        }
+    }
 
     adi_wave_s* w = new adi_wave_s();
     w->nx = nx; w->ny = ny; w->h = h; w->dt = dt; w->dtype = dtype;
     w->stream = static_cast<hipStream_t>(hip_stream);
     w->xp = xp;
-    w->M = 32;                       // chunk rows
+    w->M = M;
     if (hipGetDevice(&w->device) != hipSuccess) {
         delete w;
         return fail(ADI_EHIP, "hipGetDevice failed");
@@ -572,7 +586,7 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->ny = w->ny;
     info->dtype = (int)w->dtype;
     info->x_threads_per_line = w->xp.tr;
-    info->x_rows_per_strip = w->xp.fuse ? fused_rows(w->M) : w->xp.rs;
+    info->x_rows_per_strip = w->xp.fuse ? w->xp.frs : w->xp.rs;
     info->y_fused = w->xp.fuse;
     info->y_chunk_rows = w->M;
     info->y_chunks = w->K;
@@ -597,6 +611,7 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
         return fail(ADI_EUNSUPPORTED, "fused y-reduction does not fit in LDS for this plan");
     const int M = t->y_chunk_rows > 0 ? t->y_chunk_rows : w->M;
     if (M != 16 && M != 32) return fail(ADI_EINVAL, "y_chunk_rows must be 16 or 32");
+    if (xp.fuse && (M != w->M || !w->xp.fuse)) xp.frs = fused_rows(M);
     w->xp = xp;
     if (M != w->M) {
         if (hipStreamSynchronize(w->stream) != hipSuccess)

@@ -368,6 +368,7 @@ adi_status adi_batch_create(adi_batch_t* out, int count, const int* nx, const in
         w.nseg = (nx[s] + kSeg - 1) / kSeg;
         w.xp = xp;
         w.xp.fuse = 1;
+        w.xp.frs = b->RS;
         w.w_cap = std::max((size_t)nx[s] * ny[s], (size_t)5 * w.K * nx[s]);
         b->max_K = std::max(b->max_K, w.K);
         off[s] = total;
