@@ -92,6 +92,7 @@ def test_adjoint_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
     gk, ga, tr = gpu_grad(adw, c, K)
     rk, ra, rtr = oracle_grad(oracle_lib, c)
     tol = 1e-10 if dtype == "f64" else 2e-3
+    say(f"  rel L2: traces {rel_l2(tr, rtr):.3e}  dJ/dkappa {rel_l2(gk, rk):.3e}  dJ/dsource {rel_l2(ga, ra):.3e}")
     assert np.abs(rk).max() > 0
     assert rel_l2(tr, rtr) <= (1e-12 if dtype == "f64" else 1e-5)
     assert rel_l2(gk, rk) <= tol
