@@ -61,8 +61,18 @@ bool choose_x(int nx, adi_dtype, XPlan& p)
 // the fused y-chunk state (4 values per column) must fit in LDS next to the rest
 bool fuse_fits(int tr, adi_dtype dt)
 {
-    const size_t es = dt == ADI_F64 ? 8 : 4;
-    const size_t lds = (4 * 8 * (size_t)std::max(tr, 256) + 4 * (size_t)std::max(tr, 256)) * es;
+    // LDS of one workgroup of the fused x-sweep: G = max(tr, 256) / tr line groups
+    auto bytes = [&](auto tag) -> size_t {
+        using T = decltype(tag);
+        switch (tr) {
+        case 64: return 4 * sizeof(XShared<T, 64, true>);
+        case 128: return 2 * sizeof(XShared<T, 128, true>);
+        case 256: return sizeof(XShared<T, 256, true>);
+        case 1024: return sizeof(XShared<T, 1024, true>);
+        default: return SIZE_MAX;
+        }
+    };
+    const size_t lds = dt == ADI_F64 ? bytes(double()) : bytes(float());
     return lds <= 150 * 1024;
 }
 

@@ -63,29 +63,42 @@ __global__ void __launch_bounds__(256) k_adjoint_update(AdjArgs<T> A)
     A.lam2[p] = (T(2) * A.lam1[p] - A.lam2[p]) + T(2) * s5t;
 }
 
-// lam[idx[r]] += vals[r], sequentially (receivers may share a node)
+// Point terms of one reverse step, one thread per receiver / source index k:
+//   receivers: lam[ridx[k]] += vals[k], in increasing k at each node (receivers
+//              may share a node: the first receiver of a node adds all of that
+//              node's values, in order, so the sums match a sequential loop);
+//   sources:   out[k] = tau2 * t[sidx[k]] / r[sidx[k]]  (dJ/d source value).
+// Offsets outside [0, npts) are skipped (receivers) or give 0 (sources).
 template <typename T>
-__global__ void k_scatter_add(T* __restrict__ lam, const int* __restrict__ idx, const T* __restrict__ vals,
-                              int n, long long npts)
+__global__ void __launch_bounds__(256) k_adjoint_points(T* __restrict__ lam, const int* __restrict__ ridx,
+                                                        const T* __restrict__ vals, int nrec,
+                                                        const T* __restrict__ t, const T* __restrict__ r,
+                                                        const int* __restrict__ sidx, T* __restrict__ out,
+                                                        int nsrc, T tau2, long long npts)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int k = 0; k < n; ++k) {
-            const int id = idx[k];
-            if (id >= 0 && id < npts) lam[id] += vals[k];
-        }
-}
-
-// out[s] = dt^2 t[idx[s]] / r[idx[s]]  (dJ/d source value)
-template <typename T>
-__global__ void __launch_bounds__(256) k_gather_src(const T* __restrict__ t, const T* __restrict__ r,
-                                                    const int* __restrict__ idx, T* __restrict__ out, int n,
-                                                    T tau2, long long npts)
-{
+    __shared__ int tile[256];
     const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k < n) {
-        const int id = idx[k];
+    if (out && k < nsrc) {
+        const int id = sidx[k];
         out[k] = (id >= 0 && id < npts) ? tau2 * t[id] / r[id] : T(0);
     }
+    if (!lam || blockIdx.x * 256 >= nrec) return;          // uniform per block
+    const int id = k < nrec ? ridx[k] : -1;
+    bool mine = id >= 0 && id < npts;                        // first receiver of its node
+    T acc = mine ? lam[id] : T(0);
+    for (int base = 0; base < nrec; base += 256) {
+        __syncthreads();
+        if (base + (int)threadIdx.x < nrec) tile[threadIdx.x] = ridx[base + threadIdx.x];
+        __syncthreads();
+        const int lim = min(256, nrec - base);
+        for (int q = 0; mine && q < lim; ++q) {
+            if (tile[q] != id) continue;
+            const int j = base + q;
+            if (j < k) mine = false;                         // an earlier receiver owns the node
+            else acc += vals[j];
+        }
+    }
+    if (mine) lam[id] = acc;
 }
 
 }  // namespace adw
@@ -236,10 +249,12 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     ADI_HIP(hipMemsetAsync(lam2, 0, F, w->stream));
     ADI_HIP(hipMemsetAsync(grad_kappa, 0, F, w->stream));
     if (nrec > 0) {
-        hipLaunchKernelGGL((k_scatter_add<T>), dim3(1), dim3(64), 0, w->stream, lam1, rec->idx,
-                           gt + (size_t)(S - 1) * nrec, nrec, npts);
-        ADI_LAUNCHED("scatter_add");
+        hipLaunchKernelGGL((k_adjoint_points<T>), dim3((nrec + 255) / 256), dim3(256), 0, w->stream, lam1,
+                           rec->idx, gt + (size_t)(S - 1) * nrec, nrec, nullptr, nullptr, nullptr, nullptr, 0,
+                           T(0), npts);
+        ADI_LAUNCHED("adjoint_points");
     }
+    const int nsrc = (grad_amp && f) ? f->count : 0;
     const double beta = 0.5 * w->dt * w->dt;
     AdjArgs<T> ua{};
     ua.r = static_cast<const T*>(w->r);
@@ -278,17 +293,15 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
             ua.wk = static_cast<const T*>(wst(m));
             hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
             ADI_LAUNCHED("adjoint_update");
-            if (nrec > 0 && k >= 2) {
-                hipLaunchKernelGGL((k_scatter_add<T>), dim3(1), dim3(64), 0, w->stream, lam2, rec->idx,
-                                   gt + (size_t)(k - 2) * nrec, nrec, npts);
-                ADI_LAUNCHED("scatter_add");
-            }
-            if (grad_amp && f && f->count > 0) {
-                hipLaunchKernelGGL((k_gather_src<T>), dim3((f->count + 255) / 256), dim3(256), 0, w->stream,
-                                   tt, static_cast<const T*>(w->r), f->idx,
-                                   static_cast<T*>(grad_amp) + (size_t)(k - 1) * f->count, f->count,
+            const int nr = k >= 2 ? nrec : 0;
+            if (nr > 0 || nsrc > 0) {
+                hipLaunchKernelGGL((k_adjoint_points<T>), dim3((std::max(nr, nsrc) + 255) / 256), dim3(256), 0,
+                                   w->stream, nr > 0 ? lam2 : nullptr, nr > 0 ? rec->idx : nullptr,
+                                   nr > 0 ? gt + (size_t)(k - 2) * nrec : nullptr, nr, tt,
+                                   static_cast<const T*>(w->r), nsrc > 0 ? f->idx : nullptr,
+                                   nsrc > 0 ? static_cast<T*>(grad_amp) + (size_t)(k - 1) * nsrc : nullptr, nsrc,
                                    (T)(w->dt * w->dt), npts);
-                ADI_LAUNCHED("gather_src");
+                ADI_LAUNCHED("adjoint_points");
             }
             std::swap(lam1, lam2);
         }

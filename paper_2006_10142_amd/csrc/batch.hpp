@@ -400,17 +400,12 @@ adi_status adi_batch_create(adi_batch_t* out, int count, const int* nx, const in
         w.X = take((size_t)w.K * nx[s]);
         w.yq = b->yq;
     }
-    // work lists; x-sweep strips (cost ~ nx) and interface blocks (cost ~ ny) are
-    // ordered longest first so that the persistent grids end evenly
-    std::vector<int> by_nx(count), by_ny(count);
-    for (int s = 0; s < count; ++s) by_nx[s] = by_ny[s] = s;
-    std::stable_sort(by_nx.begin(), by_nx.end(), [&](int a, int c) { return nx[a] > nx[c]; });
-    std::stable_sort(by_ny.begin(), by_ny.end(), [&](int a, int c) { return ny[a] > ny[c]; });
+    // work lists, in simulation order
     std::vector<int2> items;
-    for (int s : by_nx)
+    for (int s = 0; s < count; ++s)
         for (int st = 0; st < (ny[s] + b->RS - 1) / b->RS; ++st) items.push_back(make_int2(s, st));
     b->nx_items = (int)items.size();
-    for (int s : by_ny)
+    for (int s = 0; s < count; ++s)
         for (int blk = 0; blk < b->sims[s].nxp / kPB; ++blk) items.push_back(make_int2(s, blk));
     b->nys_items = (int)items.size() - b->nx_items;
     for (int s = 0; s < count; ++s)

@@ -18,8 +18,9 @@
 //     w_first = H + E g_in + Ql w_below    (H = sum P_e G_e, E = sum P_e Q_e,
 //                                           P_e = prod_{i<e} q_i)
 // A line is therefore solved by one forward and one backward scan of affine
-// maps across its segments: DPP row shifts / broadcasts inside a wavefront, one
-// LDS exchange across wavefronts -- the Thomas solution up to rounding.
+// maps across its segments: DPP row shifts / broadcasts inside a wavefront and
+// one LDS exchange of wavefront totals (one barrier per row) -- the Thomas
+// solution up to rounding.
 //
 // Layout: thread t of a line group owns nodes [8t, 8t+8) of the row (two
 // 16-byte vectors); consecutive lanes read consecutive 32-byte blocks.
@@ -111,37 +112,64 @@ __device__ __forceinline__ void compose_dpp(T& a, T& b)
     b = b * b2;
 }
 
-// inclusive prefix (lanes 0..l) over the wavefront
+template <int CTRL, int ROWMASK, typename T>
+__device__ __forceinline__ void compose3_dpp(T& a0, T& a1, T& b)
+{
+    const T x0 = dpp<CTRL, ROWMASK>(T(0), a0);
+    const T x1 = dpp<CTRL, ROWMASK>(T(0), a1);
+    const T b2 = dpp<CTRL, ROWMASK>(T(1), b);
+    a0 = fma_rn(b, x0, a0);
+    a1 = fma_rn(b, x1, a1);
+    b = b * b2;
+}
+
+// prefix over each row of 16 lanes (lanes 16k..l)
 template <typename T>
-__device__ __forceinline__ void wave_scan_fwd(T& a, T& b)
+__device__ __forceinline__ void row_scan_fwd(T& a, T& b)
 {
     compose_dpp<kRowShr + 1, 0xf>(a, b);
     compose_dpp<kRowShr + 2, 0xf>(a, b);
     compose_dpp<kRowShr + 4, 0xf>(a, b);
     compose_dpp<kRowShr + 8, 0xf>(a, b);
-    compose_dpp<kRowBcast15, 0xa>(a, b);
-    compose_dpp<kRowBcast31, 0xc>(a, b);
 }
-
-// inclusive suffix (lanes l..63) over the wavefront
+// suffix over each row of 16 lanes (lanes l..16k+15)
 template <typename T>
-__device__ __forceinline__ void wave_scan_bwd(T& a, T& b, int lane)
+__device__ __forceinline__ void row_scan_bwd(T& a, T& b)
 {
     compose_dpp<kRowShl + 1, 0xf>(a, b);
     compose_dpp<kRowShl + 2, 0xf>(a, b);
     compose_dpp<kRowShl + 4, 0xf>(a, b);
     compose_dpp<kRowShl + 8, 0xf>(a, b);
-    // rows of 16 now hold row-local suffixes; fold in the rows above
-    const T a16 = readlane(a, 16), b16 = readlane(b, 16);
-    const T a32 = readlane(a, 32), b32 = readlane(b, 32);
-    const T a48 = readlane(a, 48), b48 = readlane(b, 48);
-    const T a23 = fma_rn(b32, a48, a32), b23 = b32 * b48;        // rows 2,3
-    const T a13 = fma_rn(b16, a23, a16), b13 = b16 * b23;        // rows 1..3
-    T ca = T(0), cb = T(1);
-    if (lane < 16) { ca = a13; cb = b13; }
-    else if (lane < 32) { ca = a23; cb = b23; }
-    else if (lane < 48) { ca = a48; cb = b48; }
-    a = fma_rn(b, ca, a);
+}
+
+// inclusive prefix (lanes 0..l) over the wavefront
+template <typename T>
+__device__ __forceinline__ void wave_scan_fwd(T& a, T& b)
+{
+    row_scan_fwd(a, b);
+    compose_dpp<kRowBcast15, 0xa>(a, b);
+    compose_dpp<kRowBcast31, 0xc>(a, b);
+}
+
+// inclusive suffix (lanes l..63) of three-component maps (a0 + a1 C, b)
+template <typename T>
+__device__ __forceinline__ void wave_scan_bwd3(T& a0, T& a1, T& b, int lane)
+{
+    compose3_dpp<kRowShl + 1, 0xf>(a0, a1, b);
+    compose3_dpp<kRowShl + 2, 0xf>(a0, a1, b);
+    compose3_dpp<kRowShl + 4, 0xf>(a0, a1, b);
+    compose3_dpp<kRowShl + 8, 0xf>(a0, a1, b);
+    const T p16 = readlane(a0, 16), q16 = readlane(a1, 16), b16 = readlane(b, 16);
+    const T p32 = readlane(a0, 32), q32 = readlane(a1, 32), b32 = readlane(b, 32);
+    const T p48 = readlane(a0, 48), q48 = readlane(a1, 48), b48 = readlane(b, 48);
+    const T p23 = fma_rn(b32, p48, p32), q23 = fma_rn(b32, q48, q32), b23 = b32 * b48;   // rows 2,3
+    const T p13 = fma_rn(b16, p23, p16), q13 = fma_rn(b16, q23, q16), b13 = b16 * b23;   // rows 1..3
+    T cp = T(0), cq = T(0), cb = T(1);
+    if (lane < 16) { cp = p13; cq = q13; cb = b13; }
+    else if (lane < 32) { cp = p23; cq = q23; cb = b23; }
+    else if (lane < 48) { cp = p48; cq = q48; cb = b48; }
+    a0 = fma_rn(b, cp, a0);
+    a1 = fma_rn(b, cq, a1);
     b = b * cb;
 }
 
@@ -186,45 +214,88 @@ __global__ void __launch_bounds__(256) k_xpivots(const T* __restrict__ r, T* __r
     }
 }
 
+// ---------------------------------------------------------- buffer I/O ----
+// Rows are read and written through buffer resources whose size is the row's
+// byte length (0 for a row outside the grid): the hardware range check returns
+// zero for loads past the end and drops such stores, so the accesses need no
+// branches and the compiler can count outstanding loads exactly (which keeps
+// the row-ahead prefetch in flight across the solve of the current row).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kBufWord3 = 0x00020000;   // 32-bit data format, gfx9 family
+
 template <typename T>
-__device__ __forceinline__ void load8(const T* __restrict__ row, int i0, int nx, bool vec, T (&v)[kSeg])
+__device__ __forceinline__ rsrc_t buf(const T* base, int nbytes)
 {
-    if (vec && i0 + kSeg <= nx) {
-        if constexpr (sizeof(T) == 4) {
-            const float4 x = *reinterpret_cast<const float4*>(row + i0);
-            const float4 y = *reinterpret_cast<const float4*>(row + i0 + 4);
-            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-            v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
-        } else {
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const double2 x = *reinterpret_cast<const double2*>(row + i0 + 2 * h);
-                v[2 * h] = x.x; v[2 * h + 1] = x.y;
-            }
-        }
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, nbytes, kBufWord3);
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+// (whole vectors are bit-cast: a bit cast of a single vector element is not
+// compiled correctly by this toolchain)
+
+// 8 consecutive values at byte offset voff with 16-byte accesses.  The row is
+// 16-byte aligned and its byte length a multiple of 16, so every access is
+// wholly inside or wholly outside the range.
+template <typename T>
+__device__ __forceinline__ void bload8(rsrc_t rs, int voff, T (&v)[kSeg])
+{
+    if constexpr (sizeof(T) == 4) {
+        const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
+        const f32x4 y = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, 0, 0));
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
     } else {
 #pragma unroll
-        for (int e = 0; e < kSeg; ++e) v[e] = (i0 + e < nx) ? row[i0 + e] : T(0);
+        for (int h = 0; h < kSeg / 2; ++h) {
+            const f64x2 x = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16 * h, 0, 0));
+            v[2 * h] = x.x;
+            v[2 * h + 1] = x.y;
+        }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void store8(T* __restrict__ row, int i0, int nx, bool vec, const T (&v)[kSeg])
+__device__ __forceinline__ void bstore8(rsrc_t rs, int voff, const T (&v)[kSeg])
 {
-    if (vec && i0 + kSeg <= nx) {
-        if constexpr (sizeof(T) == 4) {
-            *reinterpret_cast<float4*>(row + i0) = make_float4(v[0], v[1], v[2], v[3]);
-            *reinterpret_cast<float4*>(row + i0 + 4) = make_float4(v[4], v[5], v[6], v[7]);
-        } else {
-#pragma unroll
-            for (int h = 0; h < 4; ++h)
-                *reinterpret_cast<double2*>(row + i0 + 2 * h) = make_double2(v[2 * h], v[2 * h + 1]);
-        }
+    if constexpr (sizeof(T) == 4) {
+        const f32x4 x = {v[0], v[1], v[2], v[3]};
+        const f32x4 y = {v[4], v[5], v[6], v[7]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, x), rs, voff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, y), rs, voff + 16, 0, 0);
     } else {
 #pragma unroll
-        for (int e = 0; e < kSeg; ++e)
-            if (i0 + e < nx) row[i0 + e] = v[e];
+        for (int h = 0; h < kSeg / 2; ++h) {
+            const f64x2 x = {v[2 * h], v[2 * h + 1]};
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, x), rs, voff + 16 * h, 0, 0);
+        }
     }
+}
+
+// Rows without that alignment: per-value global accesses guarded by the row end.
+template <typename T>
+__device__ __forceinline__ void gload8(const T* __restrict__ row, int i0, int nx, T (&v)[kSeg])
+{
+#pragma unroll
+    for (int e = 0; e < kSeg; ++e) v[e] = (i0 + e < nx) ? row[i0 + e] : T(0);
+}
+template <typename T>
+__device__ __forceinline__ void gstore8(T* __restrict__ row, int i0, int nx, const T (&v)[kSeg])
+{
+#pragma unroll
+    for (int e = 0; e < kSeg; ++e)
+        if (i0 + e < nx) row[i0 + e] = v[e];
+}
+
+template <typename T>
+__device__ __forceinline__ T bload1(rsrc_t rs, int voff)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, 0, 0));
+    else
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, 0));
 }
 
 // Workgroup: max(TR, 256) threads = G line groups of TR threads.  A group owns
@@ -238,54 +309,99 @@ __device__ __forceinline__ void store8(T* __restrict__ row, int i0, int nx, bool
 // LDS.  At each chunk's interface row the planes E and Pf are written and the
 // state restarts.
 // LDS of one line group
+constexpr int kStripSrc = 32;   // point sources staged per strip (more: read per row)
+
 template <typename T, int TR, bool FUSE>
 struct XShared {
     T halo[2][2][TR];                        // segment edges of two rows: [row parity][first/last][seg]
-    T tot[2][TR / 64][2];                    // wavefront scan totals: [fwd/bwd][wave][value]
+    T totf[2][TR / 64][2];                   // wavefront totals by row parity: forward (a, b)
+    T totb[2][TR / 64][3];                   //   and backward (a0, a1, b)
     T y[FUSE ? 4 * kSeg * TR : 1];           // fused y-chunk state per column
+    T src_add[kStripSrc];                    // sources of the strip, in source order:
+    int src_pos[kStripSrc];                  //   value added to rho, row offset * 2^16 + column
+    int src_n;                               // count, or -1 when the strip has more than kStripSrc
 };
+
+// Stage the point sources that fall in rows [j0, j0 + RS) into LDS, in source
+// order (wavefront 0, 64 sources per pass, ballot-compacted), so that the row
+// loop reads them from LDS instead of global memory.
+template <typename T, int TR, bool FUSE>
+__device__ __forceinline__ void stage_sources(const XArgs<T>& A, int j0, int RS, int t,
+                                              XShared<T, TR, FUSE>& sh)
+{
+    if (t >= 64) return;
+    int n = 0;
+    for (int base = 0; base < A.nsrc; base += 64) {
+        const int q = base + t;
+        int id = -1;
+        T amp = T(0);
+        if (q < A.nsrc) { id = A.src_idx[q]; amp = A.src_amp[q]; }
+        const long long npts = (long long)A.nx * A.ny;
+        const int row = (id >= 0 && id < npts) ? id / A.nx : -1;
+        const bool hit = row >= j0 && row < j0 + RS;
+        const unsigned long long mask = __ballot(hit);
+        const int before = __popcll(mask & ((1ull << t) - 1ull));
+        if (hit && n + before < kStripSrc) {
+            sh.src_add[n + before] = A.rho_scale * A.tau2 * amp;
+            sh.src_pos[n + before] = ((row - j0) << 16) | (id - row * A.nx);
+        }
+        n += __popcll(mask);
+    }
+    if (t == 0) sh.src_n = n <= kStripSrc ? n : -1;
+}
 
 // One strip (rows_per_strip rows from strip * rows_per_strip) of one line group.
 // Every thread of the workgroup must call this with the same rows_per_strip
 // (it synchronises the workgroup twice per row).
 // STENCIL = false: the right-hand side of row j is rho_scale * (row j of A.u)
 // instead of the 5-point assembly (line solves of a given field).
-template <typename T, int TR, bool FUSE, bool STENCIL = true>
-__device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip, const int t,
-                                             XShared<T, TR, FUSE>& sh)
+template <typename T, int TR, bool FUSE, bool STENCIL, bool VEC>
+__device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int strip, const int t,
+                                                  XShared<T, TR, FUSE>& sh)
 {
     constexpr int E = kSeg;
     constexpr int NW = TR / 64;
     auto& s_halo = sh.halo;
-    auto& s_tot = sh.tot;
     const int lane = t & 63;
     const int wv = t >> 6;
     const int nx = A.nx, ny = A.ny, nseg = A.nseg;
-    const bool vec = A.vec != 0;
     const int RS = A.rows_per_strip;
     const int j0 = strip * RS;
     const int i0 = E * t;
     const bool act = t < nseg;
     const int L = act ? min(E, nx - i0) : 0;
 
-    T um[E], uc[E], u1[E], u2[E];   // rows j-1, j, j+1, j+2 of u^n
-    T rc[E], rn[E];                 // r of rows j, j+1
-    T qc = T(0), qn = T(0);         // entry pivots of rows j, j+1
+    // rolling rows of u^n (j-1 .. j+2), r and the entry pivots (j, j+1)
+    T ua[E], ub[E], uc0[E], ud[E];
+    T ra[E], rb[E];
+    T qa = T(0), qb = T(0);
 
-    auto load_u = [&](int row, T (&v)[E]) {
-        if (act && row >= 0 && row < ny) load8<T>(A.u + (size_t)row * nx, i0, nx, vec, v);
-        else {
+    const int voff = i0 * (int)sizeof(T);            // this lane's byte offset in a row
+    const int row_bytes = nx * (int)sizeof(T);
+    auto zero8 = [&](T (&v)[E]) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = T(0);
+        for (int e = 0; e < E; ++e) v[e] = T(0);
+    };
+    auto load_u = [&](int row, T (&v)[E]) {
+        const bool in = row >= 0 && row < ny;
+        if constexpr (VEC) {
+            bload8<T>(buf(A.u + (size_t)(in ? row : 0) * nx, in ? row_bytes : 0), voff, v);
+        } else {
+            if (act && in) gload8<T>(A.u + (size_t)row * nx, i0, nx, v);
+            else zero8(v);
         }
     };
     auto load_rq = [&](int row, T (&v)[E], T& q) {
-        if (act && row >= 0 && row < ny) {
-            load8<T>(A.r + (size_t)row * nx, i0, nx, vec, v);
+        const bool in = row >= 0 && row < ny;
+        if constexpr (VEC) {
+            bload8<T>(buf(A.r + (size_t)(in ? row : 0) * nx, in ? row_bytes : 0), voff, v);
+            q = bload1<T>(buf(A.qin + (size_t)(in ? row : 0) * nseg, in ? nseg * (int)sizeof(T) : 0),
+                          t * (int)sizeof(T));
+        } else if (act && in) {
+            gload8<T>(A.r + (size_t)row * nx, i0, nx, v);
             q = A.qin[(size_t)row * nseg + t];
         } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = T(0);
+            zero8(v);
             q = T(0);
         }
     };
@@ -312,20 +428,26 @@ __device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip,
     };
     if constexpr (FUSE) ystate_reset();
 
-    load_u(j0 - 1, um);
-    load_u(j0, uc);
-    load_u(j0 + 1, u1);
-    load_rq(j0, rc, qc);
-    put_halo(j0, uc);
-    put_halo(j0 + 1, u1);
+    if constexpr (STENCIL) stage_sources<T, TR, FUSE>(A, j0, RS, t, sh);
+    load_u(j0 - 1, ua);
+    load_u(j0, ub);
+    load_u(j0 + 1, uc0);
+    load_rq(j0, ra, qa);
+    put_halo(j0, ub);
     __syncthreads();
 
-    for (int it = 0; it < RS; ++it) {
+    // Row j = j0 + it.  um, uc, u1 hold rows j-1, j, j+1; u2 receives row j+2.
+    // rc, qc: row j; rn, qn receive row j+1.
+    auto row = [&](const int it, T (&um)[E], T (&uc)[E], T (&u1)[E], T (&u2)[E], T (&rc)[E], T (&rn)[E],
+                   T& qc, T& qn) {
         const int j = j0 + it;
         const bool live = j < ny;
         // prefetch
         load_u(live ? j + 2 : -1, u2);
         load_rq(live ? j + 1 : -1, rn, qn);
+        // edges of row j+1 (resident since the previous row) for the next row's stencil;
+        // the other parity buffer is read below, and row j-1's readers passed a barrier
+        if (live && j + 1 < ny) put_halo(j + 1, u1);
 
         // right-hand side of row j
         T rho[E];
@@ -333,110 +455,132 @@ __device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip,
             const int p = j & 1;
             const T west0 = (act && t > 0) ? s_halo[p][1][t - 1] : T(0);
             const T eastL = (t + 1 < nseg) ? s_halo[p][0][t + 1] : T(0);
+            // rho_scale * 2 r x == (2 rho_scale) * (r x) exactly: 2 and rho_scale
+            // (1 or 1/2) are powers of two
+            const T s2 = T(2) * A.rho_scale;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if constexpr (STENCIL) {
                     const T uw = (e == 0) ? west0 : uc[e - 1];
                     const T ue = (e == E - 1) ? eastL : uc[e + 1];
-                    rho[e] = A.rho_scale * (T(2) * rc[e] * (((uw + ue) + (um[e] + u1[e])) - T(4) * uc[e]));
+                    rho[e] = s2 * (rc[e] * (((uw + ue) + (um[e] + u1[e])) - T(4) * uc[e]));
                 } else {
                     rho[e] = A.rho_scale * uc[e];
                 }
             }
         }
-        if (live) {
-            for (int q = 0; q < A.nsrc; ++q) {
-                const int id = A.src_idx[q];
-                if (id >= 0 && id / nx == j) {
-                    const int i = id - j * nx - i0;
-                    const T add = A.rho_scale * A.tau2 * A.src_amp[q];
+        if constexpr (STENCIL) {
+            const int ns = sh.src_n;
+            if (ns > 0 && live) {
+                for (int q = 0; q < ns; ++q) {
+                    const int pos = sh.src_pos[q];
+                    if ((pos >> 16) == j - j0) {
+                        const int i = (pos & 0xffff) - i0;
+                        const T add = sh.src_add[q];
 #pragma unroll
-                    for (int e = 0; e < E; ++e)
-                        if (e == i) rho[e] += add;
+                        for (int e = 0; e < E; ++e)
+                            if (e == i) rho[e] += add;
+                    }
+                }
+            } else if (ns < 0 && live) {
+                for (int q = 0; q < A.nsrc; ++q) {
+                    const int id = A.src_idx[q];
+                    if (id >= 0 && id / nx == j) {
+                        const int i = id - j * nx - i0;
+                        const T add = A.rho_scale * A.tau2 * A.src_amp[q];
+#pragma unroll
+                        for (int e = 0; e < E; ++e)
+                            if (e == i) rho[e] += add;
+                    }
                 }
             }
         }
 
-        // local elimination of the segment from its entry pivot
-        T Ge[E], qe[E];
+        // local elimination of the segment from its entry pivot.  Nodes past the
+        // end of the line (e >= L) have r = 0 and rho = 0 (zero-filled loads): they
+        // get m = 1, q = 0, G = 0 and add nothing to the segment's maps, so no
+        // branch is needed.  A lane without nodes keeps the identity map (0, 1).
+        T Ge[E], qe[E], Qe[E];
         T fG, fQ, H, Ev;
         {
-            T q = qc, Gv = T(0), Qv = T(1), P = T(1), h = T(0), ee = T(0);
+            T q = qc, Gv = T(0), Qv = T(1), h = T(0), ee = T(0);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                if (e < L) {
-                    const T m = pivot_step<T>(rc[e], q);
-                    Gv = fma_rn(m, rho[e], q * Gv);
-                    Qv = q * Qv;
-                    h = fma_rn(P, Gv, h);
-                    ee = fma_rn(P, Qv, ee);
-                    P = P * q;
-                }
+                const T m = pivot_step<T>(rc[e], q);
+                const T P = Qv;                       // prod of q before node e
+                Gv = fma_rn(m, rho[e], q * Gv);
+                Qv = q * Qv;
+                h = fma_rn(P, Gv, h);
+                ee = fma_rn(P, Qv, ee);
                 Ge[e] = Gv;
-                qe[e] = (e < L) ? q : T(0);
+                qe[e] = q;
+                Qe[e] = Qv;
             }
-            fG = Gv; fQ = Qv; H = h; Ev = ee;     // no node: identity (0, 1)
+            fG = Gv; fQ = act ? Qv : T(1); H = h; Ev = ee;
+            if (L < E) {                              // partial segment: carry the last node's map
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (e == L - 1) { fG = Ge[e]; fQ = Qe[e]; }
+            }
         }
 
-        // forward scan across the line
-        T gin;
+        // Both scans across the line with one workgroup barrier.  The forward maps
+        // (g_out = fG + fQ g_in) are scanned inside the wavefront; the value C
+        // entering the wavefront is not known yet, so each lane's backward map
+        // a = H + Ev g_in = (H + Ev xa) + (Ev xb) C is scanned with C symbolic
+        // (components a0, a1).  After the barrier every wavefront combines the
+        // totals of all wavefronts: the carries C_k of every wavefront, and from
+        // them the backward totals (a0 + a1 C_k, b) and the value D below its last
+        // lane.
+        T gin, dbelow;
         {
+            const int par = j & 1;
             T a = fG, b = fQ;
             wave_scan_fwd(a, b);
-            if (lane == 63) { s_tot[0][wv][0] = a; s_tot[0][wv][1] = b; }
             const T xa = dpp<kWaveShr1>(T(0), a);
             const T xb = dpp<kWaveShr1>(T(1), b);
-            __syncthreads();
-            if (live && j + 2 < ny) put_halo(j + 2, u2);
-            T carry = T(0);
+            T a0 = fma_rn(Ev, xa, H), a1 = Ev * xb, bb = fQ;
+            if (!act) { a0 = T(0); a1 = T(0); bb = T(1); }
+            wave_scan_bwd3(a0, a1, bb, lane);
+            const T ya0 = dpp<kWaveShl1>(T(0), a0);
+            const T ya1 = dpp<kWaveShl1>(T(0), a1);
+            const T yb = dpp<kWaveShl1>(T(1), bb);
             if constexpr (NW > 1) {
-                T ta = (lane < NW) ? s_tot[0][lane < NW ? lane : 0][0] : T(0);
-                T tb = (lane < NW) ? s_tot[0][lane < NW ? lane : 0][1] : T(1);
-                compose_dpp<kRowShr + 1, 0xf>(ta, tb);
-                compose_dpp<kRowShr + 2, 0xf>(ta, tb);
-                compose_dpp<kRowShr + 4, 0xf>(ta, tb);
-                compose_dpp<kRowShr + 8, 0xf>(ta, tb);
-                carry = (wv > 0) ? readlane(ta, __builtin_amdgcn_readfirstlane(wv - 1)) : T(0);
+                if (lane == 63) { sh.totf[par][wv][0] = a; sh.totf[par][wv][1] = b; }
+                if (lane == 0) { sh.totb[par][wv][0] = a0; sh.totb[par][wv][1] = a1; sh.totb[par][wv][2] = bb; }
             }
-            gin = fma_rn(xb, carry, xa);
+            __syncthreads();
+            T C = T(0), D = T(0);
+            if constexpr (NW > 1) {
+                const int k = lane < NW ? lane : 0;
+                T fa = (lane < NW) ? sh.totf[par][k][0] : T(0);
+                T fb = (lane < NW) ? sh.totf[par][k][1] : T(1);
+                row_scan_fwd(fa, fb);                        // lane k: waves 0..k
+                const T Ck = dpp<kRowShr + 1, 0xf>(T(0), fa);  // lane k: value entering wave k
+                T ta = T(0), tb = T(1);
+                if (lane < NW) {
+                    ta = fma_rn(sh.totb[par][k][1], Ck, sh.totb[par][k][0]);
+                    tb = sh.totb[par][k][2];
+                }
+                row_scan_bwd(ta, tb);                        // lane k: waves k..NW-1
+                C = readlane(Ck, __builtin_amdgcn_readfirstlane(wv));
+                D = (wv + 1 < NW) ? readlane(ta, __builtin_amdgcn_readfirstlane(wv + 1)) : T(0);
+            }
+            gin = fma_rn(xb, C, xa);
+            dbelow = fma_rn(yb, D, fma_rn(ya1, C, ya0));
         }
 
-        // backward scan across the line
-        T dbelow;
-        {
-            T a = fma_rn(Ev, gin, H), b = fQ;
-            if (!act) { a = T(0); b = T(1); }
-            wave_scan_bwd(a, b, lane);
-            if (lane == 0) { s_tot[1][wv][0] = a; s_tot[1][wv][1] = b; }
-            const T ya = dpp<kWaveShl1>(T(0), a);
-            const T yb = dpp<kWaveShl1>(T(1), b);
-            __syncthreads();
-            T carry = T(0);
-            if constexpr (NW > 1) {
-                T ta = (lane < NW) ? s_tot[1][lane < NW ? lane : 0][0] : T(0);
-                T tb = (lane < NW) ? s_tot[1][lane < NW ? lane : 0][1] : T(1);
-                compose_dpp<kRowShl + 1, 0xf>(ta, tb);
-                compose_dpp<kRowShl + 2, 0xf>(ta, tb);
-                compose_dpp<kRowShl + 4, 0xf>(ta, tb);
-                compose_dpp<kRowShl + 8, 0xf>(ta, tb);
-                carry = (wv + 1 < NW) ? readlane(ta, __builtin_amdgcn_readfirstlane(wv + 1)) : T(0);
-            }
-            dbelow = fma_rn(yb, carry, ya);
-        }
-
-        // back substitution, store
+        // back substitution, store (tail nodes give 0 and feed q = 0 into the last node)
         T wout[E];
         {
-            T x = dbelow, Q = T(1);
-            T Qe[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e) { Q = Q * qe[e]; Qe[e] = Q; }
+            T x = dbelow;
 #pragma unroll
             for (int e = E - 1; e >= 0; --e) {
-                if (e < L) x = fma_rn(qe[e], x, fma_rn(Qe[e], gin, Ge[e]));
+                x = fma_rn(qe[e], x, fma_rn(Qe[e], gin, Ge[e]));
                 wout[e] = x;
             }
-            if (live && act) store8<T>(A.w + (size_t)j * nx, i0, nx, vec, wout);
+            if constexpr (VEC) bstore8<T>(buf(A.w + (size_t)(live ? j : 0) * nx, live ? row_bytes : 0), voff, wout);
+            else if (live && act) gstore8<T>(A.w + (size_t)j * nx, i0, nx, wout);
         }
 
         if constexpr (FUSE) {
@@ -474,12 +618,26 @@ __device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip,
             }
         }
 
-        qc = qn;
+    };
+
+    for (int it = 0; it < RS; ++it) {
+        row(it, ua, ub, uc0, ud, ra, rb, qa, qb);
+        qa = qb;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            um[e] = uc[e]; uc[e] = u1[e]; u1[e] = u2[e]; rc[e] = rn[e];
+            ua[e] = ub[e]; ub[e] = uc0[e]; uc0[e] = ud[e]; ra[e] = rb[e];
         }
     }
+}
+
+// Rows 16-byte aligned with a multiple of 8 values take the 16-byte accesses;
+// the choice is uniform over the launch.
+template <typename T, int TR, bool FUSE, bool STENCIL = true>
+__device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip, const int t,
+                                             XShared<T, TR, FUSE>& sh)
+{
+    if (A.vec) xsweep_strip_impl<T, TR, FUSE, STENCIL, true>(A, strip, t, sh);
+    else xsweep_strip_impl<T, TR, FUSE, STENCIL, false>(A, strip, t, sh);
 }
 
 template <typename T, int TR, bool FUSE, bool STENCIL = true>

@@ -100,6 +100,33 @@ def test_adjoint_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_shared_receiver_nodes(adw, oracle_lib, dtype):
+    """300 receivers (more than one 256-wide tile) with repeated nodes, one of them on a
+    source node, and one offset outside the grid."""
+    c = case(dtype, nx=64, ny=40, nsteps=30, seed=11)
+    nx, ny = c["nx"], c["ny"]
+    rng = np.random.default_rng(3)
+    base = rng.integers(0, nx * ny, size=120).astype(np.int32)
+    ri = np.concatenate([base, base[:100], base[:60], base[:19], c["src_idx"][:1]]).astype(np.int32)
+    rng.shuffle(ri)
+    ri = np.concatenate([ri, np.array([nx * ny + 5], np.int32)])
+    assert ri.size == 301
+    c["rec_idx"] = ri
+    c["target"] = (rng.standard_normal((c["nsteps"], ri.size)) * 1e-4).astype(npdt(dtype))
+    say(f"shared receivers {dtype}")
+    gk, ga, tr = gpu_grad(adw, c, 7)
+    valid = ri < nx * ny
+    assert np.isnan(tr[:, ~valid]).all()
+    c2 = dict(c, rec_idx=ri[valid], target=c["target"][:, valid])
+    rk, ra, rtr = oracle_grad(oracle_lib, c2)
+    tol = 1e-10 if dtype == "f64" else 2e-3
+    say(f"  rel L2: traces {rel_l2(tr[:, valid], rtr):.3e}  dJ/dkappa {rel_l2(gk, rk):.3e}  dJ/dsource {rel_l2(ga, ra):.3e}")
+    assert rel_l2(tr[:, valid], rtr) <= (1e-12 if dtype == "f64" else 1e-5)
+    assert rel_l2(gk, rk) <= tol
+    assert rel_l2(ga, ra) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_checkpoint_interval_does_not_change_the_gradient(adw, dtype):
     c = case(dtype, nx=64, ny=48, nsteps=37, seed=4)
     say(f"checkpoint invariance {dtype}")
