@@ -33,9 +33,11 @@ HBM_PEAK_GBPS = 8000.0
 #   y_reduce        reads w and r                                  2E
 #   x_sweep_rhs_y_reduce  the x-sweep with the y-chunk elimination fused: 3E
 # The whole step's two-pass minimum is 8E (32 B/node in FP32).
+#   fused_step      the one-pass step: reads u^n, r, u^{n-1}, writes u^{n+1}  4E
 ALG_BYTES_PER_NODE = {"x_sweep_rhs": 3, "x_sweep_rhs_y_reduce": 3, "y_solve_update": 5,
-                      "y_reduce": 2}
-STEP_BYTES_PER_NODE = 8
+                      "y_reduce": 2, "fused_step": 4}
+STEP_BYTES_PER_NODE = 8          # two-pass step
+FUSED_STEP_BYTES_PER_NODE = 4    # one-pass step
 
 WORKLOADS = {
     "c3": ("c3_heterogeneous_ricker_8192x8192_f32", "f32", 8192),
@@ -235,33 +237,56 @@ def main():
             return {}
         return dict(src, src_amp=amp[first:first + count])
 
-    # warm-up, then exactly `steps` timed steps bracketed by synchronisation
-    if args.warmup:
-        a, b = wave.step(a, b, args.warmup, **srcs(0, args.warmup))
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    ev0.record()
-    a, b = wave.step(a, b, args.steps, **srcs(args.warmup, args.steps))
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1)
-    npts = prob.nx * prob.ny
-    value = npts * args.steps / (ms / 1e3) / 1e6
-    if not torch.isfinite(b).all():
-        print("bench.py: non-finite field after the timed steps", file=sys.stderr)
-        sys.exit(1)
-
-    # per-kernel durations (events around every launch, same stream)
-    psteps = max(1, min(args.profile_steps, args.steps))
-    (a, b), kms = wave.profile(a, b, psteps, **srcs(0, psteps))
     esz = 4 if dtype == "f32" else 8
-    dom = max((k for k in kms if k in ALG_BYTES_PER_NODE), key=lambda k: kms[k])
-    alg_bytes = ALG_BYTES_PER_NODE[dom] * esz * npts
-    achieved = alg_bytes / (kms[dom] / 1e3) / 1e9
-    traffic = load_traffic(name, dom, alg_bytes)
+    npts = prob.nx * prob.ny
+
+    def measure(a, b):
+        """warm-up, then exactly `steps` timed steps bracketed by synchronisation, then
+        per-kernel durations (events around every launch, same stream)"""
+        if args.warmup:
+            a, b = wave.step(a, b, args.warmup, **srcs(0, args.warmup))
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        ev0.record()
+        a, b = wave.step(a, b, args.steps, **srcs(args.warmup, args.steps))
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = ev0.elapsed_time(ev1)
+        if not torch.isfinite(b).all():
+            print("bench.py: non-finite field after the timed steps", file=sys.stderr)
+            sys.exit(1)
+        psteps = max(1, min(args.profile_steps, args.steps))
+        (a, b), kms = wave.profile(a, b, psteps, **srcs(0, psteps))
+        dom = max((k for k in kms if k in ALG_BYTES_PER_NODE), key=lambda k: kms[k])
+        alg_bytes = ALG_BYTES_PER_NODE[dom] * esz * npts
+        achieved = alg_bytes / (kms[dom] / 1e3) / 1e9
+        info = wave.info()
+        per_node = FUSED_STEP_BYTES_PER_NODE if info["fused_step"] else STEP_BYTES_PER_NODE
+        step_gbps = per_node * esz * npts * args.steps / (ms / 1e3) / 1e9
+        res = {"value": round(npts * args.steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / args.steps, 5),
+               "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                            "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                            "traffic": load_traffic(name, dom, alg_bytes)},
+               "step_algorithmic_bytes_per_node": per_node * esz,
+               "step_algorithmic_GBps": round(step_gbps, 1),
+               "step_frac_of_peak": round(step_gbps / HBM_PEAK_GBPS, 4),
+               "kernel_ms": {k: round(v, 5) for k, v in kms.items()},
+               "launch_plan": info, "wall_s_timed": round(wall, 4)}
+        return a, b, res
+
+    a, b, main = measure(a, b)
+    two_pass = None
+    if main["launch_plan"]["fused_step"]:
+        wave.set_tuning(fused_step=False)
+        a, b, two_pass = measure(a, b)
+        two_pass.pop("launch_plan")
+        wave.set_tuning(fused_step=True)
+    value = main["value"]
+    ms = main["ms_per_step"] * args.steps
 
     # achievable copy bandwidth on this GPU (1 GiB read + 1 GiB write)
     x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -278,15 +303,14 @@ def main():
     copy_gbps = 2 * x.numel() * 4 * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
     del x, y
 
-    step_gbps = STEP_BYTES_PER_NODE * esz * npts * args.steps / (ms / 1e3) / 1e9
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": value,
         "unit": "Mpts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 5),
+        "ms_per_step": main["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -295,24 +319,28 @@ def main():
         "config": {"workload": name, "nx": prob.nx, "ny": prob.ny,
                    "coefficient": "per-node" if prob.c is not None else "constant",
                    "source": "ricker point source" if src else "none",
-                   "launch_plan": wave.info()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic},
-        "step_algorithmic_GBps": round(step_gbps, 1),
-        "step_frac_of_peak": round(step_gbps / HBM_PEAK_GBPS, 4),
-        "kernel_ms": {k: round(v, 5) for k, v in kms.items()},
+                   "step": "one-pass" if main["launch_plan"]["fused_step"] else "two-pass",
+                   "launch_plan": main["launch_plan"]},
+        "roofline": main["roofline"],
+        "step_algorithmic_bytes_per_node": main["step_algorithmic_bytes_per_node"],
+        "step_algorithmic_GBps": main["step_algorithmic_GBps"],
+        "step_frac_of_peak": main["step_frac_of_peak"],
+        "kernel_ms": main["kernel_ms"],
+        "two_pass": two_pass,
         "copy_GBps": round(copy_gbps, 1),
         "create_ms": round(create_ms, 2),
-        "wall_s_timed": round(wall, 4),
+        "wall_s_timed": main["wall_s_timed"],
     }
     wave.close()
     del a, b
     torch.cuda.empty_cache()
+    tp_value = two_pass["value"] if two_pass else value
     if not args.no_batch:
         out["batched"] = bench_batched(adw, torch, args.steps, args.warmup, value)
+        out["batched"]["vs_two_pass"] = round(out["batched"]["value"] / tp_value, 4)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(adw, torch, value)
+        out["adjoint"]["vs_two_pass"] = round(out["adjoint"]["value"] / tp_value, 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(out), flush=True)

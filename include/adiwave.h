@@ -246,6 +246,9 @@ typedef struct {
     int y_chunks;             /* number of chunks per y-line */
     int kernels_per_step;     /* launches queued per ADI step */
     size_t workspace_bytes;   /* device bytes owned by the handle */
+    int fused_step;           /* 1: adi_wave_step runs the one-pass step (FP32) */
+    int fused_allowed;        /* 1: the one-pass step's truncation bound holds (FP32) */
+    double r_max;             /* largest r = dt^2 kappa / (2 h^2) (FP32 handles) */
 } adi_wave_info;
 
 adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
@@ -258,6 +261,8 @@ typedef struct {
     int x_rows_per_strip;     /* >= 1 (unfused plans; a fused strip is one y-chunk) */
     int y_fused;              /* 1 = fuse the y-chunk elimination into the x-sweep, 2 = separate */
     int y_chunk_rows;         /* 16 or 32 */
+    int fused_step;           /* 1 = one-pass step when allowed (else ADI_EUNSUPPORTED),
+                                 2 = exact two-pass step, 0 = keep */
 } adi_tuning;
 adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t);
 

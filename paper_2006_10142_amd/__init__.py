@@ -233,11 +233,14 @@ class Wave:
         return {f: getattr(inf, f) for f, _ in _lib.AdiWaveInfo._fields_}
 
     def set_tuning(self, x_threads_per_line=0, x_rows_per_strip=0, y_fused=None,
-                   y_chunk_rows=0):
-        """Override the launch plan (0 / None keeps the current value)."""
+                   y_chunk_rows=0, fused_step=None):
+        """Override the launch plan (0 / None keeps the current value).  fused_step:
+        True = one-pass step (FP32, when its truncation bound holds), False = exact
+        two-pass step."""
         self._sync_stream()
         f = 0 if y_fused is None else (1 if y_fused else 2)
-        t = _lib.AdiTuning(x_threads_per_line, x_rows_per_strip, f, y_chunk_rows)
+        fs = 0 if fused_step is None else (1 if fused_step else 2)
+        t = _lib.AdiTuning(x_threads_per_line, x_rows_per_strip, f, y_chunk_rows, fs)
         _lib.check(_lib.load().adi_wave_set_tuning(self._h, ctypes.byref(t)))
 
     def close(self):

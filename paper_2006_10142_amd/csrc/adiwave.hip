@@ -13,6 +13,7 @@
 
 #include "adiwave.h"
 #include "kernels.hpp"
+#include "fused.hpp"
 
 using namespace adw;
 
@@ -233,6 +234,11 @@ struct adi_wave_s {
     YScanPlan yq{};
     size_t bytes = 0;
     adi_adjoint_s* adj = nullptr;   // created by the first adjoint forward run
+    // one-pass step (FP32): allowed when the truncation bound holds for the
+    // largest r; mode 0 = automatic, 1 = on when allowed, 2 = off
+    float rmax = 0.f;
+    int fused_ok = 0, fused_mode = 0, fstep = 0;
+    int f_wt = 0, f_tx = 0, f_tiles = 0, f_grid = 0;
 };
 
 namespace {
@@ -412,6 +418,44 @@ adi_status static_planes(adi_wave_s* w)
     return ADI_OK;
 }
 
+// One-pass step: the truncation error of a step is at most 4 qs^(Ky+1) max|w|
+// (see fused.hpp); it is enabled only when that is below 2^-24.
+bool fused_bound_holds(double rm)
+{
+    if (!(rm >= 0.0) || !std::isfinite(rm)) return false;
+    const double qs = rm > 0.0 ? (1.0 + 2.0 * rm - std::sqrt(1.0 + 4.0 * rm)) / (2.0 * rm) : 0.0;
+    return 4.0 * std::pow(qs, kFuKy + 1) <= std::ldexp(1.0, -24);
+}
+
+void fused_plan(adi_wave_s* w)
+{
+    w->fused_ok = (w->dtype == ADI_F32 && w->nx % 4 == 0 && fused_bound_holds(w->rmax)) ? 1 : 0;
+    const bool autoon = (long long)w->nx * w->ny >= (1LL << 16);
+    w->fstep = w->fused_ok && (w->fused_mode == 1 || (w->fused_mode == 0 && autoon)) ? 1 : 0;
+    const int tx = (w->nx + kFuWmax - 1) / kFuWmax;
+    w->f_wt = ((w->nx + tx - 1) / tx + 7) / 8 * 8;
+    w->f_tx = (w->nx + w->f_wt - 1) / w->f_wt;
+    w->f_tiles = w->f_tx * ((w->ny + kFuHt - 1) / kFuHt);
+    w->f_grid = (w->f_tiles + 7) / 8 * 8;
+}
+
+// largest r of an FP32 handle (synchronises the stream); X is free scratch here
+adi_status measure_rmax(adi_wave_s* w)
+{
+    const long long n = (long long)w->nx * w->ny;
+    ADI_HIP(hipMemsetAsync(w->X, 0, sizeof(unsigned int), w->stream));
+    const int grid = (int)std::min<long long>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_rmax, dim3(grid), dim3(256), 0, w->stream, static_cast<const float*>(w->r), n,
+                       static_cast<unsigned int*>(w->X));
+    ADI_LAUNCHED("rmax");
+    unsigned int bits = 0;
+    ADI_HIP(hipMemcpyAsync(&bits, w->X, sizeof(bits), hipMemcpyDeviceToHost, w->stream));
+    ADI_HIP(hipStreamSynchronize(w->stream));
+    std::memcpy(&w->rmax, &bits, sizeof(bits));
+    fused_plan(w);
+    return ADI_OK;
+}
+
 template <typename T>
 adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared)
 {
@@ -425,15 +469,47 @@ adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared
     hipLaunchKernelGGL((k_xpivots<T>), dim3((w->ny + 255) / 256), dim3(256), 0, w->stream,
                        static_cast<const T*>(w->r), static_cast<T*>(w->qin), w->nx, w->ny, w->nseg);
     ADI_LAUNCHED("x_pivots");
+    if constexpr (sizeof(T) == 4) {
+        if (adi_status s = measure_rmax(w)) return s;
+    }
     return static_planes<T>(w);
 }
 
+adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const adi_source* f, int k)
+{
+    FArgs a{};
+    a.uc = static_cast<const float*>(u_curr);
+    a.up = static_cast<float*>(u_prev);
+    a.r = static_cast<const float*>(w->r);
+    a.qin = static_cast<const float*>(w->qin);
+    a.nx = w->nx;
+    a.ny = w->ny;
+    a.nseg = w->nseg;
+    a.wt = w->f_wt;
+    a.tiles_x = w->f_tx;
+    a.tiles = w->f_tiles;
+    a.xcd_map = 1;
+    a.tau2 = (float)(w->dt * w->dt);
+    if (f && f->count > 0) {
+        a.nsrc = f->count;
+        a.src_idx = f->idx;
+        a.src_amp = static_cast<const float*>(f->amp) + (size_t)k * f->count;
+    }
+    hipLaunchKernelGGL(k_fused, dim3(w->f_grid), dim3(1024), 0, w->stream, a);
+    ADI_LAUNCHED("fused_step");
+    return ADI_OK;
+}
+
+// allow_fused = false keeps the exact two-pass step (the adjoint recomputes
+// its forward run with that path and needs the same trajectory)
 template <typename T>
 adi_status do_step(adi_wave_s* w, void** u_prev, void** u_curr, const adi_source* f,
-                   const adi_receivers* rec, int nsteps)
+                   const adi_receivers* rec, int nsteps, bool allow_fused = true)
 {
+    const bool fused = sizeof(T) == 4 && allow_fused && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
     for (int k = 0; k < nsteps; ++k) {
-        adi_status s = queue_solve<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1), nullptr);
+        adi_status s = fused ? queue_fused(w, *u_curr, *u_prev, f, k)
+                             : queue_solve<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1), nullptr);
         if (s != ADI_OK) return s;
         if (rec && rec->count > 0) {
             hipLaunchKernelGGL((k_record<T>), dim3((rec->count + 255) / 256), dim3(256), 0, w->stream,
@@ -600,8 +676,11 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->y_fused = w->xp.fuse;
     info->y_chunk_rows = w->M;
     info->y_chunks = w->K;
-    info->kernels_per_step = w->xp.fuse ? 3 : 4;
+    info->kernels_per_step = w->fstep ? 1 : (w->xp.fuse ? 3 : 4);
     info->workspace_bytes = w->bytes;
+    info->fused_step = w->fstep;
+    info->fused_allowed = w->fused_ok;
+    info->r_max = w->dtype == ADI_F32 ? (double)w->rmax : 0.0;
     return ADI_OK;
 }
 
@@ -621,6 +700,13 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
         return fail(ADI_EUNSUPPORTED, "fused y-reduction does not fit in LDS for this plan");
     const int M = t->y_chunk_rows > 0 ? t->y_chunk_rows : w->M;
     if (M != 16 && M != 32) return fail(ADI_EINVAL, "y_chunk_rows must be 16 or 32");
+    if (t->fused_step < 0 || t->fused_step > 2) return fail(ADI_EINVAL, "fused_step must be 0, 1 or 2");
+    if (t->fused_step == 1 && !w->fused_ok)
+        return fail(ADI_EUNSUPPORTED, "the one-pass step needs FP32, nx % 4 == 0 and r <= 0.18 everywhere");
+    if (t->fused_step > 0) {
+        w->fused_mode = t->fused_step;
+        fused_plan(w);
+    }
     if (xp.fuse && (M != w->M || !w->xp.fuse)) xp.frs = fused_rows(M);
     w->xp = xp;
     if (M != w->M) {
@@ -647,16 +733,37 @@ adi_status adi_wave_profile(adi_wave_t w, void** u_prev, void** u_curr, const ad
     adi_status st = ADI_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) { st = fail(ADI_EHIP, "hipEventCreate failed"); break; }
+    const bool fused = w->dtype == ADI_F32 && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
     for (int k = 0; k < nsteps && st == ADI_OK; ++k) {
         hipEvent_t* e = &ev[(size_t)k * 5];
-        st = w->dtype == ADI_F32
-                 ? queue_solve<float>(w, *u_curr, *u_prev, *u_prev, 2.f, -1.f, f, k, 1.f, e)
-                 : queue_solve<double>(w, *u_curr, *u_prev, *u_prev, 2.0, -1.0, f, k, 1.0, e);
+        if (fused) {
+            if (hipEventRecord(e[0], w->stream) != hipSuccess) st = fail(ADI_EHIP, "hipEventRecord failed");
+            if (st == ADI_OK) st = queue_fused(w, *u_curr, *u_prev, f, k);
+            if (st == ADI_OK && hipEventRecord(e[1], w->stream) != hipSuccess)
+                st = fail(ADI_EHIP, "hipEventRecord failed");
+        } else {
+            st = w->dtype == ADI_F32
+                     ? queue_solve<float>(w, *u_curr, *u_prev, *u_prev, 2.f, -1.f, f, k, 1.f, e)
+                     : queue_solve<double>(w, *u_curr, *u_prev, *u_prev, 2.0, -1.0, f, k, 1.0, e);
+        }
         if (st == ADI_OK) std::swap(*u_prev, *u_curr);
     }
     if (st == ADI_OK && hipStreamSynchronize(w->stream) != hipSuccess)
         st = fail(ADI_EHIP, "stream synchronise failed");
-    if (st == ADI_OK) {
+    if (st == ADI_OK && fused) {
+        double acc = 0.0;
+        for (int k = 0; k < nsteps && st == ADI_OK; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[(size_t)k * 5], ev[(size_t)k * 5 + 1]) != hipSuccess)
+                st = fail(ADI_EHIP, "hipEventElapsedTime failed");
+            acc += ms;
+        }
+        if (st == ADI_OK) {
+            ms_per_kernel[0] = acc / nsteps;
+            if (names) names[0] = "fused_step";
+            *nkinds = 1;
+        }
+    } else if (st == ADI_OK) {
         double acc[4] = {0, 0, 0, 0};
         for (int k = 0; k < nsteps && st == ADI_OK; ++k)
             for (int q = 0; q < 4; ++q) {

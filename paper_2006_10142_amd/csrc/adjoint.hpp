@@ -223,7 +223,7 @@ adi_status adj_forward(adi_wave_s* w, const void* u_prev, const void* u_curr, co
             rc = *rec;
             rc.traces = static_cast<char*>(rec->traces) + (size_t)c * K * rec->count * sizeof(T);
         }
-        if (adi_status s = do_step<T>(w, &p, &q, f ? &sc : nullptr, rec ? &rc : nullptr, n)) return s;
+        if (adi_status s = do_step<T>(w, &p, &q, f ? &sc : nullptr, rec ? &rc : nullptr, n, false)) return s;
     }
     return ADI_OK;
 }

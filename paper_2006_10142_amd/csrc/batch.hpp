@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep_batch(BatchArgs
 {
     constexpr int G = (TR >= 256 ? TR : 256) / TR;
     __shared__ XShared<T, TR, true> sh[G];
-    const int g = threadIdx.x / TR;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / TR);
     const int t = threadIdx.x - g * TR;
     for (int base = blockIdx.x * G; base < B.nitems; base += gridDim.x * G) {
         const int it = base + g;

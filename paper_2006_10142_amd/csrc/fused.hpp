@@ -1,0 +1,346 @@
+// fused.hpp -- the whole ADI step in one pass (FP32): right-hand side, x-lines,
+// y-lines and the update of each output tile from u^n, u^{n-1} and r, without
+// writing the x-sweep result to memory.  Included by adiwave.hip.
+//
+// Truncated line solves.  Every line system -r x_{i-1} + (1 + 2r) x_i - r x_{i+1}
+// = b is strictly diagonally dominant, and all its elimination pivots q lie in
+// [0, qs], qs = (1 + 2 rm - sqrt(1 + 4 rm)) / (2 rm) the fixed point of the pivot
+// map at the largest coefficient rm.  Solving the line on a window whose carries
+// are set to zero at its ends (x-lines: the full-line elimination with the
+// forward carry entering the window and the back-substitution value leaving it
+// replaced by 0; y-lines: the window's own system with zero values beyond it)
+// changes the solution at distance d from a cut by at most qs^d max|x|: the
+// dropped carry is multiplied by one pivot per node it crosses.  Output nodes are
+// 17 columns from the x-cuts and 9 rows from the y-cuts, and the y-solve does not
+// amplify errors of its right-hand side in the max norm (its inverse has norm
+// <= 1), so one step differs from the exact two-pass step by at most
+//     2 qs^17 max|w| + 2 qs^9 max|d|  <=  4 qs^9 max|w|,
+// which the host keeps below 2^-24 (half an FP32 ulp) by enabling this path only
+// when rm is small enough (rm <= 0.18); otherwise the exact path runs.
+//
+// A tile is Wt output columns (a multiple of 8, <= 480) by 64 output rows.
+//   Phase 1: x-lines of the 80 rows [r0 - 8, r0 + 72), each on the column window
+//            [c0 - 16, c0 + Wt + 16): one wavefront per row, 8 nodes per lane, the
+//            segment scheme of xsweep.hpp with the full-line entry pivots; the Wt
+//            central values of w go to LDS (80 x Wt).
+//   Phase 2: y-lines: two windows of 48 rows per column ([r0 - 8, r0 + 40) and
+//            [r0 + 24, r0 + 72)), one thread each, Thomas in registers; the 32
+//            central rows of d replace w in LDS.
+//   Phase 3: u^{n+1} = 2 u^n - u^{n-1} + d over the tile, written over u^{n-1}
+//            (each node of u^{n-1} is read only by the tile that owns it).
+// Rows and columns outside the grid read as zero through the buffer range checks:
+// such nodes have r = 0 and decouple, which is the zero Dirichlet boundary.
+
+namespace adw {
+
+constexpr int kFuKx = 16;           // x-halo columns on each side
+constexpr int kFuKy = 8;            // y-halo rows on each side
+constexpr int kFuHb = 32;           // output rows per y-window
+constexpr int kFuNb = kFuHb + 2 * kFuKy;   // rows of a y-window (48)
+constexpr int kFuHt = 2 * kFuHb;    // output rows per tile (64)
+constexpr int kFuRows = kFuHt + 2 * kFuKy;   // x-rows per tile (80)
+constexpr int kFuWmax = 64 * kSeg - 2 * kFuKx;   // widest tile (480)
+constexpr int kFuSrc = 32;          // point sources staged per tile
+constexpr int kFuOOB = 0x40000000;  // byte offset beyond every buffer range used here
+                                    // (grids hold at most 2^27 values, 2^29 bytes)
+
+struct FArgs {
+    const float* uc;     // u^n
+    float* up;           // u^{n-1} in, u^{n+1} out
+    const float* r;
+    const float* qin;    // full-line entry pivot of every 8-node x-segment
+    int nx, ny, nseg;
+    int wt;              // output columns per tile (multiple of 8)
+    int tiles_x, tiles;  // tiles across, total tiles
+    int xcd_map;         // 1: block -> tile map that keeps neighbours on one XCD
+    float tau2;
+    int nsrc;
+    const int* src_idx;
+    const float* src_amp;
+};
+
+struct FShared {
+    float w[kFuRows * kFuWmax];
+    float src_add[kFuSrc];
+    int src_pos[kFuSrc];   // (x-row << 16) | window column
+    int src_n;             // -1: more than kFuSrc in this tile
+};
+
+// inclusive suffix (lanes l..63) of two-component affine maps over the wavefront
+__device__ __forceinline__ void wave_scan_bwd2(float& a, float& b, int lane)
+{
+    row_scan_bwd(a, b);
+    const float a16 = readlane(a, 16), b16 = readlane(b, 16);
+    const float a32 = readlane(a, 32), b32 = readlane(b, 32);
+    const float a48 = readlane(a, 48), b48 = readlane(b, 48);
+    const float a23 = fma_rn(b32, a48, a32), b23 = b32 * b48;
+    const float a13 = fma_rn(b16, a23, a16), b13 = b16 * b23;
+    float ca = 0.f, cb = 1.f;
+    if (lane < 16) { ca = a13; cb = b13; }
+    else if (lane < 32) { ca = a23; cb = b23; }
+    else if (lane < 48) { ca = a48; cb = b48; }
+    a = fma_rn(b, ca, a);
+    b = b * cb;
+}
+
+__global__ void __launch_bounds__(1024) k_fused(FArgs A)
+{
+    __shared__ FShared sh;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    // block -> tile: with xcd_map, the blocks of one XCD (b mod 8) take one
+    // contiguous band of tiles, so tiles that share halo rows share an L2
+    int tile = blockIdx.x;
+    if (A.xcd_map) tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (tile >= A.tiles) return;
+    const int nx = A.nx, ny = A.ny, wt = A.wt;
+    const int c0 = (tile % A.tiles_x) * wt;
+    const int r0 = (tile / A.tiles_x) * kFuHt;
+    const int nl = (wt + 2 * kFuKx) / kSeg;             // lanes of the x-window
+    const long long npts = (long long)nx * ny;
+
+    // ---- point sources of the tile's x-rows and x-window, in source order
+    if (t < 64) {
+        int n = 0;
+        for (int base = 0; base < A.nsrc; base += 64) {
+            const int qq = base + t;
+            int id = -1;
+            float amp = 0.f;
+            if (qq < A.nsrc) { id = A.src_idx[qq]; amp = A.src_amp[qq]; }
+            const int row = (id >= 0 && id < npts) ? id / nx : -1;
+            const int col = row >= 0 ? id - row * nx : 0;
+            const int xr = row - (r0 - kFuKy);
+            const int wc = col - (c0 - kFuKx);
+            const bool hit = row >= 0 && xr >= 0 && xr < kFuRows && wc >= 0 && wc < nl * kSeg;
+            const unsigned long long mask = __ballot(hit);
+            const int before = __popcll(mask & ((1ull << t) - 1ull));
+            if (hit && n + before < kFuSrc) {
+                sh.src_add[n + before] = A.tau2 * amp;
+                sh.src_pos[n + before] = (xr << 16) | wc;
+            }
+            n += __popcll(mask);
+        }
+        if (t == 0) sh.src_n = n <= kFuSrc ? n : -1;
+    }
+    __syncthreads();
+
+    // ---------------------------------------------------------- phase 1: x
+    {
+        const bool inwin = lane < nl;
+        const int seg = (c0 - kFuKx) / kSeg + lane;        // full-line segment index
+        const int col0 = seg * kSeg;
+        const int voff = inwin ? col0 * 4 : kFuOOB;
+        const int qoff = inwin ? seg * 4 : kFuOOB;           // negative segments wrap past the row
+        const int eoff = (lane == 0) ? (c0 - kFuKx - 1) * 4 : (lane == nl - 1) ? (c0 + wt + kFuKx) * 4 : kFuOOB;
+        const int row_bytes = nx * 4;
+        const int xr0 = wv * (kFuRows / 16);               // 5 consecutive x-rows per wavefront
+        float um[kSeg], uc[kSeg], u1[kSeg], u2[kSeg], rc[kSeg], rn[kSeg];
+        float eM, eC, e1, e2, qc, qn;
+        auto row_ok = [&](int j) { return j >= 0 && j < ny; };
+        auto load_u = [&](int j, float (&v)[kSeg], float& e) {
+            const bool ok = row_ok(j);
+            const rsrc_t rs = buf(A.uc + (size_t)(ok ? j : 0) * nx, ok ? row_bytes : 0);
+            bload8<float>(rs, voff, v);
+            e = bload1<float>(rs, eoff);
+        };
+        auto load_r = [&](int j, float (&v)[kSeg], float& q) {
+            const bool ok = row_ok(j);
+            bload8<float>(buf(A.r + (size_t)(ok ? j : 0) * nx, ok ? row_bytes : 0), voff, v);
+            q = bload1<float>(buf(A.qin + (size_t)(ok ? j : 0) * A.nseg, ok ? A.nseg * 4 : 0), qoff);
+        };
+        int j = r0 - kFuKy + xr0;
+        load_u(j - 1, um, eM);
+        load_u(j, uc, eC);
+        load_u(j + 1, u1, e1);
+        load_r(j, rc, qc);
+        const int ns = sh.src_n;
+        for (int it = 0; it < kFuRows / 16; ++it, ++j) {
+            const int xr = xr0 + it;
+            load_u(j + 2, u2, e2);
+            load_r(j + 1, rn, qn);
+            // right-hand side: west / east neighbours across lanes, window edges loaded
+            float rho[kSeg];
+            {
+                const float west = dpp<kWaveShr1>(0.f, uc[kSeg - 1]);
+                const float east = dpp<kWaveShl1>(0.f, uc[0]);
+                const float w0 = lane == 0 ? eC : west;
+                const float eL = lane == nl - 1 ? eC : east;
+#pragma unroll
+                for (int e = 0; e < kSeg; ++e) {
+                    const float uw = e == 0 ? w0 : uc[e - 1];
+                    const float ue = e == kSeg - 1 ? eL : uc[e + 1];
+                    rho[e] = 2.f * (rc[e] * (((uw + ue) + (um[e] + u1[e])) - 4.f * uc[e]));
+                }
+            }
+            if (ns > 0) {
+                for (int s = 0; s < ns; ++s) {
+                    const int pos = sh.src_pos[s];
+                    if ((pos >> 16) == xr) {
+                        const int i = (pos & 0xffff) - lane * kSeg;
+                        const float add = sh.src_add[s];
+#pragma unroll
+                        for (int e = 0; e < kSeg; ++e)
+                            if (e == i) rho[e] += add;
+                    }
+                }
+            } else if (ns < 0 && row_ok(j)) {
+                for (int s = 0; s < A.nsrc; ++s) {
+                    const int id = A.src_idx[s];
+                    if (id >= 0 && id < npts && id / nx == j) {
+                        const int i = id - j * nx - col0;
+                        const float add = A.tau2 * A.src_amp[s];
+#pragma unroll
+                        for (int e = 0; e < kSeg; ++e)
+                            if (e == i && inwin) rho[e] += add;
+                    }
+                }
+            }
+            // segment elimination from the full-line entry pivot (zero rows decouple)
+            float Ge[kSeg], qe[kSeg], Qe[kSeg];
+            float fG, fQ, H, Ev;
+            {
+                float q = qc, Gv = 0.f, Qv = 1.f, h = 0.f, ee = 0.f;
+#pragma unroll
+                for (int e = 0; e < kSeg; ++e) {
+                    const float m = pivot_step<float>(rc[e], q);
+                    const float P = Qv;
+                    Gv = fma_rn(m, rho[e], q * Gv);
+                    Qv = q * Qv;
+                    h = fma_rn(P, Gv, h);
+                    ee = fma_rn(P, Qv, ee);
+                    Ge[e] = Gv;
+                    qe[e] = q;
+                    Qe[e] = Qv;
+                }
+                fG = Gv; fQ = Qv; H = h; Ev = ee;
+            }
+            // forward carries within the window (zero entering lane 0)
+            float a = fG, b = fQ;
+            wave_scan_fwd(a, b);
+            const float gin = dpp<kWaveShr1>(0.f, a);
+            // backward values within the window (zero leaving the last lane)
+            float ba = inwin ? fma_rn(Ev, gin, H) : 0.f, bb = inwin ? fQ : 1.f;
+            wave_scan_bwd2(ba, bb, lane);
+            const float dbelow = dpp<kWaveShl1>(0.f, ba);
+            float wout[kSeg];
+            {
+                float x = dbelow;
+#pragma unroll
+                for (int e = kSeg - 1; e >= 0; --e) {
+                    x = fma_rn(qe[e], x, fma_rn(Qe[e], gin, Ge[e]));
+                    wout[e] = x;
+                }
+            }
+            // central columns to LDS (lanes 2 .. nl-3 hold columns c0 .. c0+wt-1)
+            if (lane >= kFuKx / kSeg && lane < nl - kFuKx / kSeg) {
+                float* dst = sh.w + xr * wt + (lane - kFuKx / kSeg) * kSeg;
+                *reinterpret_cast<float4*>(dst) = make_float4(wout[0], wout[1], wout[2], wout[3]);
+                *reinterpret_cast<float4*>(dst + 4) = make_float4(wout[4], wout[5], wout[6], wout[7]);
+            }
+            // roll
+            eM = eC; eC = e1; e1 = e2; qc = qn;
+#pragma unroll
+            for (int e = 0; e < kSeg; ++e) {
+                um[e] = uc[e]; uc[e] = u1[e]; u1[e] = u2[e]; rc[e] = rn[e];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------- phase 2: y windows
+    const bool ythr = t < 2 * wt;
+    const int ci = ythr ? (t < wt ? t : t - wt) : 0;
+    const int half = t < wt ? 0 : 1;
+    float gk[kFuNb], qk[kFuNb];
+    if (ythr) {
+        const int gcol = c0 + ci;
+        const int jtop = r0 - kFuKy + kFuHb * half;         // global row of window row 0
+        const rsrc_t rall = buf(A.r, (int)(npts * 4));
+        auto roff = [&](int k) {
+            const int j = jtop + k;
+            return (j >= 0 && j < ny && gcol < nx) ? (j * nx + gcol) * 4 : kFuOOB;
+        };
+        float rbuf[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) rbuf[k] = bload1<float>(rall, roff(k));
+        float q = 0.f, g = 0.f;
+        const float* wcol = sh.w + (kFuHb * half) * wt + ci;
+#pragma unroll
+        for (int k = 0; k < kFuNb; ++k) {
+            const float rk = rbuf[k & 7];
+            if (k + 8 < kFuNb) rbuf[k & 7] = bload1<float>(rall, roff(k + 8));
+            const float m = pivot_step<float>(rk, q);
+            g = fma_rn(m, wcol[k * wt], q * g);
+            gk[k] = g;
+            qk[k] = q;
+        }
+    }
+    __syncthreads();
+    if (ythr) {
+        float d = 0.f;
+        float* dcol = sh.w + (kFuHb * half) * wt + ci;
+#pragma unroll
+        for (int k = kFuNb - 1; k >= 0; --k) {
+            d = fma_rn(qk[k], d, gk[k]);
+            if (k >= kFuKy && k < kFuKy + kFuHb) dcol[k * wt] = d;
+        }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------ phase 3: update
+    {
+        const int nq = wt / 4;                              // float4 per tile row
+        const int total = kFuHt * nq;
+        const int lim = (int)(npts * 4);
+        const rsrc_t ruc = buf(A.uc, lim);
+        const rsrc_t rup = buf(static_cast<const float*>(A.up), lim);
+        for (int base = 0; base < total; base += 1024 * 4) {
+            f32x4 cv[4], pv[4];
+            int off[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int idx = base + s * 1024 + t;
+                const int orow = idx / nq, oq = idx - orow * nq;
+                const int j = r0 + orow, i = c0 + 4 * oq;
+                off[s] = (idx < total && j < ny && i < nx) ? (j * nx + i) * 4 : kFuOOB;
+                cv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ruc, off[s], 0, 0));
+                pv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rup, off[s], 0, 0));
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int idx = base + s * 1024 + t;
+                if (idx < total) {
+                    const int orow = idx / nq, oq = idx - orow * nq;
+                    const float4 dv = *reinterpret_cast<const float4*>(sh.w + (kFuKy + orow) * wt + 4 * oq);
+                    const f32x4 o = {fma_rn(2.f, cv[s].x, -pv[s].x) + dv.x, fma_rn(2.f, cv[s].y, -pv[s].y) + dv.y,
+                                     fma_rn(2.f, cv[s].z, -pv[s].z) + dv.z, fma_rn(2.f, cv[s].w, -pv[s].w) + dv.w};
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, o), rup, off[s], 0, 0);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace adw
+
+namespace adw {
+
+// largest r (r >= 0, so the float bits order like the values): per-block
+// maximum, then one atomic per block on the bit pattern
+__global__ void __launch_bounds__(256) k_rmax(const float* __restrict__ r, long long n, unsigned int* out)
+{
+    __shared__ float red[256];
+    float m = 0.f;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        m = fmaxf(m, r[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+}  // namespace adw

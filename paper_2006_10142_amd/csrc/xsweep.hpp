@@ -223,10 +223,16 @@ __global__ void __launch_bounds__(256) k_xpivots(const T* __restrict__ r, T* __r
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kBufWord3 = 0x00020000;   // 32-bit data format, gfx9 family
 
+// base and nbytes must be the same in every lane of the wavefront (they are
+// moved to scalar registers, so the compiler needs no per-lane loop)
 template <typename T>
 __device__ __forceinline__ rsrc_t buf(const T* base, int nbytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, nbytes, kBufWord3);
+    const unsigned long long a = reinterpret_cast<unsigned long long>(base);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    T* p = reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, __builtin_amdgcn_readfirstlane(nbytes), kBufWord3);
 }
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
@@ -363,7 +369,7 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
     constexpr int NW = TR / 64;
     auto& s_halo = sh.halo;
     const int lane = t & 63;
-    const int wv = t >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int nx = A.nx, ny = A.ny, nseg = A.nseg;
     const int RS = A.rows_per_strip;
     const int j0 = strip * RS;
@@ -645,7 +651,7 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
 {
     constexpr int G = (TR >= 256 ? TR : 256) / TR;
     __shared__ XShared<T, TR, FUSE> sh[G];
-    const int g = threadIdx.x / TR;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / TR);   // one group per wavefront or more
     xsweep_strip<T, TR, FUSE, STENCIL>(A, blockIdx.x * G + g, threadIdx.x - g * TR, sh[g]);
 }
 

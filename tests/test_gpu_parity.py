@@ -124,12 +124,15 @@ def test_single_step_increment(adw, oracle_lib, dtype, nx, ny):
 
 
 # ------------------------------------------------------------ full runs ----
-def gpu_run(adw, prob, nsteps=None, rec=False):
+def gpu_run(adw, prob, nsteps=None, rec=False, fused_step=None):
     nsteps = prob.nsteps if nsteps is None else nsteps
     t = tdt(prob.dtype)
     wave = adw.Wave(prob.nx, prob.ny, prob.h, prob.dt, dtype=t,
                     c=dev(prob.c) if prob.c is not None else prob.c_scalar,
                     kappa=dev(prob.kappa) if prob.kappa is not None else None)
+    if fused_step is not None:
+        wave.set_tuning(fused_step=fused_step)
+        assert wave.info()["fused_step"] == int(fused_step)
     if prob.u_curr is not None:
         a, b = dev(prob.u_prev), dev(prob.u_curr)
     else:
@@ -206,13 +209,21 @@ def test_c3_shape_at_1024(adw, oracle_lib, dtype, variant):
     assert rel_l2(got, ref) <= TOL_RUN[dtype]
 
 
-def test_c3_full_size_steps(adw, oracle_lib):
-    """C3 at its full size (8192^2 FP32, the benchmark's launch plan): 3 steps from a
-    Gaussian pulse, compared node by node with the oracle."""
+@pytest.fixture(scope="module")
+def c3p_reference(oracle_lib):
     p = wl.config_c3p(dtype="f32", nsteps=3)
-    say("C3p f32 8192^2 3 steps")
-    _, got, _ = gpu_run(adw, p)
     _, ref, _ = oracle_lib.run_problem(p)
+    return p, ref
+
+
+@pytest.mark.parametrize("one_pass", [True, False])
+def test_c3_full_size_steps(adw, c3p_reference, one_pass):
+    """C3 at its full size (8192^2 FP32): 3 steps from a Gaussian pulse, compared node
+    by node with the oracle, with the benchmark's default (one-pass) step and with the
+    exact two-pass step."""
+    p, ref = c3p_reference
+    say(f"C3p f32 8192^2 3 steps one_pass={one_pass}")
+    _, got, _ = gpu_run(adw, p, fused_step=one_pass)
     assert rel_l2(got, ref) <= TOL_RUN["f32"]
 
 
@@ -285,7 +296,7 @@ def test_launch_plans(adw, oracle_lib, dtype, tr, rs, fused, m):
     if fused and dtype == "f64" and tr == 1024:
         pytest.skip("the fused FP64 state does not fit in LDS at 1024 threads per line")
     wave = adw.Wave(nx, ny, h, dt, c=dev(c), dtype=tdt(dtype))
-    wave.set_tuning(tr, rs, fused, m)
+    wave.set_tuning(tr, rs, fused, m, fused_step=False)
     inf = wave.info()
     assert (inf["x_threads_per_line"], inf["y_fused"], inf["y_chunk_rows"]) == (tr, int(fused), m)
     assert inf["x_rows_per_strip"] == ((32 if m == 16 else 32) if fused else rs)
