@@ -143,6 +143,44 @@ def bench_batched(adw, torch, steps: int, warmup: int, plain_value: float):
             "vs_plain": round(value / plain_value, 4), "finite": finite}
 
 
+def bench_cr(adw, torch, prob, steps: int, plain_value: float):
+    """The paper's line solver (cyclic reduction, one launch per level for all lines of
+    a sweep) on the same workload, same GPU: a short timed run."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    wave = adw.Wave(prob.nx, prob.ny, prob.h, prob.dt, dtype=torch.float32,
+                    c=torch.from_numpy(prob.c).to(dev) if prob.c is not None else prob.c_scalar)
+    if prob.u_curr is not None:
+        a = torch.from_numpy(np.ascontiguousarray(prob.u_prev)).to(dev)
+        b = torch.from_numpy(np.ascontiguousarray(prob.u_curr)).to(dev)
+    else:
+        a = torch.from_numpy(np.ascontiguousarray(prob.u0)).to(dev)
+        b = wave.start(a)
+    wave.set_tuning(cyclic_reduction=True)
+    warm, kw = {}, {}
+    if prob.src_amp is not None:
+        si = torch.from_numpy(prob.src_idx).to(dev)
+        amp = torch.from_numpy(np.ascontiguousarray(prob.src_amp[:steps + 2])).to(dev)
+        warm, kw = dict(src_idx=si, src_amp=amp[:2]), dict(src_idx=si, src_amp=amp[2:])
+    a, b = wave.step(a, b, 2, **warm)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    a, b = wave.step(a, b, steps, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    info = wave.info()
+    wave.close()
+    value = prob.nx * prob.ny * steps / (ms / 1e3) / 1e6
+    return {"solver": "cyclic reduction, one launch per level, all lines of a sweep per launch",
+            "value": round(value, 1), "unit": "Mpts/s", "ms_per_step": round(ms / steps, 4),
+            "steps": steps, "launches_per_step": info["kernels_per_step"],
+            "default_over_cr": round(plain_value / value, 2),
+            "finite": bool(torch.isfinite(b).all())}
+
+
 def bench_adjoint(adw, torch, plain_value: float):
     """C5: dJ/dkappa of a receiver misfit on 1024^2 FP32, 2000 steps, checkpoints every 100
     steps, 64 receivers; target traces from the run on the second kappa field."""
@@ -195,6 +233,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cr", action="store_true", help="skip the cyclic-reduction baseline leg")
     ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
 
@@ -341,6 +380,8 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(adw, torch, value)
         out["adjoint"]["vs_two_pass"] = round(out["adjoint"]["value"] / tp_value, 4)
+    if not args.no_cr and dtype == "f32":
+        out["cr_baseline"] = bench_cr(adw, torch, prob, 10, value)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(out), flush=True)

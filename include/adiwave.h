@@ -249,6 +249,7 @@ typedef struct {
     int fused_step;           /* 1: adi_wave_step runs the one-pass step (FP32) */
     int fused_allowed;        /* 1: the one-pass step's truncation bound holds (FP32) */
     double r_max;             /* largest r = dt^2 kappa / (2 h^2) (FP32 handles) */
+    int line_solver;          /* 1: partition / scan solvers, 2: cyclic-reduction baseline */
 } adi_wave_info;
 
 adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
@@ -263,6 +264,10 @@ typedef struct {
     int y_chunk_rows;         /* 16 or 32 */
     int fused_step;           /* 1 = one-pass step when allowed (else ADI_EUNSUPPORTED),
                                  2 = exact two-pass step, 0 = keep */
+    int line_solver;          /* 1 = partition / scan line solvers (default),
+                                 2 = cyclic reduction, one launch per level for all lines
+                                 of a sweep (the paper's Sec. 3.1 solver, as a same-GPU
+                                 baseline; allocates 3 nx*ny values), 0 = keep */
 } adi_tuning;
 adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t);
 

@@ -14,6 +14,7 @@
 #include "adiwave.h"
 #include "kernels.hpp"
 #include "fused.hpp"
+#include "cr.hpp"
 
 using namespace adw;
 
@@ -239,6 +240,9 @@ struct adi_wave_s {
     float rmax = 0.f;
     int fused_ok = 0, fused_mode = 0, fstep = 0;
     int f_wt = 0, f_tx = 0, f_tiles = 0, f_grid = 0;
+    // cyclic-reduction baseline (line_solver = 2): coefficient arrays a, b, c
+    int cr = 0;
+    void* cr_abc = nullptr;   // 3 * nx * ny values
 };
 
 namespace {
@@ -252,7 +256,8 @@ void free_ws(adi_wave_s* w)
     if (w->sum) (void)hipFree(w->sum);
     if (w->X) (void)hipFree(w->X);
     if (w->qin) (void)hipFree(w->qin);
-    w->r = w->w = w->sum = w->X = w->qin = nullptr;
+    if (w->cr_abc) (void)hipFree(w->cr_abc);
+    w->r = w->w = w->sum = w->X = w->qin = w->cr_abc = nullptr;
 }
 
 adi_status alloc_chunks(adi_wave_s* w)
@@ -500,16 +505,84 @@ adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const ad
     return ADI_OK;
 }
 
+int cr_levels(int n)   // m with 2^m - 1 >= n
+{
+    int m = 1;
+    while ((1LL << m) - 1 < n) ++m;
+    return m;
+}
+
+int cr_grid(long long work) { return (int)std::max<long long>(1, std::min<long long>((work + 255) / 256, 1 << 16)); }
+
+// all lines of one sweep by cyclic reduction, one launch per level (d holds the
+// right-hand sides and receives the solutions)
+template <typename T>
+adi_status queue_cr_lines(adi_wave_s* w, CrArgs<T> A)
+{
+    const int m = cr_levels(A.n);
+    for (int k = 1; k < m; ++k) {
+        A.h = 1 << (k - 1);
+        hipLaunchKernelGGL((k_cr_forward<T>), dim3(cr_grid((long long)(A.n / (2 * A.h)) * A.lines)), dim3(256), 0,
+                           w->stream, A);
+        ADI_LAUNCHED("cr_forward");
+    }
+    A.h = 1 << (m - 1);
+    hipLaunchKernelGGL((k_cr_div<T>), dim3(cr_grid(A.lines)), dim3(256), 0, w->stream, A);
+    ADI_LAUNCHED("cr_div");
+    for (int k = m - 1; k >= 1; --k) {
+        A.h = 1 << (k - 1);
+        hipLaunchKernelGGL((k_cr_backward<T>), dim3(cr_grid((long long)((A.n / A.h + 1) / 2) * A.lines)), dim3(256),
+                           0, w->stream, A);
+        ADI_LAUNCHED("cr_backward");
+    }
+    return ADI_OK;
+}
+
+// one ADI step with cyclic-reduction line solves: out = alpha u + beta v + d
+template <typename T>
+adi_status queue_cr_step(adi_wave_s* w, const void* u, const void* v, void* out, T alpha, T beta,
+                         const adi_source* f, int k, T rho_scale)
+{
+    const long long n = (long long)w->nx * w->ny;
+    T* a = static_cast<T*>(w->cr_abc);
+    T* b = a + n;
+    T* c = b + n;
+    T* d = static_cast<T*>(w->w);
+    const T* r = static_cast<const T*>(w->r);
+    hipLaunchKernelGGL((k_cr_setup<T>), dim3(cr_grid(n)), dim3(256), 0, w->stream, static_cast<const T*>(u), r, a,
+                       b, c, d, w->nx, w->ny, 0, rho_scale);
+    ADI_LAUNCHED("cr_setup_x");
+    if (f && f->count > 0) {
+        hipLaunchKernelGGL((k_cr_sources<T>), dim3(1), dim3(64), 0, w->stream, d, f->idx,
+                           static_cast<const T*>(f->amp) + (size_t)k * f->count, f->count,
+                           (T)(rho_scale * (T)(w->dt * w->dt)), n);
+        ADI_LAUNCHED("cr_sources");
+    }
+    CrArgs<T> X{a, b, c, d, w->nx, w->ny, (long long)w->nx, 1LL, 0};
+    if (adi_status s = queue_cr_lines<T>(w, X)) return s;
+    hipLaunchKernelGGL((k_cr_setup<T>), dim3(cr_grid(n)), dim3(256), 0, w->stream, static_cast<const T*>(u), r, a,
+                       b, c, d, w->nx, w->ny, 1, rho_scale);
+    ADI_LAUNCHED("cr_setup_y");
+    CrArgs<T> Y{a, b, c, d, w->ny, w->nx, 1LL, (long long)w->nx, 0};
+    if (adi_status s = queue_cr_lines<T>(w, Y)) return s;
+    hipLaunchKernelGGL((k_cr_update<T>), dim3(cr_grid(n)), dim3(256), 0, w->stream, static_cast<const T*>(u),
+                       static_cast<const T*>(v), d, static_cast<T*>(out), alpha, beta, n);
+    ADI_LAUNCHED("cr_update");
+    return ADI_OK;
+}
+
 // allow_fused = false keeps the exact two-pass step (the adjoint recomputes
 // its forward run with that path and needs the same trajectory)
 template <typename T>
 adi_status do_step(adi_wave_s* w, void** u_prev, void** u_curr, const adi_source* f,
                    const adi_receivers* rec, int nsteps, bool allow_fused = true)
 {
-    const bool fused = sizeof(T) == 4 && allow_fused && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
+    const bool cr = allow_fused && w->cr;
+    const bool fused = !cr && sizeof(T) == 4 && allow_fused && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
     for (int k = 0; k < nsteps; ++k) {
-        adi_status s = fused ? queue_fused(w, *u_curr, *u_prev, f, k)
-                             : queue_solve<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1), nullptr);
+        adi_status s = cr      ? queue_cr_step<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1))
+                       : fused ? queue_fused(w, *u_curr, *u_prev, f, k)
+                               : queue_solve<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1), nullptr);
         if (s != ADI_OK) return s;
         if (rec && rec->count > 0) {
             hipLaunchKernelGGL((k_record<T>), dim3((rec->count + 255) / 256), dim3(256), 0, w->stream,
@@ -676,11 +749,13 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->y_fused = w->xp.fuse;
     info->y_chunk_rows = w->M;
     info->y_chunks = w->K;
-    info->kernels_per_step = w->fstep ? 1 : (w->xp.fuse ? 3 : 4);
+    info->kernels_per_step = w->cr ? 1 + 2 * cr_levels(w->nx) + 2 * cr_levels(w->ny)
+                                   : w->fstep ? 1 : (w->xp.fuse ? 3 : 4);
     info->workspace_bytes = w->bytes;
     info->fused_step = w->fstep;
     info->fused_allowed = w->fused_ok;
     info->r_max = w->dtype == ADI_F32 ? (double)w->rmax : 0.0;
+    info->line_solver = w->cr ? 2 : 1;
     return ADI_OK;
 }
 
@@ -707,6 +782,17 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
         w->fused_mode = t->fused_step;
         fused_plan(w);
     }
+    if (t->line_solver < 0 || t->line_solver > 2) return fail(ADI_EINVAL, "line_solver must be 0, 1 or 2");
+    if (t->line_solver == 2 && !w->cr_abc) {
+        const size_t bytes = 3 * (size_t)w->nx * w->ny * esize(w->dtype);
+        if (hipMalloc(&w->cr_abc, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            w->cr_abc = nullptr;
+            return fail(ADI_ENOMEM, "hipMalloc of the cyclic-reduction coefficients failed");
+        }
+        w->bytes += bytes;
+    }
+    if (t->line_solver > 0) w->cr = t->line_solver == 2 ? 1 : 0;
     if (xp.fuse && (M != w->M || !w->xp.fuse)) xp.frs = fused_rows(M);
     w->xp = xp;
     if (M != w->M) {
@@ -733,12 +819,17 @@ adi_status adi_wave_profile(adi_wave_t w, void** u_prev, void** u_curr, const ad
     adi_status st = ADI_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) { st = fail(ADI_EHIP, "hipEventCreate failed"); break; }
-    const bool fused = w->dtype == ADI_F32 && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
+    const bool cr = w->cr != 0;
+    const bool fused = cr || (w->dtype == ADI_F32 && w->fstep && aligned16(*u_prev) && aligned16(*u_curr));
     for (int k = 0; k < nsteps && st == ADI_OK; ++k) {
         hipEvent_t* e = &ev[(size_t)k * 5];
-        if (fused) {
+        if (fused) {   // one timed range per step (one-pass step, or the whole cyclic-reduction step)
             if (hipEventRecord(e[0], w->stream) != hipSuccess) st = fail(ADI_EHIP, "hipEventRecord failed");
-            if (st == ADI_OK) st = queue_fused(w, *u_curr, *u_prev, f, k);
+            if (st == ADI_OK)
+                st = !cr ? queue_fused(w, *u_curr, *u_prev, f, k)
+                   : w->dtype == ADI_F32
+                       ? queue_cr_step<float>(w, *u_curr, *u_prev, *u_prev, 2.f, -1.f, f, k, 1.f)
+                       : queue_cr_step<double>(w, *u_curr, *u_prev, *u_prev, 2.0, -1.0, f, k, 1.0);
             if (st == ADI_OK && hipEventRecord(e[1], w->stream) != hipSuccess)
                 st = fail(ADI_EHIP, "hipEventRecord failed");
         } else {
@@ -760,7 +851,7 @@ adi_status adi_wave_profile(adi_wave_t w, void** u_prev, void** u_curr, const ad
         }
         if (st == ADI_OK) {
             ms_per_kernel[0] = acc / nsteps;
-            if (names) names[0] = "fused_step";
+            if (names) names[0] = cr ? "cr_step" : "fused_step";
             *nkinds = 1;
         }
     } else if (st == ADI_OK) {
