@@ -139,7 +139,11 @@ def bench_batched(adw, torch, steps: int, warmup: int, plain_value: float):
             "plan": {k: plan[k] for k in ("x_threads_per_line", "x_grid", "yscan_grid",
                                           "ysolve_grid")},
             "autotune_ms_per_step": round(tuned_ms, 5),
-            "step_algorithmic_GBps": round(STEP_BYTES_PER_NODE * 4 * nodes * steps / (ms / 1e3) / 1e9, 1),
+            "step": "one-pass" if plan["fused_step"] else "two-pass",
+            "step_algorithmic_bytes_per_node": 4 * (FUSED_STEP_BYTES_PER_NODE if plan["fused_step"]
+                                                    else STEP_BYTES_PER_NODE),
+            "step_algorithmic_GBps": round((FUSED_STEP_BYTES_PER_NODE if plan["fused_step"] else STEP_BYTES_PER_NODE)
+                                           * 4 * nodes * steps / (ms / 1e3) / 1e9, 1),
             "vs_plain": round(value / plain_value, 4), "finite": finite}
 
 

@@ -204,6 +204,11 @@ typedef struct {
     long long nodes;          /* total grid nodes (read-only) */
     size_t workspace_bytes;   /* device bytes owned by the batch (read-only) */
     int x_items, yscan_items, ysolve_items;   /* work-list lengths (read-only) */
+    int fused_step;           /* 1: one-pass step for every simulation (FP32, when each
+                                 simulation's truncation bound holds; the default then),
+                                 2 (set only): exact two-pass step, 0 (set): keep */
+    int fused_allowed;        /* read-only: the one-pass step is allowed for the batch */
+    int fused_items;          /* read-only: one-pass tiles over all simulations */
 } adi_batch_plan;
 adi_status adi_batch_get_plan(adi_batch_t b, adi_batch_plan* p);
 adi_status adi_batch_set_plan(adi_batch_t b, const adi_batch_plan* p);

@@ -332,12 +332,15 @@ class Batch:
         _lib.check(_lib.load().adi_batch_get_plan(self._h, ctypes.byref(p)))
         return {f: getattr(p, f) for f, _ in _lib.AdiBatchPlan._fields_}
 
-    def set_plan(self, x_threads_per_line=0, x_grid=0, yscan_grid=0, ysolve_grid=0):
+    def set_plan(self, x_threads_per_line=0, x_grid=0, yscan_grid=0, ysolve_grid=0, fused_step=None):
+        """Launch plan of the two-pass step; fused_step: True = one-pass step for every
+        simulation (FP32, when allowed), False = exact two-pass step, None = keep."""
         p = _lib.AdiBatchPlan()
         _lib.check(_lib.load().adi_batch_get_plan(self._h, ctypes.byref(p)))
         if x_threads_per_line:
             p.x_threads_per_line = x_threads_per_line
         p.x_grid, p.yscan_grid, p.ysolve_grid = x_grid, yscan_grid, ysolve_grid
+        p.fused_step = 0 if fused_step is None else (1 if fused_step else 2)
         _lib.check(_lib.load().adi_batch_set_plan(self._h, ctypes.byref(p)))
 
     def autotune(self, trial_steps: int = 10, cache: Optional[str] = None) -> float:

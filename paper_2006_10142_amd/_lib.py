@@ -50,7 +50,9 @@ class AdiBatchPlan(ctypes.Structure):
                 ("yscan_grid", ctypes.c_int), ("ysolve_grid", ctypes.c_int),
                 ("graph", ctypes.c_int), ("count", ctypes.c_int), ("nodes", ctypes.c_longlong),
                 ("workspace_bytes", ctypes.c_size_t), ("x_items", ctypes.c_int),
-                ("yscan_items", ctypes.c_int), ("ysolve_items", ctypes.c_int)]
+                ("yscan_items", ctypes.c_int), ("ysolve_items", ctypes.c_int),
+                ("fused_step", ctypes.c_int), ("fused_allowed", ctypes.c_int),
+                ("fused_items", ctypes.c_int)]
 
 
 _SIGNATURES = {

@@ -16,6 +16,7 @@ namespace adw {
 template <typename T>
 struct SimDesc {
     int nx, ny, nseg, K, nxp, vec;
+    int f_wt, f_tx, f_tiles;   // one-pass tiles (see fused.hpp)
     T* r;
     T* w;
     T* qin;
@@ -35,6 +36,36 @@ struct BatchArgs {
     int out_slot;         // level written
     T alpha, beta, rho_scale;
 };
+
+// one-pass step of every simulation: work list of (simulation, tile), one tile
+// per workgroup (FP32)
+struct FBatchArgs {
+    const SimDesc<float>* sims;
+    const int2* items;
+    int nitems;
+    int u_slot, out_slot;   // level read as u^n; level holding u^{n-1}, receiving u^{n+1}
+};
+
+__global__ void __launch_bounds__(1024) k_fused_batch(FBatchArgs B)
+{
+    __shared__ FShared sh;
+    const int it = xcd_band(blockIdx.x);
+    if (it >= B.nitems) return;
+    const int2 wi = B.items[it];
+    const SimDesc<float>& S = B.sims[wi.x];
+    FArgs A{};
+    A.uc = S.lev[B.u_slot];
+    A.up = S.lev[B.out_slot];
+    A.r = S.r;
+    A.qin = S.qin;
+    A.nx = __builtin_amdgcn_readfirstlane(S.nx);
+    A.ny = __builtin_amdgcn_readfirstlane(S.ny);
+    A.nseg = __builtin_amdgcn_readfirstlane(S.nseg);
+    A.wt = __builtin_amdgcn_readfirstlane(S.f_wt);
+    A.tiles_x = __builtin_amdgcn_readfirstlane(S.f_tx);
+    A.tiles = __builtin_amdgcn_readfirstlane(S.f_tiles);
+    fused_tile(A, __builtin_amdgcn_readfirstlane(wi.y), sh);
+}
 
 template <typename T, int TR>
 __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep_batch(BatchArgs<T> B)
@@ -150,12 +181,18 @@ struct adi_batch_s {
     hipGraphExec_t gexec = nullptr;
     size_t bytes = 0;
     long long nodes = 0;
+    // one-pass step: allowed when every simulation allows it (FP32, bound holds)
+    int fused_ok = 0, fused = 0;
+    int2* fitems = nullptr;         // (simulation, tile)
+    int nf_items = 0;
 };
 
 namespace {
 
 void batch_free(adi_batch_s* b)
 {
+    if (b->fitems) (void)hipFree(b->fitems);
+    b->fitems = nullptr;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->pool) (void)hipFree(b->pool);
@@ -176,6 +213,7 @@ void fill_desc(adi_batch_s* b)
     for (int s = 0; s < b->count; ++s) {
         const adi_wave_s& w = b->sims[s];
         d[s].nx = w.nx; d[s].ny = w.ny; d[s].nseg = w.nseg; d[s].K = w.K; d[s].nxp = w.nxp;
+        d[s].f_wt = w.f_wt; d[s].f_tx = w.f_tx; d[s].f_tiles = w.f_tiles;
         d[s].vec = ((size_t)w.nx * sizeof(T)) % 16 == 0;
         d[s].r = (T*)w.r; d[s].w = (T*)w.w; d[s].qin = (T*)w.qin; d[s].sum = (T*)w.sum; d[s].X = (T*)w.X;
         d[s].lev[0] = b->bound ? (T*)b->lev0[s] : nullptr;
@@ -265,6 +303,12 @@ adi_status queue_batch_solve(adi_batch_s* b, int u_slot, int v_slot, int out_slo
 adi_status batch_step_once(adi_batch_s* b, hipStream_t st, int parity)
 {
     const int p = parity;
+    if (b->fused) {
+        FBatchArgs a{static_cast<const SimDesc<float>*>(b->desc), b->fitems, b->nf_items, p ^ 1, p};
+        hipLaunchKernelGGL(k_fused_batch, dim3((b->nf_items + 7) / 8 * 8), dim3(1024), 0, st, a);
+        ADI_LAUNCHED("fused_batch");
+        return ADI_OK;
+    }
     return b->dtype == ADI_F32
                ? queue_batch_solve<float>(b, p ^ 1, p, p, 2.f, -1.f, 1.f, st)
                : queue_batch_solve<double>(b, p ^ 1, p, p, 2.0, -1.0, 1.0, st);
@@ -427,6 +471,27 @@ adi_status adi_batch_create(adi_batch_t* out, int count, const int* nx, const in
         st = dtype == ADI_F32 ? batch_setup_sim<float>(&b->sims[s], f, sc)
                               : batch_setup_sim<double>(&b->sims[s], f, sc);
     }
+    if (st == ADI_OK) {
+        // one-pass tiles of every simulation (each view's plan was set with its r)
+        b->fused_ok = dtype == ADI_F32 ? 1 : 0;
+        std::vector<int2> fi;
+        for (int s = 0; s < count && b->fused_ok; ++s) {
+            if (!b->sims[s].fused_ok) b->fused_ok = 0;
+            for (int tl = 0; tl < b->sims[s].f_tiles; ++tl) fi.push_back(make_int2(s, tl));
+        }
+        if (b->fused_ok) {
+            b->nf_items = (int)fi.size();
+            if (hipMalloc(&b->fitems, fi.size() * sizeof(int2)) != hipSuccess) {
+                (void)hipGetLastError();
+                b->fitems = nullptr;
+                st = fail(ADI_ENOMEM, "hipMalloc of the one-pass work list failed");
+            } else if (hipMemcpyAsync(b->fitems, fi.data(), fi.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                      b->stream) != hipSuccess) {
+                st = fail(ADI_EHIP, "upload of the one-pass work list failed");
+            }
+            b->fused = st == ADI_OK ? 1 : 0;
+        }
+    }
     if (st == ADI_OK) st = batch_upload(b);
     if (st != ADI_OK) {
         batch_free(b);
@@ -528,6 +593,9 @@ adi_status adi_batch_get_plan(adi_batch_t b, adi_batch_plan* p)
     p->x_items = b->nx_items;
     p->yscan_items = b->nys_items;
     p->ysolve_items = b->nyv_items;
+    p->fused_step = b->fused;
+    p->fused_allowed = b->fused_ok;
+    p->fused_items = b->nf_items;
     return ADI_OK;
 }
 
@@ -541,6 +609,10 @@ adi_status adi_batch_set_plan(adi_batch_t b, const adi_batch_plan* p)
     if (!batch_fits(tr, b->dtype)) return fail(ADI_EUNSUPPORTED, "plan does not fit in LDS");
     if (p->x_grid < 0 || p->yscan_grid < 0 || p->ysolve_grid < 0)
         return fail(ADI_EINVAL, "grid sizes must be >= 0");
+    if (p->fused_step < 0 || p->fused_step > 2) return fail(ADI_EINVAL, "fused_step must be 0, 1 or 2");
+    if (p->fused_step == 1 && !b->fused_ok)
+        return fail(ADI_EUNSUPPORTED, "the one-pass step is not allowed for every simulation of the batch");
+    if (p->fused_step > 0) b->fused = p->fused_step == 1 ? 1 : 0;
     b->x_tr = tr;
     b->x_grid = p->x_grid;
     b->ys_grid = p->yscan_grid;
@@ -593,10 +665,14 @@ adi_status adi_batch_autotune(adi_batch_t b, int trial_steps, double* best_ms)
         return ADI_OK;
     };
     // candidates: line-group width, then each kernel's persistent grid in turn
+    // (the one-pass step has no plan to choose: it is only timed)
     double best = 1e30;
     int btr = b->x_tr, bxg = b->x_grid, bsg = b->ys_grid, bvg = b->yv_grid;
     static const int grids[] = {0, 256, 512, 1024, 2048, 4096};
-    if (st == ADI_OK) {
+    if (st == ADI_OK && b->fused) {
+        double ms = 0;
+        if ((st = trial(ms)) == ADI_OK) best = ms;
+    } else if (st == ADI_OK) {
         for (int tr : {128, 256, 1024}) {
             if (8LL * tr < b->max_nx || !batch_fits(tr, b->dtype)) continue;
             b->x_tr = tr; b->x_grid = 0; b->ys_grid = 0; b->yv_grid = 0;

@@ -83,17 +83,17 @@ __device__ __forceinline__ void wave_scan_bwd2(float& a, float& b, int lane)
     b = b * cb;
 }
 
-__global__ void __launch_bounds__(1024) k_fused(FArgs A)
+// block -> work index: the blocks of one XCD (b mod 8) take one contiguous band
+// of indices, so tiles that share halo rows share an L2 (gridDim.x is a
+// multiple of 8)
+__device__ __forceinline__ int xcd_band(int b) { return (b & 7) * (int)(gridDim.x >> 3) + (b >> 3); }
+
+// one tile of one grid; every thread of the 1024-thread workgroup takes part
+__device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShared& sh)
 {
-    __shared__ FShared sh;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    // block -> tile: with xcd_map, the blocks of one XCD (b mod 8) take one
-    // contiguous band of tiles, so tiles that share halo rows share an L2
-    int tile = blockIdx.x;
-    if (A.xcd_map) tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-    if (tile >= A.tiles) return;
     const int nx = A.nx, ny = A.ny, wt = A.wt;
     const int c0 = (tile % A.tiles_x) * wt;
     const int r0 = (tile / A.tiles_x) * kFuHt;
@@ -320,6 +320,14 @@ __global__ void __launch_bounds__(1024) k_fused(FArgs A)
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(1024) k_fused(FArgs A)
+{
+    __shared__ FShared sh;
+    const int tile = A.xcd_map ? xcd_band(blockIdx.x) : (int)blockIdx.x;
+    if (tile >= A.tiles) return;
+    fused_tile(A, tile, sh);
 }
 
 }  // namespace adw

@@ -84,8 +84,35 @@ def test_batch_matches_oracle(adw, oracle_lib, dtype):
     say(f"batch {dtype} {len(sims)} sims, 25 steps")
     got, info = run_batch(adw, sims, dtype, 25)
     assert info["count"] == len(sims)
+    assert info["fused_allowed"] == 0 and info["fused_step"] == 0   # rows of 1, 9, 33 values
     for s, g in zip(sims, got):
         assert rel_l2(g, oracle_run(oracle_lib, s, 25)) <= TOL[dtype], (s["nx"], s["ny"])
+
+
+# every row length a multiple of 4: the FP32 batch then runs the one-pass step
+SIZES4 = [(64, 64), (100, 37), (4, 9), (8, 1), (256, 256), (300, 211), (1000, 50), (36, 517)]
+
+
+def test_batch_one_pass_matches_oracle(adw, oracle_lib):
+    sims = make_batch("f32", sizes=SIZES4, seed=5)
+    say("batch one-pass f32, 25 steps")
+    got, info = run_batch(adw, sims, "f32", 25)
+    assert info["fused_allowed"] == 1 and info["fused_step"] == 1 and info["fused_items"] > len(sims)
+    for s, g in zip(sims, got):
+        assert rel_l2(g, oracle_run(oracle_lib, s, 25)) <= TOL["f32"], (s["nx"], s["ny"])
+
+
+def test_batch_one_pass_graph_and_exact_step(adw):
+    sims = make_batch("f32", sizes=SIZES4, seed=6)
+    say("batch one-pass graph / exact")
+    eager, _ = run_batch(adw, sims, "f32", 11)
+    graph, info = run_batch(adw, sims, "f32", 11, graph=True)
+    assert info["graph"] == 1
+    exact, info2 = run_batch(adw, sims, "f32", 11, plan=dict(fused_step=False))
+    assert info2["fused_step"] == 0
+    for a, b, c in zip(eager, graph, exact):
+        assert np.array_equal(a, b)
+        assert rel_l2(a, c) <= 3e-6
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
