@@ -11,16 +11,16 @@
 // replaced by 0; y-lines: the window's own system with zero values beyond it)
 // changes the solution at distance d from a cut by at most qs^d max|x|: the
 // dropped carry is multiplied by one pivot per node it crosses.  Output nodes are
-// 17 columns from the x-cuts and 9 rows from the y-cuts, and the y-solve does not
+// 9 columns from the x-cuts and 9 rows from the y-cuts, and the y-solve does not
 // amplify errors of its right-hand side in the max norm (its inverse has norm
 // <= 1), so one step differs from the exact two-pass step by at most
-//     2 qs^17 max|w| + 2 qs^9 max|d|  <=  4 qs^9 max|w|,
+//     2 qs^9 max|w| + 2 qs^9 max|d|  <=  4 qs^9 max|w|,
 // which the host keeps below 2^-24 (half an FP32 ulp) by enabling this path only
 // when rm is small enough (rm <= 0.18); otherwise the exact path runs.
 //
-// A tile is Wt output columns (a multiple of 8, <= 480) by 64 output rows.
+// A tile is Wt output columns (a multiple of 8, <= 496) by 64 output rows.
 //   Phase 1: x-lines of the 80 rows [r0 - 8, r0 + 72), each on the column window
-//            [c0 - 16, c0 + Wt + 16): one wavefront per row, 8 nodes per lane, the
+//            [c0 - 8, c0 + Wt + 8): one wavefront per row, 8 nodes per lane, the
 //            segment scheme of xsweep.hpp with the full-line entry pivots; the Wt
 //            central values of w go to LDS (80 x Wt).
 //   Phase 2: y-lines: two windows of 48 rows per column ([r0 - 8, r0 + 40) and
@@ -33,13 +33,13 @@
 
 namespace adw {
 
-constexpr int kFuKx = 16;           // x-halo columns on each side
+constexpr int kFuKx = 8;            // x-halo columns on each side (one 8-node segment)
 constexpr int kFuKy = 8;            // y-halo rows on each side
 constexpr int kFuHb = 32;           // output rows per y-window
 constexpr int kFuNb = kFuHb + 2 * kFuKy;   // rows of a y-window (48)
 constexpr int kFuHt = 2 * kFuHb;    // output rows per tile (64)
 constexpr int kFuRows = kFuHt + 2 * kFuKy;   // x-rows per tile (80)
-constexpr int kFuWmax = 64 * kSeg - 2 * kFuKx;   // widest tile (480)
+constexpr int kFuWmax = 64 * kSeg - 2 * kFuKx;   // widest tile (496)
 constexpr int kFuSrc = 32;          // point sources staged per tile
 constexpr int kFuOOB = 0x40000000;  // byte offset beyond every buffer range used here
                                     // (grids hold at most 2^27 values, 2^29 bytes)
