@@ -16,9 +16,16 @@ Parity status of each function (what pins it; see tests/test_oracle_pins.py):
   adjoint                  -- central finite differences of the forward loss on
                               random cells; the source-to-trace dot-product
                               identity <F f, d> = <f, F^T d>.
+  step_tdc                 -- eq. (CN1) with a time-dependent coefficient: the
+                              unfactored eq. (CN1) with c^{k+1}, c^{k-1} solved
+                              densely (gap shrinks like dt^6); the discrete
+                              closed form of a mode under a spatially constant
+                              kappa(t); second-order convergence to a
+                              manufactured solution with kappa(t, x, y); equal
+                              to step_parts for a constant coefficient.
 """
 from .oracle import (build, lib, max_threads, thomas, tridiag_batched, step_parts, run,
-                     start, initial_levels, run_problem, adjoint)
+                     start, initial_levels, run_problem, adjoint, step_tdc)
 
 __all__ = ["build", "lib", "max_threads", "thomas", "tridiag_batched", "step_parts", "run",
-           "start", "initial_levels", "run_problem", "adjoint"]
+           "start", "initial_levels", "run_problem", "adjoint", "step_tdc"]

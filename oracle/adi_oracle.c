@@ -376,6 +376,40 @@ static void apply_lyy(int nx, int ny, double h, const double *v, double *out)
         }
 }
 
+/* ------------------------------------------------------------------------
+ * Eq. (CN1) with a coefficient that changes in time (its c^{k+1} and c^{k-1}):
+ * kappa_next multiplies the Laplacian of u^{k+1}, kappa_prev that of u^{k-1};
+ * the coefficient at t_k does not enter.  With delta = u^{k+1} - 2u^k + u^{k-1}
+ * and beta = dt^2 / 2, eq. (CN1) is
+ *   (I - beta K+ Lap) delta = dt^2 f^k + beta (2 K+ Lap u^k + (K- - K+) Lap u^{k-1}),
+ * and the ADI step replaces the operator on the left by
+ * (I - beta K+ Lxx)(I - beta K+ Lyy), x-lines first.  With K- = K+ it is the
+ * step of oracle_adi_step_parts.
+ * ------------------------------------------------------------------------ */
+int oracle_adi_step_tdc(int nx, int ny, double h, double dt, const double *kappa_prev,
+                        const double *kappa_next, const double *u_prev, const double *u_curr,
+                        const double *f, double *u_next, int nthreads)
+{
+    if (check_grid(nx, ny, h, dt)) return ORACLE_EINVAL;
+    set_threads(nthreads);
+    size_t npts = (size_t)nx * ny;
+    double *tmp = malloc(sizeof(double) * 5 * npts);
+    if (!tmp) return ORACLE_ENOMEM;
+    double *lap_c = tmp, *lap_p = tmp + npts, *rho = tmp + 2 * npts;
+    double *w = tmp + 3 * npts, *d = tmp + 4 * npts;
+    const double beta = 0.5 * dt * dt;
+    apply_lap(nx, ny, h, u_curr, lap_c);
+    apply_lap(nx, ny, h, u_prev, lap_p);
+    for (size_t p = 0; p < npts; ++p)
+        rho[p] = dt * dt * (f ? f[p] : 0.0) +
+                 beta * (2.0 * kappa_next[p] * lap_c[p] + (kappa_prev[p] - kappa_next[p]) * lap_p[p]);
+    int rc = adi_solves(nx, ny, h, dt, kappa_next, rho, w, d);
+    if (rc == ORACLE_OK)
+        for (size_t p = 0; p < npts; ++p) u_next[p] = 2.0 * u_curr[p] - u_prev[p] + d[p];
+    free(tmp);
+    return rc;
+}
+
 /* transposed line solves: along x (rows) or y (columns) */
 static int transposed_solves(int nx, int ny, double h, double dt, const double *kappa,
                              int along_y, const double *rhs, double *out)

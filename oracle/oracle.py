@@ -58,9 +58,12 @@ def lib():
         l.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      _dp, _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.c_int, _ip,
                                      _dp, ctypes.c_int, _dp, _dp, ctypes.c_int]
+        l.oracle_adi_step_tdc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         l.oracle_max_threads.argtypes = []
         for f in (l.oracle_thomas, l.oracle_tridiag_batched, l.oracle_adi_step_parts,
-                  l.oracle_adi_run, l.oracle_adi_start, l.oracle_max_threads, l.oracle_adjoint):
+                  l.oracle_adi_run, l.oracle_adi_start, l.oracle_max_threads, l.oracle_adjoint,
+                  l.oracle_adi_step_tdc):
             f.restype = ctypes.c_int
         _lib = l
     return _lib
@@ -125,6 +128,19 @@ def step_parts(kappa, u_prev, u_curr, h: float, dt: float, f=None, threads: int 
                                        _ptr(f), _ptr(out["rho"]), _ptr(out["w"]),
                                        _ptr(out["d"]), _ptr(out["u_next"]), threads),
            "step_parts")
+    return out
+
+
+def step_tdc(kappa_prev, kappa_next, u_prev, u_curr, h: float, dt: float, f=None, threads: int = 0):
+    """One step of eq. (CN1) with a time-dependent coefficient: kappa_prev multiplies the
+    Laplacian of u^{k-1}, kappa_next that of u^{k+1}.  Returns u^{k+1}."""
+    u_prev, u_curr = _f64(u_prev), _f64(u_curr)
+    ny, nx = u_curr.shape
+    kp, kn = _kappa(kappa_prev, nx, ny), _kappa(kappa_next, nx, ny)
+    f = None if f is None else _f64(f)
+    out = np.empty_like(u_curr)
+    _check(lib().oracle_adi_step_tdc(nx, ny, h, dt, _ptr(kp), _ptr(kn), _ptr(u_prev), _ptr(u_curr),
+                                     _ptr(f), _ptr(out), threads), "step_tdc")
     return out
 
 
