@@ -156,6 +156,23 @@ adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_c
 adi_status adi_adjoint_backward(adi_wave_t w, const adi_source* f, const adi_receivers* rec,
                                 const void* grad_traces, void* grad_kappa, void* grad_amp);
 
+/* One step of eq. (CN1) with a coefficient that changes in time (Sec. 2: the
+ * c^{k+1} and c^{k-1} of the scheme).  kappa_prev multiplies the Laplacian of
+ * u^{n-1} and kappa_next that of u^{n+1} (device nx*ny fields of the handle's
+ * dtype, the coefficient kappa = c^2 itself; NULL = the handle's current
+ * coefficient).  In delta form the step solves
+ *   (I - beta K^{n+1} Lxx)(I - beta K^{n+1} Lyy) delta
+ *       = dt^2 f + beta (2 K^{n+1} Lap u^n + (K^{n-1} - K^{n+1}) Lap u^{n-1}),
+ * beta = dt^2 / 2, and u^{n+1} = 2u^n - u^{n-1} + delta is written over u^{n-1};
+ * the pointers rotate as in adi_wave_step (one step).  f: this step's source
+ * values (count values, already divided by h^2); rec: traces of u^{n+1} (count
+ * values).  kappa_next becomes the handle's coefficient (its pivots and chunk
+ * planes are rebuilt on the stream); the one-pass step stays off until the next
+ * adi_wave_set_kappa, which measures the coefficient again.  Uses the exact
+ * two-pass kernels; the first call allocates two nx*ny fields of workspace. */
+adi_status adi_wave_step_tdc(adi_wave_t w, void** u_prev, void** u_curr, const void* kappa_prev,
+                             const void* kappa_next, const adi_source* f, const adi_receivers* rec);
+
 /* ------------------------------------------------------ batched simulations -- */
 
 /* Many independent simulations of uneven grid sizes advanced together: each

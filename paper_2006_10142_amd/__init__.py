@@ -164,6 +164,33 @@ class Wave:
             return u_prev, u_curr
         return u_curr, u_prev
 
+    def step_tdc(self, u_prev, u_curr, kappa_prev=None, kappa_next=None, src_idx=None, src_amp=None,
+                 rec_idx=None, traces=None) -> Tuple:
+        """One step of eq. (CN1) with a time-dependent coefficient: kappa_prev multiplies the
+        Laplacian of u^{n-1}, kappa_next that of u^{n+1} ((ny, nx) device tensors; None =
+        the current coefficient).  kappa_next becomes the handle's coefficient.  Returns
+        (u_prev, u_curr) rotated as by step(..., 1)."""
+        self._sync_stream()
+        a = _field(u_prev, self.dtype, self._shape(), "u_prev")
+        b = _field(u_curr, self.dtype, self._shape(), "u_curr")
+        kp = None if kappa_prev is None else _field(kappa_prev, self.dtype, self._shape(), "kappa_prev")
+        kn = None if kappa_next is None else _field(kappa_next, self.dtype, self._shape(), "kappa_next")
+        src = self._sources(src_idx, src_amp, 1)
+        rec = None
+        if rec_idx is not None and rec_idx.numel() > 0:
+            _index(rec_idx, "rec_idx")
+            if traces is None or traces.dtype != self.dtype or not traces.is_contiguous() \
+                    or traces.numel() < rec_idx.numel():
+                raise ValueError("traces must be a contiguous tensor of the handle dtype with count values")
+            rec = _lib.AdiReceivers(rec_idx.numel(), rec_idx.data_ptr(), traces.data_ptr())
+        pa, pb = ctypes.c_void_p(a.value), ctypes.c_void_p(b.value)
+        _lib.check(_lib.load().adi_wave_step_tdc(self._h, ctypes.byref(pa), ctypes.byref(pb), kp, kn,
+                                                 ctypes.byref(src) if src else None,
+                                                 ctypes.byref(rec) if rec else None))
+        if pb.value == b.value:
+            return u_prev, u_curr
+        return u_curr, u_prev
+
     def profile(self, u_prev, u_curr, nsteps: int, src_idx=None, src_amp=None):
         """Run nsteps steps with per-launch events; returns ((u_prev, u_curr), {kernel: mean ms})."""
         self._sync_stream()

@@ -63,6 +63,8 @@ _SIGNATURES = {
     "adi_wave_start": [_vp, _vp, _vp, ctypes.POINTER(AdiSource), ctypes.c_int, _vp],
     "adi_wave_step": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(AdiSource),
                       ctypes.POINTER(AdiReceivers), ctypes.c_int],
+    "adi_wave_step_tdc": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp,
+                          ctypes.POINTER(AdiSource), ctypes.POINTER(AdiReceivers)],
     "adi_wave_destroy": [_vp],
     "tridiag_solve_batched": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
                               ctypes.c_longlong, ctypes.c_longlong, _vp],

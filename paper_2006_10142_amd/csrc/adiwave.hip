@@ -243,6 +243,9 @@ struct adi_wave_s {
     // cyclic-reduction baseline (line_solver = 2): coefficient arrays a, b, c
     int cr = 0;
     void* cr_abc = nullptr;   // 3 * nx * ny values
+    // time-dependent coefficient steps: r at the previous level, right-hand side
+    void* r_prev = nullptr;
+    void* rho_buf = nullptr;
 };
 
 namespace {
@@ -257,7 +260,9 @@ void free_ws(adi_wave_s* w)
     if (w->X) (void)hipFree(w->X);
     if (w->qin) (void)hipFree(w->qin);
     if (w->cr_abc) (void)hipFree(w->cr_abc);
-    w->r = w->w = w->sum = w->X = w->qin = w->cr_abc = nullptr;
+    if (w->r_prev) (void)hipFree(w->r_prev);
+    if (w->rho_buf) (void)hipFree(w->rho_buf);
+    w->r = w->w = w->sum = w->X = w->qin = w->cr_abc = w->r_prev = w->rho_buf = nullptr;
 }
 
 adi_status alloc_chunks(adi_wave_s* w)
@@ -462,7 +467,7 @@ adi_status measure_rmax(adi_wave_s* w)
 }
 
 template <typename T>
-adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared)
+adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared, bool measure = true)
 {
     const long long n = (long long)w->nx * w->ny;
     const double s = w->dt * w->dt / (2.0 * w->h * w->h);
@@ -475,7 +480,8 @@ adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared
                        static_cast<const T*>(w->r), static_cast<T*>(w->qin), w->nx, w->ny, w->nseg);
     ADI_LAUNCHED("x_pivots");
     if constexpr (sizeof(T) == 4) {
-        if (adi_status s = measure_rmax(w)) return s;
+        if (measure)
+            if (adi_status s = measure_rmax(w)) return s;
     }
     return static_planes<T>(w);
 }
@@ -972,3 +978,4 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
 
 #include "batch.hpp"
 #include "adjoint.hpp"
+#include "tdc.hpp"
