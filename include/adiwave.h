@@ -272,6 +272,10 @@ typedef struct {
     int fused_allowed;        /* 1: the one-pass step's truncation bound holds (FP32) */
     double r_max;             /* largest r = dt^2 kappa / (2 h^2) (FP32 handles) */
     int line_solver;          /* 1: partition / scan solvers, 2: cyclic-reduction baseline */
+    int fused_tile_cols;      /* one-pass step: output columns per tile (64 rows each);
+                                 chosen to balance the tiles over the device's compute
+                                 units unless set through adi_wave_set_tuning */
+    int fused_tiles;          /* one-pass step: tiles per step (one workgroup each) */
 } adi_wave_info;
 
 adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
@@ -290,6 +294,8 @@ typedef struct {
                                  2 = cyclic reduction, one launch per level for all lines
                                  of a sweep (the paper's Sec. 3.1 solver, as a same-GPU
                                  baseline; allocates 3 nx*ny values), 0 = keep */
+    int fused_tile_cols;      /* one-pass tile width: a multiple of 8, at most 496;
+                                 -1 = back to the automatic choice, 0 = keep */
 } adi_tuning;
 adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t);
 

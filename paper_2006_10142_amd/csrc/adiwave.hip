@@ -240,6 +240,8 @@ struct adi_wave_s {
     float rmax = 0.f;
     int fused_ok = 0, fused_mode = 0, fstep = 0;
     int f_wt = 0, f_tx = 0, f_tiles = 0, f_grid = 0;
+    int f_ncu = 0;       // compute units the tiles are balanced over (0: widest tiles)
+    int f_wt_user = 0;   // tile width set through adi_wave_set_tuning (0: chosen here)
     // cyclic-reduction baseline (line_solver = 2): coefficient arrays a, b, c
     int cr = 0;
     void* cr_abc = nullptr;   // 3 * nx * ny values
@@ -437,13 +439,44 @@ bool fused_bound_holds(double rm)
     return 4.0 * std::pow(qs, kFuKy + 1) <= std::ldexp(1.0, -24);
 }
 
+// Tile width of the one-pass step.  The x-phase of a tile issues a fixed number
+// of instructions per row whatever its width (one wavefront per row), which at
+// full occupancy costs about as much time as streaming kFuXfloor columns; the
+// rest of a tile's time grows with its window (x-phase traffic) and its width
+// (y-phase, update).  A step is ceil(tiles / CUs) rounds of tiles, so with ncu > 0
+// the width minimises rounds * (max(floor, window) + width); with ncu = 0 (many
+// simulations share the rounds) the tiles are the widest that fit.
+constexpr int kFuXfloor = 300;
+constexpr int kFuWmin = 64;
+
+int fused_width(int nx, int ny, int ncu)
+{
+    const int tx0 = (nx + kFuWmax - 1) / kFuWmax;
+    auto width = [&](int tx) { return ((nx + tx - 1) / tx + 7) / 8 * 8; };
+    int best = width(tx0);
+    if (ncu <= 0) return best;
+    const long long ty = (ny + kFuHt - 1) / kFuHt;
+    long long best_cost = -1;
+    for (int tx = tx0; tx <= (nx + kFuWmin - 1) / kFuWmin; ++tx) {
+        const int wt = width(tx);
+        if (wt < kFuWmin && tx > tx0) break;
+        const long long tiles = (long long)((nx + wt - 1) / wt) * ty;
+        const long long rounds = (tiles + ncu - 1) / ncu;
+        const long long cost = rounds * (std::max(kFuXfloor, wt + 2 * kFuKx) + wt);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = wt;
+        }
+    }
+    return best;
+}
+
 void fused_plan(adi_wave_s* w)
 {
     w->fused_ok = (w->dtype == ADI_F32 && w->nx % 4 == 0 && fused_bound_holds(w->rmax)) ? 1 : 0;
     const bool autoon = (long long)w->nx * w->ny >= (1LL << 16);
     w->fstep = w->fused_ok && (w->fused_mode == 1 || (w->fused_mode == 0 && autoon)) ? 1 : 0;
-    const int tx = (w->nx + kFuWmax - 1) / kFuWmax;
-    w->f_wt = ((w->nx + tx - 1) / tx + 7) / 8 * 8;
+    w->f_wt = w->f_wt_user > 0 ? w->f_wt_user : fused_width(w->nx, w->ny, w->f_ncu);
     w->f_tx = (w->nx + w->f_wt - 1) / w->f_wt;
     w->f_tiles = w->f_tx * ((w->ny + kFuHt - 1) / kFuHt);
     w->f_grid = (w->f_tiles + 7) / 8 * 8;
@@ -667,6 +700,10 @@ adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
         delete w;
         return fail(ADI_EHIP, "hipGetDevice failed");
     }
+    if (hipDeviceGetAttribute(&w->f_ncu, hipDeviceAttributeMultiprocessorCount, w->device) != hipSuccess) {
+        (void)hipGetLastError();
+        w->f_ncu = 0;
+    }
     const size_t es = esize(dtype);
     const size_t npts = (size_t)nx * ny;
     w->nseg = (nx + kSeg - 1) / kSeg;
@@ -762,6 +799,8 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->fused_allowed = w->fused_ok;
     info->r_max = w->dtype == ADI_F32 ? (double)w->rmax : 0.0;
     info->line_solver = w->cr ? 2 : 1;
+    info->fused_tile_cols = w->f_wt;
+    info->fused_tiles = w->f_tiles;
     return ADI_OK;
 }
 
@@ -784,10 +823,12 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
     if (t->fused_step < 0 || t->fused_step > 2) return fail(ADI_EINVAL, "fused_step must be 0, 1 or 2");
     if (t->fused_step == 1 && !w->fused_ok)
         return fail(ADI_EUNSUPPORTED, "the one-pass step needs FP32, nx % 4 == 0 and r <= 0.18 everywhere");
-    if (t->fused_step > 0) {
-        w->fused_mode = t->fused_step;
-        fused_plan(w);
-    }
+    if (t->fused_tile_cols > 0 && (t->fused_tile_cols % 8 != 0 || t->fused_tile_cols > kFuWmax))
+        return fail(ADI_EINVAL, "fused_tile_cols must be a multiple of 8 and at most 496");
+    if (t->fused_step > 0) w->fused_mode = t->fused_step;
+    if (t->fused_tile_cols > 0) w->f_wt_user = t->fused_tile_cols;
+    if (t->fused_tile_cols == -1) w->f_wt_user = 0;
+    if (t->fused_step > 0 || t->fused_tile_cols > 0 || t->fused_tile_cols == -1) fused_plan(w);
     if (t->line_solver < 0 || t->line_solver > 2) return fail(ADI_EINVAL, "line_solver must be 0, 1 or 2");
     if (t->line_solver == 2 && !w->cr_abc) {
         const size_t bytes = 3 * (size_t)w->nx * w->ny * esize(w->dtype);

@@ -66,10 +66,44 @@ struct FShared {
     int src_n;             // -1: more than kFuSrc in this tile
 };
 
+// Wavefront scans of affine maps with each DPP lane move folded into the
+// composing multiply-add / multiply: a lane whose source lane does not exist (or
+// lies in a row outside the mask) is left as it is, which is composition with the
+// identity map, so the results are those of wave_scan_fwd / row_scan_bwd bit for
+// bit (the same fused roundings) in a third of the instructions.  A DPP read of a
+// register written by the previous VALU instruction needs two wait states: the
+// s_nop before, between and after the steps provide them.
+#define ADW_FU_STEP(CTRL, MASK) \
+    "v_fmac_f32_dpp %0, %0, %1 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t" \
+    "v_mul_f32_dpp %1, %1, %1 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t" \
+    "s_nop 0\n\t"
+
+// inclusive prefix (lanes 0..l) over the wavefront
+__device__ __forceinline__ void fu_scan_fwd(float& a, float& b)
+{
+    asm volatile("s_nop 1\n\t"
+                 ADW_FU_STEP("row_shr:1", "0xf") ADW_FU_STEP("row_shr:2", "0xf")
+                 ADW_FU_STEP("row_shr:4", "0xf") ADW_FU_STEP("row_shr:8", "0xf")
+                 ADW_FU_STEP("row_bcast:15", "0xa") ADW_FU_STEP("row_bcast:31", "0xc")
+                 "s_nop 1"
+                 : "+v"(a), "+v"(b));
+}
+
+// inclusive suffix over each row of 16 lanes (lanes l..16k+15)
+__device__ __forceinline__ void fu_row_scan_bwd(float& a, float& b)
+{
+    asm volatile("s_nop 1\n\t"
+                 ADW_FU_STEP("row_shl:1", "0xf") ADW_FU_STEP("row_shl:2", "0xf")
+                 ADW_FU_STEP("row_shl:4", "0xf") ADW_FU_STEP("row_shl:8", "0xf")
+                 "s_nop 1"
+                 : "+v"(a), "+v"(b));
+}
+#undef ADW_FU_STEP
+
 // inclusive suffix (lanes l..63) of two-component affine maps over the wavefront
 __device__ __forceinline__ void wave_scan_bwd2(float& a, float& b, int lane)
 {
-    row_scan_bwd(a, b);
+    fu_row_scan_bwd(a, b);
     const float a16 = readlane(a, 16), b16 = readlane(b, 16);
     const float a32 = readlane(a, 32), b32 = readlane(b, 32);
     const float a48 = readlane(a, 48), b48 = readlane(b, 48);
@@ -155,6 +189,7 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
         load_u(j + 1, u1, e1);
         load_r(j, rc, qc);
         const int ns = sh.src_n;
+#pragma unroll
         for (int it = 0; it < kFuRows / 16; ++it, ++j) {
             const int xr = xr0 + it;
             load_u(j + 2, u2, e2);
@@ -217,7 +252,7 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
             }
             // forward carries within the window (zero entering lane 0)
             float a = fG, b = fQ;
-            wave_scan_fwd(a, b);
+            fu_scan_fwd(a, b);
             const float gin = dpp<kWaveShr1>(0.f, a);
             // backward values within the window (zero leaving the last lane)
             float ba = inwin ? fma_rn(Ev, gin, H) : 0.f, bb = inwin ? fQ : 1.f;
@@ -257,21 +292,26 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
         const int gcol = c0 + ci;
         const int jtop = r0 - kFuKy + kFuHb * half;         // global row of window row 0
         const rsrc_t rall = buf(A.r, (int)(npts * 4));
-        auto roff = [&](int k) {
-            const int j = jtop + k;
-            return (j >= 0 && j < ny && gcol < nx) ? (j * nx + gcol) * 4 : kFuOOB;
-        };
+        // byte offset of node (jtop + k, gcol) is off + k * rowb, in 32-bit unsigned
+        // arithmetic: rows above the grid wrap to offsets near 2^32 and rows below it
+        // lie past the end, both outside the buffer range (they read as zero);
+        // columns past the grid start at 2^31 and stay outside it
+        const unsigned rowb = (unsigned)nx * 4u;
+        unsigned off = gcol < nx ? (unsigned)(jtop * nx + gcol) * 4u : 0x80000000u;
         float rbuf[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) rbuf[k] = bload1<float>(rall, roff(k));
+        for (int k = 0; k < 8; ++k, off += rowb) rbuf[k] = bload1<float>(rall, (int)off);
         float q = 0.f, g = 0.f;
-        const float* wcol = sh.w + (kFuHb * half) * wt + ci;
+        int wo = (kFuHb * half) * wt + ci;                 // LDS index of (window row k, ci)
 #pragma unroll
-        for (int k = 0; k < kFuNb; ++k) {
+        for (int k = 0; k < kFuNb; ++k, wo += wt) {
             const float rk = rbuf[k & 7];
-            if (k + 8 < kFuNb) rbuf[k & 7] = bload1<float>(rall, roff(k + 8));
+            if (k + 8 < kFuNb) {
+                rbuf[k & 7] = bload1<float>(rall, (int)off);
+                off += rowb;
+            }
             const float m = pivot_step<float>(rk, q);
-            g = fma_rn(m, wcol[k * wt], q * g);
+            g = fma_rn(m, sh.w[wo], q * g);
             gk[k] = g;
             qk[k] = q;
         }
