@@ -41,6 +41,8 @@ constexpr int kFuHt = 2 * kFuHb;    // output rows per tile (64)
 constexpr int kFuRows = kFuHt + 2 * kFuKy;   // x-rows per tile (80)
 constexpr int kFuWmax = 64 * kSeg - 2 * kFuKx;   // widest tile (496)
 constexpr int kFuSrc = 32;          // point sources staged per tile
+constexpr int kFuRing = 16;         // rows of r requested ahead in a y-window
+constexpr int kFuUp = (kFuHt * kFuWmax / 4 + 1023) / 1024;   // float4 updated per thread (8)
 constexpr int kFuOOB = 0x40000000;  // byte offset beyond every buffer range used here
                                     // (grids hold at most 2^27 values, 2^29 bytes)
 
@@ -281,33 +283,37 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
             }
         }
     }
-    __syncthreads();
 
     // ------------------------------------------------- phase 2: y windows
     const bool ythr = t < 2 * wt;
     const int ci = ythr ? (t < wt ? t : t - wt) : 0;
     const int half = t < wt ? 0 : 1;
+    const int gcol = c0 + ci;
+    const int jtop = r0 - kFuKy + kFuHb * half;             // global row of window row 0
+    const rsrc_t rall = buf(A.r, (int)(npts * 4));
+    // byte offset of node (jtop + k, gcol) is off + k * rowb, in 32-bit unsigned
+    // arithmetic: rows above the grid wrap to offsets near 2^32 and rows below it
+    // lie past the end, both outside the buffer range (they read as zero); columns
+    // past the grid start at 2^31 and stay outside it
+    const unsigned rowb = (unsigned)nx * 4u;
+    unsigned off = gcol < nx ? (unsigned)(jtop * nx + gcol) * 4u : 0x80000000u;
+    // r of the window, kFuRing rows ahead; the first rows are requested before the
+    // barrier that ends the x-phase (a barrier waits for LDS traffic only)
+    float rbuf[kFuRing];
+    if (ythr) {
+#pragma unroll
+        for (int k = 0; k < kFuRing; ++k, off += rowb) rbuf[k] = bload1<float>(rall, (int)off);
+    }
+    __syncthreads();
     float gk[kFuNb], qk[kFuNb];
     if (ythr) {
-        const int gcol = c0 + ci;
-        const int jtop = r0 - kFuKy + kFuHb * half;         // global row of window row 0
-        const rsrc_t rall = buf(A.r, (int)(npts * 4));
-        // byte offset of node (jtop + k, gcol) is off + k * rowb, in 32-bit unsigned
-        // arithmetic: rows above the grid wrap to offsets near 2^32 and rows below it
-        // lie past the end, both outside the buffer range (they read as zero);
-        // columns past the grid start at 2^31 and stay outside it
-        const unsigned rowb = (unsigned)nx * 4u;
-        unsigned off = gcol < nx ? (unsigned)(jtop * nx + gcol) * 4u : 0x80000000u;
-        float rbuf[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k, off += rowb) rbuf[k] = bload1<float>(rall, (int)off);
         float q = 0.f, g = 0.f;
         int wo = (kFuHb * half) * wt + ci;                 // LDS index of (window row k, ci)
 #pragma unroll
         for (int k = 0; k < kFuNb; ++k, wo += wt) {
-            const float rk = rbuf[k & 7];
-            if (k + 8 < kFuNb) {
-                rbuf[k & 7] = bload1<float>(rall, (int)off);
+            const float rk = rbuf[k % kFuRing];
+            if (k + kFuRing < kFuNb) {
+                rbuf[k % kFuRing] = bload1<float>(rall, (int)off);
                 off += rowb;
             }
             const float m = pivot_step<float>(rk, q);
@@ -326,38 +332,36 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
             if (k >= kFuKy && k < kFuKy + kFuHb) dcol[k * wt] = d;
         }
     }
-    __syncthreads();
 
     // ------------------------------------------------------ phase 3: update
-    {
-        const int nq = wt / 4;                              // float4 per tile row
-        const int total = kFuHt * nq;
-        const int lim = (int)(npts * 4);
-        const rsrc_t ruc = buf(A.uc, lim);
-        const rsrc_t rup = buf(static_cast<const float*>(A.up), lim);
-        for (int base = 0; base < total; base += 1024 * 4) {
-            f32x4 cv[4], pv[4];
-            int off[4];
+    // every float4 of the tile's u^n and u^{n-1} that this thread updates is
+    // requested before the barrier, all at once
+    const int nq = wt / 4;                                  // float4 per tile row
+    const int total = kFuHt * nq;
+    const int lim = (int)(npts * 4);
+    const rsrc_t ruc = buf(A.uc, lim);
+    const rsrc_t rup = buf(static_cast<const float*>(A.up), lim);
+    f32x4 cv[kFuUp], pv[kFuUp];
+    int uoff[kFuUp];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int idx = base + s * 1024 + t;
-                const int orow = idx / nq, oq = idx - orow * nq;
-                const int j = r0 + orow, i = c0 + 4 * oq;
-                off[s] = (idx < total && j < ny && i < nx) ? (j * nx + i) * 4 : kFuOOB;
-                cv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ruc, off[s], 0, 0));
-                pv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rup, off[s], 0, 0));
-            }
+    for (int s = 0; s < kFuUp; ++s) {
+        const int idx = s * 1024 + t;
+        const int orow = idx / nq, oq = idx - orow * nq;
+        const int j = r0 + orow, i = c0 + 4 * oq;
+        uoff[s] = (idx < total && j < ny && i < nx) ? (j * nx + i) * 4 : kFuOOB;
+        cv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ruc, uoff[s], 0, 0));
+        pv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rup, uoff[s], 0, 0));
+    }
+    __syncthreads();
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int idx = base + s * 1024 + t;
-                if (idx < total) {
-                    const int orow = idx / nq, oq = idx - orow * nq;
-                    const float4 dv = *reinterpret_cast<const float4*>(sh.w + (kFuKy + orow) * wt + 4 * oq);
-                    const f32x4 o = {fma_rn(2.f, cv[s].x, -pv[s].x) + dv.x, fma_rn(2.f, cv[s].y, -pv[s].y) + dv.y,
-                                     fma_rn(2.f, cv[s].z, -pv[s].z) + dv.z, fma_rn(2.f, cv[s].w, -pv[s].w) + dv.w};
-                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, o), rup, off[s], 0, 0);
-                }
-            }
+    for (int s = 0; s < kFuUp; ++s) {
+        const int idx = s * 1024 + t;
+        if (idx < total) {
+            const int orow = idx / nq, oq = idx - orow * nq;
+            const float4 dv = *reinterpret_cast<const float4*>(sh.w + (kFuKy + orow) * wt + 4 * oq);
+            const f32x4 o = {fma_rn(2.f, cv[s].x, -pv[s].x) + dv.x, fma_rn(2.f, cv[s].y, -pv[s].y) + dv.y,
+                             fma_rn(2.f, cv[s].z, -pv[s].z) + dv.z, fma_rn(2.f, cv[s].w, -pv[s].w) + dv.w};
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, o), rup, uoff[s], 0, 0);
         }
     }
 }
