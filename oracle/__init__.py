@@ -23,9 +23,15 @@ Parity status of each function (what pins it; see tests/test_oracle_pins.py):
                               kappa(t); second-order convergence to a
                               manufactured solution with kappa(t, x, y); equal
                               to step_parts for a constant coefficient.
+  step_split               -- the split as printed (eqs. (fr1)-(fr2)) and Listing
+                              1's line systems: each sub-step against its printed
+                              equation solved densely with Kronecker operators and
+                              per-node kappa; the scalar recurrence of a grid mode
+                              over many steps; the phase speed of the printed
+                              split, sqrt(2) times the continuous one.
 """
 from .oracle import (build, lib, max_threads, thomas, tridiag_batched, step_parts, run,
-                     start, initial_levels, run_problem, adjoint, step_tdc)
+                     start, initial_levels, run_problem, adjoint, step_tdc, step_split)
 
 __all__ = ["build", "lib", "max_threads", "thomas", "tridiag_batched", "step_parts", "run",
-           "start", "initial_levels", "run_problem", "adjoint", "step_tdc"]
+           "start", "initial_levels", "run_problem", "adjoint", "step_tdc", "step_split"]

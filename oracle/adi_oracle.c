@@ -410,6 +410,80 @@ int oracle_adi_step_tdc(int nx, int ny, double h, double dt, const double *kappa
     return rc;
 }
 
+/* ------------------------------------------------------------------------
+ * The ADI split as printed, eqs. (fr1)-(fr2) (Sec. 2), and the line systems of
+ * Listing 1 (Sec. 3.2).  Levels sit on half steps: the x-sub-step takes
+ * (u^{k-1/2}, u^k) to u^{k+1/2}, the y-sub-step (u^k, u^{k+1/2}) to u^{k+1}.
+ * Each sub-step is a three-level scheme with the tau^2 denominator and one
+ * direction's second difference D (zero Dirichlet walls),
+ *   (u_new - 2 u_mid + u_old) / tau^2 - th_new kappa D u_new - th_old kappa D u_old = f,
+ * i.e. with g = th_new tau^2 kappa / h^2 the line system
+ *   -g u_new[k-1] + (1 + 2 g) u_new[k] - g u_new[k+1]
+ *      = 2 u_mid - u_old + th_old (tau^2 kappa / h^2) (u_old[k-1] - 2 u_old[k] + u_old[k+1]) + tau^2 f.
+ * mode 1: eqs. (fr1)-(fr2): th_new = th_old = 1/2, f^k in the x-sub-step and
+ *         f^{k+1/2} in the y-sub-step;
+ * mode 2: Listing 1: a = c = tau^2, b = 2 tau^2 + h^2 and a right-hand side
+ *         from the two older levels only, i.e. th_new = 1, th_old = 0 (the
+ *         listing has kappa = 1 and f = 0; kappa and f enter as above).
+ * ------------------------------------------------------------------------ */
+static int split_substep(int nx, int ny, double h, double dt, const double *kappa, int along_y,
+                         double th_new, double th_old, const double *u_old, const double *u_mid,
+                         const double *f, double *u_new)
+{
+    const double s = dt * dt / (h * h);
+    const int n = along_y ? ny : nx, lines = along_y ? nx : ny;
+    const size_t step = along_y ? (size_t)nx : 1;
+    int rc = ORACLE_OK;
+#pragma omp parallel
+    {
+        double *buf = malloc(sizeof(double) * 6 * (size_t)n);
+        if (!buf) {
+#pragma omp atomic write
+            rc = ORACLE_ENOMEM;
+        } else {
+            double *la = buf, *lb = buf + n, *lc = buf + 2 * n, *ld = buf + 3 * n;
+            double *cp = buf + 4 * n, *dp = buf + 5 * n;
+#pragma omp for schedule(static)
+            for (int l = 0; l < lines; ++l) {
+                for (int k = 0; k < n; ++k) {
+                    size_t p = along_y ? (size_t)k * nx + l : (size_t)l * nx + k;
+                    double lo = k > 0 ? u_old[p - step] : 0.0;
+                    double hi = k < n - 1 ? u_old[p + step] : 0.0;
+                    double g = th_new * s * kappa[p];
+                    la[k] = k > 0 ? -g : 0.0;
+                    lb[k] = 1.0 + 2.0 * g;
+                    lc[k] = k < n - 1 ? -g : 0.0;
+                    ld[k] = 2.0 * u_mid[p] - u_old[p] + th_old * s * kappa[p] * (lo - 2.0 * u_old[p] + hi) +
+                            dt * dt * (f ? f[p] : 0.0);
+                }
+                thomas(n, la, lb, lc, ld, ld, cp, dp);
+                for (int k = 0; k < n; ++k) {
+                    size_t p = along_y ? (size_t)k * nx + l : (size_t)l * nx + k;
+                    u_new[p] = ld[k];
+                }
+            }
+            free(buf);
+        }
+    }
+    return rc;
+}
+
+int oracle_adi_step_split(int nx, int ny, double h, double dt, const double *kappa, int mode,
+                          const double *u_half, const double *u_curr, const double *f,
+                          const double *f_half, double *u_half_next, double *u_next, int nthreads)
+{
+    if (check_grid(nx, ny, h, dt) || (mode != 1 && mode != 2)) return ORACLE_EINVAL;
+    if (u_half_next == u_half || u_half_next == u_curr || u_next == u_half || u_next == u_curr ||
+        u_next == u_half_next)
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    const double th_new = mode == 1 ? 0.5 : 1.0, th_old = mode == 1 ? 0.5 : 0.0;
+    int rc = split_substep(nx, ny, h, dt, kappa, 0, th_new, th_old, u_half, u_curr, f, u_half_next);
+    if (rc == ORACLE_OK)
+        rc = split_substep(nx, ny, h, dt, kappa, 1, th_new, th_old, u_curr, u_half_next, f_half, u_next);
+    return rc;
+}
+
 /* transposed line solves: along x (rows) or y (columns) */
 static int transposed_solves(int nx, int ny, double h, double dt, const double *kappa,
                              int along_y, const double *rhs, double *out)

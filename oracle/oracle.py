@@ -60,10 +60,12 @@ def lib():
                                      _dp, ctypes.c_int, _dp, _dp, ctypes.c_int]
         l.oracle_adi_step_tdc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                           _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        l.oracle_adi_step_split.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                            _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         l.oracle_max_threads.argtypes = []
         for f in (l.oracle_thomas, l.oracle_tridiag_batched, l.oracle_adi_step_parts,
                   l.oracle_adi_run, l.oracle_adi_start, l.oracle_max_threads, l.oracle_adjoint,
-                  l.oracle_adi_step_tdc):
+                  l.oracle_adi_step_tdc, l.oracle_adi_step_split):
             f.restype = ctypes.c_int
         _lib = l
     return _lib
@@ -142,6 +144,26 @@ def step_tdc(kappa_prev, kappa_next, u_prev, u_curr, h: float, dt: float, f=None
     _check(lib().oracle_adi_step_tdc(nx, ny, h, dt, _ptr(kp), _ptr(kn), _ptr(u_prev), _ptr(u_curr),
                                      _ptr(f), _ptr(out), threads), "step_tdc")
     return out
+
+
+SPLIT_MODES = {"fr": 1, "theta1": 2}
+
+
+def step_split(kappa, u_half, u_curr, h: float, dt: float, f=None, f_half=None, mode: str = "fr",
+               threads: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """One pair of sub-steps of the split as printed: mode "fr" = eqs. (fr1)-(fr2),
+    "theta1" = the line systems of Listing 1.  From (u^{k-1/2}, u^k) returns
+    (u^{k+1/2}, u^{k+1}); f is f^k (x-sub-step), f_half is f^{k+1/2} (y-sub-step)."""
+    u_half, u_curr = _f64(u_half), _f64(u_curr)
+    ny, nx = u_curr.shape
+    k = _kappa(kappa, nx, ny)
+    f = None if f is None else _f64(f)
+    f_half = None if f_half is None else _f64(f_half)
+    out_half, out = np.empty_like(u_curr), np.empty_like(u_curr)
+    _check(lib().oracle_adi_step_split(nx, ny, h, dt, _ptr(k), SPLIT_MODES[mode], _ptr(u_half),
+                                       _ptr(u_curr), _ptr(f), _ptr(f_half), _ptr(out_half), _ptr(out),
+                                       threads), "step_split")
+    return out_half, out
 
 
 def run(kappa, u_prev, u_curr, h: float, dt: float, nsteps: int,

@@ -170,9 +170,11 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
         const int qoff = inwin ? seg * 4 : kFuOOB;           // negative segments wrap past the row
         const int eoff = (lane == 0) ? (c0 - kFuKx - 1) * 4 : (lane == nl - 1) ? (c0 + wt + kFuKx) * 4 : kFuOOB;
         const int row_bytes = nx * 4;
-        const int xr0 = wv * (kFuRows / 16);               // 5 consecutive x-rows per wavefront
-        float um[kSeg], uc[kSeg], u1[kSeg], u2[kSeg], rc[kSeg], rn[kSeg];
-        float eM, eC, e1, e2, qc, qn;
+        constexpr int kR = kFuRows / 16;                    // consecutive x-rows per wavefront (5)
+        const int xr0 = wv * kR;
+        // rows of u^n j0-1 .. j0+kR and of r j0 .. j0+kR-1, each requested two rows
+        // before the row that first needs it
+        float ub[kR + 2][kSeg], eb[kR + 2], rb[kR][kSeg], qb[kR];
         auto row_ok = [&](int j) { return j >= 0 && j < ny; };
         auto load_u = [&](int j, float (&v)[kSeg], float& e) {
             const bool ok = row_ok(j);
@@ -185,17 +187,23 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
             bload8<float>(buf(A.r + (size_t)(ok ? j : 0) * nx, ok ? row_bytes : 0), voff, v);
             q = bload1<float>(buf(A.qin + (size_t)(ok ? j : 0) * A.nseg, ok ? A.nseg * 4 : 0), qoff);
         };
-        int j = r0 - kFuKy + xr0;
-        load_u(j - 1, um, eM);
-        load_u(j, uc, eC);
-        load_u(j + 1, u1, e1);
-        load_r(j, rc, qc);
+        const int j0 = r0 - kFuKy + xr0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) load_u(j0 - 1 + k, ub[k], eb[k]);
+        load_r(j0, rb[0], qb[0]);
+        load_r(j0 + 1, rb[1], qb[1]);
         const int ns = sh.src_n;
 #pragma unroll
-        for (int it = 0; it < kFuRows / 16; ++it, ++j) {
+        for (int it = 0; it < kR; ++it) {
             const int xr = xr0 + it;
-            load_u(j + 2, u2, e2);
-            load_r(j + 1, rn, qn);
+            const int j = j0 + it;
+            if (it + 4 < kR + 2) load_u(j + 3, ub[it + 4], eb[it + 4]);
+            if (it + 2 < kR) load_r(j + 2, rb[it + 2], qb[it + 2]);
+            const float(&um)[kSeg] = ub[it];
+            const float(&uc)[kSeg] = ub[it + 1];
+            const float(&u1)[kSeg] = ub[it + 2];
+            const float(&rc)[kSeg] = rb[it];
+            const float eC = eb[it + 1], qc = qb[it];
             // right-hand side: west / east neighbours across lanes, window edges loaded
             float rho[kSeg];
             {
@@ -269,17 +277,11 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
                     wout[e] = x;
                 }
             }
-            // central columns to LDS (lanes 2 .. nl-3 hold columns c0 .. c0+wt-1)
+            // central columns to LDS (lanes 1 .. nl-2 hold columns c0 .. c0+wt-1)
             if (lane >= kFuKx / kSeg && lane < nl - kFuKx / kSeg) {
                 float* dst = sh.w + xr * wt + (lane - kFuKx / kSeg) * kSeg;
                 *reinterpret_cast<float4*>(dst) = make_float4(wout[0], wout[1], wout[2], wout[3]);
                 *reinterpret_cast<float4*>(dst + 4) = make_float4(wout[4], wout[5], wout[6], wout[7]);
-            }
-            // roll
-            eM = eC; eC = e1; e1 = e2; qc = qn;
-#pragma unroll
-            for (int e = 0; e < kSeg; ++e) {
-                um[e] = uc[e]; uc[e] = u1[e]; u1[e] = u2[e]; rc[e] = rn[e];
             }
         }
     }

@@ -52,7 +52,7 @@ def case(nx, ny, cfl=0.4, seed=3, nsteps=30, nsrc=2, nrec=6):
 
 def gpu(adw, k, one_pass):
     wave = adw.Wave(k["nx"], k["ny"], k["h"], k["dt"], c=dev(k["c"]), dtype=torch.float32)
-    wave.set_tuning(fused_step=one_pass)
+    wave.set_tuning(fused_step=one_pass, fused_tile_cols=k.get("tile_cols", 0))
     info = wave.info()
     assert info["fused_step"] == int(one_pass)
     a = dev(k["u0"])
@@ -94,12 +94,38 @@ def test_plan_selection_and_bound(adw):
     w.close()
 
 
+def widest(nx):
+    """the widest tile layout: fewest tiles across, each a multiple of 8 columns"""
+    tx = -(-nx // 496)
+    return (-(-nx // tx) + 7) // 8 * 8
+
+
+def balanced_width(nx, ny, ncu):
+    """the plan's tile width: least rounds * (max(300, window) + width)"""
+    best, cost = widest(nx), None
+    tx = -(-nx // 496)
+    while tx <= -(-nx // 64):
+        wt = (-(-nx // tx) + 7) // 8 * 8
+        if wt < 64 and tx > -(-nx // 496):
+            break
+        tiles = -(-nx // wt) * -(-ny // 64)
+        c = -(-tiles // ncu) * (max(300, wt + 16) + wt)
+        if cost is None or c < cost:
+            best, cost = wt, c
+        tx += 1
+    return best
+
+
 @pytest.mark.parametrize("nx,ny", [(480, 64), (488, 65), (1000, 700), (960, 130), (64, 64), (2048, 300),
                                    (4, 200), (1504, 33)])
-def test_one_pass_matches_oracle(adw, oracle_lib, nx, ny):
+@pytest.mark.parametrize("layout", ["plan", "widest"])
+def test_one_pass_matches_oracle(adw, oracle_lib, nx, ny, layout):
     k = case(nx, ny, seed=nx + ny)
-    say(f"one-pass {nx}x{ny}")
-    got, tr, _ = gpu(adw, k, True)
+    k["tile_cols"] = widest(nx) if layout == "widest" else 0
+    say(f"one-pass {nx}x{ny} {layout}")
+    got, tr, info = gpu(adw, k, True)
+    if layout == "widest":
+        assert info["fused_tile_cols"] == widest(nx)
     ref, rtr = oracle(oracle_lib, k)
     assert rel_l2(got, ref) <= TOL
     assert rel_l2(tr, rtr) <= TOL
@@ -139,3 +165,36 @@ def test_one_pass_many_sources_in_a_tile(adw, oracle_lib):
     ref, rtr = oracle(oracle_lib, k)
     assert rel_l2(got, ref) <= TOL
     assert rel_l2(tr, rtr) <= TOL
+
+
+def test_tile_width_plan(adw):
+    """The plan balances the tiles over the device's compute units; the width can
+    be forced and set back to automatic; bad widths are rejected."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    for n in (8192, 4096, 2048, 1024):
+        w = adw.Wave(n, n, 1.0 / (n + 1), 0.5 / (n + 1), c=1.0, dtype=torch.float32)
+        i = w.info()
+        assert i["fused_tile_cols"] == balanced_width(n, n, ncu), (n, i)
+        assert i["fused_tiles"] == -(-n // i["fused_tile_cols"]) * -(-n // 64)
+        w.set_tuning(fused_tile_cols=488)
+        assert w.info()["fused_tile_cols"] == 488
+        w.set_tuning(fused_tile_cols=-1)
+        assert w.info()["fused_tile_cols"] == i["fused_tile_cols"]
+        for bad in (500, 100):
+            with pytest.raises(RuntimeError):
+                w.set_tuning(fused_tile_cols=bad)
+        w.close()
+
+
+def test_forced_widths_agree(adw):
+    """Different tile layouts truncate at different places: each stays within
+    the bound of the exact step."""
+    k = case(1000, 700, cfl=0.5, seed=4, nsteps=40)
+    ref, rtr, _ = gpu(adw, k, False)
+    for wt in (64, 136, 256, 496):
+        k["tile_cols"] = wt
+        say(f"one-pass 1000x700 width {wt}")
+        got, tr, info = gpu(adw, k, True)
+        assert info["fused_tile_cols"] == wt
+        assert rel_l2(got, ref) <= 3e-6
+        assert rel_l2(tr, rtr) <= 3e-6
