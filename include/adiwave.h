@@ -173,6 +173,32 @@ adi_status adi_adjoint_backward(adi_wave_t w, const adi_source* f, const adi_rec
 adi_status adi_wave_step_tdc(adi_wave_t w, void** u_prev, void** u_curr, const void* kappa_prev,
                              const void* kappa_next, const adi_source* f, const adi_receivers* rec);
 
+/* Paper-fidelity modes: one pair of sub-steps of the ADI split exactly as
+ * printed.  Levels sit on half steps; the x-sub-step takes (u^{k-1/2}, u^k) to
+ * u^{k+1/2} and the y-sub-step (u^k, u^{k+1/2}) to u^{k+1}, each a three-level
+ * scheme with the tau^2 denominator and one direction's second difference:
+ *   ADI_SPLIT_FR      eqs. (fr1)-(fr2) of Sec. 2: weights 1/2 on the new and the
+ *                     oldest level of each sub-step;
+ *   ADI_SPLIT_THETA1  the line systems of Listing 1 (Sec. 3.2: a = c = tau^2,
+ *                     b = 2 tau^2 + h^2): weight 1 on the new level, a right-hand
+ *                     side from the two older levels only (kappa and f enter as
+ *                     kappa tau^2 on the second difference and tau^2 f).
+ * u_half: device nx*ny, u^{k-1/2} on entry and u^{k+1/2} on return; u_curr: u^k
+ * on entry and u^{k+1} on return (distinct buffers of the handle's dtype; no
+ * pointer rotation).  f: sources of f^k for the x-sub-step, f_half: of
+ * f^{k+1/2} for the y-sub-step (count values each, already divided by h^2, or
+ * NULL); rec: receivers sampled from u^{k+1} (count values).  The lines are
+ * solved by cyclic reduction, one launch per level (the first call allocates
+ * 3 nx*ny values).  Neither mode is the scheme of adi_wave_step: the printed
+ * split moves waves sqrt(2) times too fast and Listing 1's system is first
+ * order and dissipative; they reproduce the paper's formulas for comparison. */
+typedef enum {
+    ADI_SPLIT_FR = 1,
+    ADI_SPLIT_THETA1 = 2
+} adi_split_mode;
+adi_status adi_wave_step_split(adi_wave_t w, int mode, void* u_half, void* u_curr, const adi_source* f,
+                               const adi_source* f_half, const adi_receivers* rec);
+
 /* ------------------------------------------------------ batched simulations -- */
 
 /* Many independent simulations of uneven grid sizes advanced together: each

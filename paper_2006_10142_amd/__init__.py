@@ -191,6 +191,32 @@ class Wave:
             return u_prev, u_curr
         return u_curr, u_prev
 
+    SPLIT_MODES = {"fr": 1, "theta1": 2}
+
+    def step_split(self, u_half, u_curr, mode="fr", src_idx=None, src_amp=None, src_amp_half=None,
+                   rec_idx=None, traces=None) -> Tuple:
+        """One pair of sub-steps of the split as printed (mode "fr": eqs. (fr1)-(fr2);
+        "theta1": Listing 1's line systems).  u_half holds u^{k-1/2} and becomes
+        u^{k+1/2}; u_curr holds u^k and becomes u^{k+1} (in place).  src_amp: values
+        of f^k at src_idx, src_amp_half: of f^{k+1/2}; traces: receivers of u^{k+1}."""
+        self._sync_stream()
+        a = _field(u_half, self.dtype, self._shape(), "u_half")
+        b = _field(u_curr, self.dtype, self._shape(), "u_curr")
+        src = self._sources(src_idx, src_amp, 1) if src_amp is not None else None
+        src_h = self._sources(src_idx, src_amp_half, 1) if src_amp_half is not None else None
+        rec = None
+        if rec_idx is not None and rec_idx.numel() > 0:
+            _index(rec_idx, "rec_idx")
+            if traces is None or traces.dtype != self.dtype or not traces.is_contiguous() \
+                    or traces.numel() < rec_idx.numel():
+                raise ValueError("traces must be a contiguous tensor of the handle dtype with count values")
+            rec = _lib.AdiReceivers(rec_idx.numel(), rec_idx.data_ptr(), traces.data_ptr())
+        _lib.check(_lib.load().adi_wave_step_split(self._h, self.SPLIT_MODES[mode], a, b,
+                                                   ctypes.byref(src) if src else None,
+                                                   ctypes.byref(src_h) if src_h else None,
+                                                   ctypes.byref(rec) if rec else None))
+        return u_half, u_curr
+
     def profile(self, u_prev, u_curr, nsteps: int, src_idx=None, src_amp=None):
         """Run nsteps steps with per-launch events; returns ((u_prev, u_curr), {kernel: mean ms})."""
         self._sync_stream()

@@ -67,6 +67,8 @@ _SIGNATURES = {
                       ctypes.POINTER(AdiReceivers), ctypes.c_int],
     "adi_wave_step_tdc": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp,
                           ctypes.POINTER(AdiSource), ctypes.POINTER(AdiReceivers)],
+    "adi_wave_step_split": [_vp, ctypes.c_int, _vp, _vp, ctypes.POINTER(AdiSource),
+                            ctypes.POINTER(AdiSource), ctypes.POINTER(AdiReceivers)],
     "adi_wave_destroy": [_vp],
     "tridiag_solve_batched": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
                               ctypes.c_longlong, ctypes.c_longlong, _vp],

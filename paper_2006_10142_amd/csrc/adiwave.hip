@@ -1020,3 +1020,4 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
 #include "batch.hpp"
 #include "adjoint.hpp"
 #include "tdc.hpp"
+#include "split.hpp"
