@@ -43,6 +43,7 @@ constexpr int kFuWmax = 64 * kSeg - 2 * kFuKx;   // widest tile (496)
 constexpr int kFuSrc = 32;          // point sources staged per tile
 constexpr int kFuRing = 16;         // rows of r requested ahead in a y-window
 constexpr int kFuUp = (kFuHt * kFuWmax / 4 + 1023) / 1024;   // float4 updated per thread (8)
+constexpr int kFuNT = 2;            // buffer cache policy: non-temporal (a last use of the line)
 constexpr int kFuOOB = 0x40000000;  // byte offset beyond every buffer range used here
                                     // (grids hold at most 2^27 values, 2^29 bytes)
 
@@ -117,6 +118,13 @@ __device__ __forceinline__ void wave_scan_bwd2(float& a, float& b, int lane)
     else if (lane < 48) { ca = a48; cb = b48; }
     a = fma_rn(b, ca, a);
     b = b * cb;
+}
+
+// one value through a buffer resource, marked as the last use of its line (the
+// x-phase read it first; the line should not displace data still to be re-read)
+__device__ __forceinline__ float fu_load1_nt(rsrc_t rs, int voff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, 0, kFuNT));
 }
 
 // block -> work index: the blocks of one XCD (b mod 8) take one contiguous band
@@ -304,7 +312,7 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
     float rbuf[kFuRing];
     if (ythr) {
 #pragma unroll
-        for (int k = 0; k < kFuRing; ++k, off += rowb) rbuf[k] = bload1<float>(rall, (int)off);
+        for (int k = 0; k < kFuRing; ++k, off += rowb) rbuf[k] = fu_load1_nt(rall, (int)off);
     }
     __syncthreads();
     float gk[kFuNb], qk[kFuNb];
@@ -315,7 +323,7 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
         for (int k = 0; k < kFuNb; ++k, wo += wt) {
             const float rk = rbuf[k % kFuRing];
             if (k + kFuRing < kFuNb) {
-                rbuf[k % kFuRing] = bload1<float>(rall, (int)off);
+                rbuf[k % kFuRing] = fu_load1_nt(rall, (int)off);
                 off += rowb;
             }
             const float m = pivot_step<float>(rk, q);
@@ -337,7 +345,9 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
 
     // ------------------------------------------------------ phase 3: update
     // every float4 of the tile's u^n and u^{n-1} that this thread updates is
-    // requested before the barrier, all at once
+    // requested before the barrier, all at once; these loads and the stores of
+    // u^{n+1} are last uses of their lines within the step (non-temporal), so
+    // they leave L2 room for the rows that later tiles and phases re-read
     const int nq = wt / 4;                                  // float4 per tile row
     const int total = kFuHt * nq;
     const int lim = (int)(npts * 4);
@@ -351,8 +361,8 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
         const int orow = idx / nq, oq = idx - orow * nq;
         const int j = r0 + orow, i = c0 + 4 * oq;
         uoff[s] = (idx < total && j < ny && i < nx) ? (j * nx + i) * 4 : kFuOOB;
-        cv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ruc, uoff[s], 0, 0));
-        pv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rup, uoff[s], 0, 0));
+        cv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ruc, uoff[s], 0, kFuNT));
+        pv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rup, uoff[s], 0, kFuNT));
     }
     __syncthreads();
 #pragma unroll
@@ -363,7 +373,7 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
             const float4 dv = *reinterpret_cast<const float4*>(sh.w + (kFuKy + orow) * wt + 4 * oq);
             const f32x4 o = {fma_rn(2.f, cv[s].x, -pv[s].x) + dv.x, fma_rn(2.f, cv[s].y, -pv[s].y) + dv.y,
                              fma_rn(2.f, cv[s].z, -pv[s].z) + dv.z, fma_rn(2.f, cv[s].w, -pv[s].w) + dv.w};
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, o), rup, uoff[s], 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, o), rup, uoff[s], 0, kFuNT);
         }
     }
 }
