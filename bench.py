@@ -319,6 +319,14 @@ def main():
                "step_frac_of_peak": round(step_gbps / HBM_PEAK_GBPS, 4),
                "kernel_ms": {k: round(v, 5) for k, v in kms.items()},
                "launch_plan": info, "wall_s_timed": round(wall, 4)}
+        # HBM bytes the counters measured for every launch of a step (committed
+        # rocprofv3 summary of the same sources), over the measured step time
+        counted = [load_traffic(name, k, 0.0) for k in kms]
+        if kms and all(c is not None for c in counted):
+            per_step = sum(counted)
+            gbps = per_step / (ms / args.steps / 1e3) / 1e9
+            res["hbm_counted"] = {"bytes_per_step": round(per_step), "GBps": round(gbps, 1),
+                                  "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
         return a, b, res
 
     a, b, main = measure(a, b)
@@ -368,12 +376,17 @@ def main():
         "step_algorithmic_bytes_per_node": main["step_algorithmic_bytes_per_node"],
         "step_algorithmic_GBps": main["step_algorithmic_GBps"],
         "step_frac_of_peak": main["step_frac_of_peak"],
+        "hbm_counted": main.get("hbm_counted"),
         "kernel_ms": main["kernel_ms"],
         "two_pass": two_pass,
         "copy_GBps": round(copy_gbps, 1),
         "create_ms": round(create_ms, 2),
         "wall_s_timed": main["wall_s_timed"],
     }
+    for blk in (out, two_pass):
+        hc = blk.get("hbm_counted") if blk else None
+        if hc and copy_gbps > 0:
+            hc["frac_of_copy"] = round(hc["GBps"] / copy_gbps, 4)
     wave.close()
     del a, b
     torch.cuda.empty_cache()

@@ -302,6 +302,8 @@ typedef struct {
                                  chosen to balance the tiles over the device's compute
                                  units unless set through adi_wave_set_tuning */
     int fused_tiles;          /* one-pass step: tiles per step (one workgroup each) */
+    int fused_lane_nodes;     /* one-pass step: x-line nodes per lane (8, or 4 on tiles of at
+                                 most 240 columns whose r stays in LDS for the y-lines) */
 } adi_wave_info;
 
 adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
@@ -320,8 +322,10 @@ typedef struct {
                                  2 = cyclic reduction, one launch per level for all lines
                                  of a sweep (the paper's Sec. 3.1 solver, as a same-GPU
                                  baseline; allocates 3 nx*ny values), 0 = keep */
-    int fused_tile_cols;      /* one-pass tile width: a multiple of 8, at most 496;
-                                 -1 = back to the automatic choice, 0 = keep */
+    int fused_tile_cols;      /* one-pass tile width: a multiple of 8, at most 496 (240 with 4
+                                 nodes per lane); -1 = back to the automatic choice, 0 = keep */
+    int fused_lane_nodes;     /* one-pass x-line nodes per lane: 8 or 4; -1 = back to the
+                                 automatic choice (4 where the tiles come out narrow), 0 = keep */
 } adi_tuning;
 adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t);
 

@@ -52,7 +52,7 @@ def case(nx, ny, cfl=0.4, seed=3, nsteps=30, nsrc=2, nrec=6):
 
 def gpu(adw, k, one_pass):
     wave = adw.Wave(k["nx"], k["ny"], k["h"], k["dt"], c=dev(k["c"]), dtype=torch.float32)
-    wave.set_tuning(fused_step=one_pass, fused_tile_cols=k.get("tile_cols", 0))
+    wave.set_tuning(fused_step=one_pass, fused_lane_nodes=k.get("lane", 0), fused_tile_cols=k.get("tile_cols", 0))
     info = wave.info()
     assert info["fused_step"] == int(one_pass)
     a = dev(k["u0"])
@@ -94,9 +94,9 @@ def test_plan_selection_and_bound(adw):
     w.close()
 
 
-def widest(nx):
+def widest(nx, wmax=496):
     """the widest tile layout: fewest tiles across, each a multiple of 8 columns"""
-    tx = -(-nx // 496)
+    tx = -(-nx // wmax)
     return (-(-nx // tx) + 7) // 8 * 8
 
 
@@ -118,14 +118,19 @@ def balanced_width(nx, ny, ncu):
 
 @pytest.mark.parametrize("nx,ny", [(480, 64), (488, 65), (1000, 700), (960, 130), (64, 64), (2048, 300),
                                    (4, 200), (1504, 33)])
-@pytest.mark.parametrize("layout", ["plan", "widest"])
+@pytest.mark.parametrize("layout", ["auto", "lane8", "lane8_widest", "lane4", "lane4_widest"])
 def test_one_pass_matches_oracle(adw, oracle_lib, nx, ny, layout):
+    """layouts: the automatic plan; eight or four nodes per lane (four: r kept in LDS
+    for the y-lines), each on the plan's width and on the widest tiles"""
     k = case(nx, ny, seed=nx + ny)
-    k["tile_cols"] = widest(nx) if layout == "widest" else 0
+    k["lane"] = {"auto": -1, "lane8": 8, "lane8_widest": 8, "lane4": 4, "lane4_widest": 4}[layout]
+    k["tile_cols"] = widest(nx, 240 if k["lane"] == 4 else 496) if layout.endswith("widest") else -1
     say(f"one-pass {nx}x{ny} {layout}")
     got, tr, info = gpu(adw, k, True)
-    if layout == "widest":
-        assert info["fused_tile_cols"] == widest(nx)
+    if layout.endswith("widest"):
+        assert info["fused_tile_cols"] == widest(nx, 240 if k["lane"] == 4 else 496)
+    if k["lane"] > 0:
+        assert info["fused_lane_nodes"] == k["lane"]
     ref, rtr = oracle(oracle_lib, k)
     assert rel_l2(got, ref) <= TOL
     assert rel_l2(tr, rtr) <= TOL
@@ -140,13 +145,15 @@ def test_one_pass_equals_two_pass_on_gpu(adw):
     assert rel_l2(ta, tb) <= 3e-6
 
 
-def test_one_pass_near_the_bound(adw, oracle_lib):
+@pytest.mark.parametrize("lane", [8, 4])
+def test_one_pass_near_the_bound(adw, oracle_lib, lane):
     """r_max = 0.17, just inside the bound (the truncation is then closest to 2^-24)."""
     nx = ny = 512
     h = 1.0 / 513
     dt = np.sqrt(2 * 0.17) * h / 3.0
     k = case(nx, ny, seed=5, nsteps=80)
     k["dt"] = dt
+    k["lane"] = lane
     say("one-pass near bound")
     got, tr, info = gpu(adw, k, True)
     assert 0.165 < info["r_max"] < 0.175
@@ -155,10 +162,12 @@ def test_one_pass_near_the_bound(adw, oracle_lib):
     assert rel_l2(tr, rtr) <= TOL
 
 
-def test_one_pass_many_sources_in_a_tile(adw, oracle_lib):
+@pytest.mark.parametrize("lane", [8, 4])
+def test_one_pass_many_sources_in_a_tile(adw, oracle_lib, lane):
     """More point sources in one tile than it stages (read from memory instead),
     including repeated nodes."""
     k = case(480, 64, seed=11, nsteps=20, nsrc=40)
+    k["lane"] = lane
     k["src_idx"][5] = k["src_idx"][3]
     say("one-pass 40 sources")
     got, tr, _ = gpu(adw, k, True)
@@ -175,11 +184,15 @@ def test_tile_width_plan(adw):
         w = adw.Wave(n, n, 1.0 / (n + 1), 0.5 / (n + 1), c=1.0, dtype=torch.float32)
         i = w.info()
         assert i["fused_tile_cols"] == balanced_width(n, n, ncu), (n, i)
+        assert i["fused_lane_nodes"] == (4 if balanced_width(n, n, ncu) <= 128 else 8)
         assert i["fused_tiles"] == -(-n // i["fused_tile_cols"]) * -(-n // 64)
-        w.set_tuning(fused_tile_cols=488)
-        assert w.info()["fused_tile_cols"] == 488
-        w.set_tuning(fused_tile_cols=-1)
+        w.set_tuning(fused_lane_nodes=8, fused_tile_cols=488)
+        assert w.info()["fused_tile_cols"] == 488 and w.info()["fused_lane_nodes"] == 8
+        with pytest.raises(RuntimeError):
+            w.set_tuning(fused_lane_nodes=4, fused_tile_cols=248)     # 4 nodes per lane: <= 240
+        w.set_tuning(fused_lane_nodes=-1, fused_tile_cols=-1)
         assert w.info()["fused_tile_cols"] == i["fused_tile_cols"]
+        assert w.info()["fused_lane_nodes"] == i["fused_lane_nodes"]
         for bad in (500, 100):
             with pytest.raises(RuntimeError):
                 w.set_tuning(fused_tile_cols=bad)
@@ -191,10 +204,11 @@ def test_forced_widths_agree(adw):
     the bound of the exact step."""
     k = case(1000, 700, cfl=0.5, seed=4, nsteps=40)
     ref, rtr, _ = gpu(adw, k, False)
-    for wt in (64, 136, 256, 496):
+    for wt, lane in ((64, 8), (136, 8), (256, 8), (496, 8), (64, 4), (120, 4), (240, 4)):
         k["tile_cols"] = wt
-        say(f"one-pass 1000x700 width {wt}")
+        k["lane"] = lane
+        say(f"one-pass 1000x700 width {wt}, {lane} nodes per lane")
         got, tr, info = gpu(adw, k, True)
-        assert info["fused_tile_cols"] == wt
+        assert info["fused_tile_cols"] == wt and info["fused_lane_nodes"] == lane
         assert rel_l2(got, ref) <= 3e-6
         assert rel_l2(tr, rtr) <= 3e-6
