@@ -273,8 +273,8 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
     const T* __restrict__ w = A.w;
     const T* __restrict__ r = A.r;
     const T* __restrict__ u = A.u;
-    const T* __restrict__ v = A.v;
-    T* __restrict__ out = A.out;
+    const T* v = A.v;     // may be the same buffer as out (u^{n+1} written over u^{n-1})
+    T* out = A.out;
     const bool scale = A.rhs_times_r != 0;
     T qa[M], da[M];
     T q = T(0), dpv = T(0);
@@ -286,7 +286,7 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
             rr[k - g0] = T(0); ww[k - g0] = T(0);
             if (FULL || k < L - 1) {
                 rr[k - g0] = r[base + (size_t)k * nx];
-                ww[k - g0] = w[base + (size_t)k * nx];
+                ww[k - g0] = __builtin_nontemporal_load(&w[base + (size_t)k * nx]);
                 if (scale) ww[k - g0] *= rr[k - g0];
             }
         }
@@ -316,7 +316,7 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
             if (FULL || k < L) {
                 const size_t p = base + (size_t)k * nx;
                 uu[g1 - k] = hasu ? u[p] : T(0);
-                vv[g1 - k] = hasv ? v[p] : T(0);
+                vv[g1 - k] = hasv ? __builtin_nontemporal_load(&v[p]) : T(0);
             }
         }
 #pragma unroll
@@ -324,7 +324,7 @@ __device__ __forceinline__ void ysolve_chunk(const YArgs<T>& A, size_t base, siz
             if (FULL || k < L) {
                 if (k < L - 1) x = fma_rn(qa[k], x, da[k]);
                 else x = Xc;
-                out[base + (size_t)k * nx] = fma_rn(A.beta, vv[g1 - k], A.alpha * uu[g1 - k]) + x;
+                __builtin_nontemporal_store(fma_rn(A.beta, vv[g1 - k], A.alpha * uu[g1 - k]) + x, &out[base + (size_t)k * nx]);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
