@@ -442,21 +442,23 @@ bool fused_bound_holds(double rm)
     return 4.0 * std::pow(qs, kFuKy + 1) <= std::ldexp(1.0, -24);
 }
 
-// Tile width of the one-pass step.  The x-phase of a tile issues a fixed number
-// of instructions per row whatever its width (one wavefront per row), which at
-// full occupancy costs about as much time as streaming kFuXfloor columns; the
-// rest of a tile's time grows with its window (x-phase traffic) and its width
-// (y-phase, update).  A step is ceil(tiles / CUs) rounds of tiles, so with ncu > 0
-// the width minimises rounds * (max(floor, window) + width); with ncu = 0 (many
-// simulations share the rounds) the tiles are the widest that fit.
-constexpr int kFuXfloor = 300;
+// Tile width and lane variant of the one-pass step.  A step is ceil(tiles / CUs)
+// rounds of tiles, and a tile under full load takes a fixed time (the x-rows'
+// instruction stream, one wavefront per row, and the phase barriers) plus a
+// part that grows with its width (traffic, y-lines, update).  The two parts,
+// in ns, were fitted to both kernels on MI355X from 1024^2 to 8192^2; the plan
+// takes the width, and with ncu > 0 the variant, of least rounds * tile time.
+// With ncu = 0 (many simulations share the rounds) the tiles are the widest.
+constexpr int kFuT8a = 16000, kFuT8b = 30;   // eight nodes per lane (fused.hpp)
+constexpr int kFuT4a = 12000, kFuT4b = 15;   // four nodes per lane (fused4.hpp)
 constexpr int kFuWmin = 64;
 
-int fused_width(int nx, int ny, int ncu, int wmax)
+int fused_width(int nx, int ny, int ncu, int wmax, int ta, int tb, long long* cost)
 {
     const int tx0 = (nx + wmax - 1) / wmax;
     auto width = [&](int tx) { return ((nx + tx - 1) / tx + 7) / 8 * 8; };
     int best = width(tx0);
+    *cost = 0;
     if (ncu <= 0) return best;
     const long long ty = (ny + kFuHt - 1) / kFuHt;
     long long best_cost = -1;
@@ -465,12 +467,13 @@ int fused_width(int nx, int ny, int ncu, int wmax)
         if (wt < kFuWmin && tx > tx0) break;
         const long long tiles = (long long)((nx + wt - 1) / wt) * ty;
         const long long rounds = (tiles + ncu - 1) / ncu;
-        const long long cost = rounds * (std::max(kFuXfloor, wt + 2 * kFuKx) + wt);
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
+        const long long c = rounds * (ta + (long long)tb * wt);
+        if (best_cost < 0 || c < best_cost) {
+            best_cost = c;
             best = wt;
         }
     }
+    *cost = best_cost;
     return best;
 }
 
@@ -479,14 +482,12 @@ void fused_plan(adi_wave_s* w)
     w->fused_ok = (w->dtype == ADI_F32 && w->nx % 4 == 0 && fused_bound_holds(w->rmax)) ? 1 : 0;
     const bool autoon = (long long)w->nx * w->ny >= (1LL << 16);
     w->fstep = w->fused_ok && (w->fused_mode == 1 || (w->fused_mode == 0 && autoon)) ? 1 : 0;
-    // four nodes per lane where the tiles come out narrow: a narrow tile leaves
-    // most lanes of its x-rows idle at eight nodes per lane, and four keep twice
-    // as many busy (measured: 1024^2 in 14 us against 17 us; from 2048^2 on the
-    // eight-node tiles are faster)
-    w->f_lane = w->f_lane_user ? w->f_lane_user
-                : (w->f_ncu > 0 && fused_width(w->nx, w->ny, w->f_ncu, kFuWmax) <= 128) ? 4 : 8;
+    long long c8 = 0, c4 = 0;
+    const int w8 = fused_width(w->nx, w->ny, w->f_ncu, kFuWmax, kFuT8a, kFuT8b, &c8);
+    const int w4 = fused_width(w->nx, w->ny, w->f_ncu, kF4Wmax, kFuT4a, kFuT4b, &c4);
+    w->f_lane = w->f_lane_user ? w->f_lane_user : (w->f_ncu > 0 && c4 < c8) ? 4 : 8;
     const int wmax = w->f_lane == 4 ? kF4Wmax : kFuWmax;
-    w->f_wt = w->f_wt_user > 0 ? std::min(w->f_wt_user, wmax) : fused_width(w->nx, w->ny, w->f_ncu, wmax);
+    w->f_wt = w->f_wt_user > 0 ? std::min(w->f_wt_user, wmax) : (w->f_lane == 4 ? w4 : w8);
     w->f_tx = (w->nx + w->f_wt - 1) / w->f_wt;
     w->f_tiles = w->f_tx * ((w->ny + kFuHt - 1) / kFuHt);
     w->f_grid = (w->f_tiles + 7) / 8 * 8;

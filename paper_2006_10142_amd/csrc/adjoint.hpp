@@ -76,26 +76,32 @@ __global__ void __launch_bounds__(256) k_adjoint_points(T* __restrict__ lam, con
                                                         const int* __restrict__ sidx, T* __restrict__ out,
                                                         int nsrc, T tau2, long long npts)
 {
-    __shared__ int tile[256];
+    __shared__ int itile[256];
+    __shared__ T vtile[256];
     const int k = blockIdx.x * 256 + threadIdx.x;
-    if (out && k < nsrc) {
-        const int id = sidx[k];
-        out[k] = (id >= 0 && id < npts) ? tau2 * t[id] / r[id] : T(0);
-    }
-    if (!lam || blockIdx.x * 256 >= nrec) return;          // uniform per block
-    const int id = k < nrec ? ridx[k] : -1;
+    // every independent load first: the source and receiver indices and values
+    const int sid = (out && k < nsrc) ? sidx[k] : -1;
+    const bool rec_block = lam && (int)(blockIdx.x * 256) < nrec;   // uniform per block
+    const int id = (rec_block && k < nrec) ? ridx[k] : -1;
+    const T val = (rec_block && k < nrec) ? vals[k] : T(0);
     bool mine = id >= 0 && id < npts;                        // first receiver of its node
-    T acc = mine ? lam[id] : T(0);
+    const T lam0 = mine ? lam[id] : T(0);
+    if (out && k < nsrc) out[k] = (sid >= 0 && sid < npts) ? tau2 * t[sid] / r[sid] : T(0);
+    if (!rec_block) return;
+    T acc = lam0;
     for (int base = 0; base < nrec; base += 256) {
+        const bool own = base == (int)(blockIdx.x * 256);       // this block's receivers: registers
         __syncthreads();
-        if (base + (int)threadIdx.x < nrec) tile[threadIdx.x] = ridx[base + threadIdx.x];
+        if (base + (int)threadIdx.x < nrec) {
+            itile[threadIdx.x] = own ? id : ridx[base + threadIdx.x];
+            vtile[threadIdx.x] = own ? val : vals[base + threadIdx.x];
+        }
         __syncthreads();
         const int lim = min(256, nrec - base);
         for (int q = 0; mine && q < lim; ++q) {
-            if (tile[q] != id) continue;
-            const int j = base + q;
-            if (j < k) mine = false;                         // an earlier receiver owns the node
-            else acc += vals[j];
+            if (itile[q] != id) continue;
+            if (base + q < k) mine = false;                  // an earlier receiver owns the node
+            else acc += vtile[q];
         }
     }
     if (mine) lam[id] = acc;

@@ -16,7 +16,9 @@
 //            r0 + 24 + 16 k), k = 0..3, one thread each, Thomas in registers on
 //            w and r from LDS; the 16 central rows of d replace w.  Output rows
 //            stay 9 rows from every cut, so the bound of fused.hpp holds as is.
-//   Phase 3: u^{n+1} = 2 u^n - u^{n-1} + d over the tile, written over u^{n-1}.
+//   Phase 3: u^{n+1} = 2 u^n - u^{n-1} + d, written over u^{n-1}, by the wavefront
+//            that solved each x-row: u^n of the row is still in its registers
+//            (not read again) and u^{n-1} was requested during the x-phase.
 
 namespace adw {
 
@@ -25,7 +27,6 @@ constexpr int kF4Wmax = 64 * kF4Seg - 2 * kFuKx;   // widest tile (240)
 constexpr int kF4Hb = 16;                      // output rows per y-window
 constexpr int kF4Nb = kF4Hb + 2 * kFuKy;       // rows of a y-window (32)
 constexpr int kF4Win = kFuHt / kF4Hb;          // y-windows per column (4)
-constexpr int kF4Up = (kFuHt * kF4Wmax / 4 + 1023) / 1024;   // float4 updated per thread (4)
 
 struct FShared4 {
     float w[kFuRows * kF4Wmax];
@@ -71,18 +72,20 @@ __device__ __forceinline__ void fused4_tile(const FArgs& A, const int tile, FSha
     }
     __syncthreads();
 
+    constexpr int kR = kFuRows / 16;                           // consecutive x-rows per wavefront (5)
+    const int xr0 = wv * kR;
+    const int row_bytes = nx * 4;
+    const int col0 = c0 - kFuKx + lane * kF4Seg;              // first column of the lane
+    const int voff = lane < nl ? col0 * 4 : kFuOOB;
+    float keep_u[kR][kF4Seg], keep_p[kR][kF4Seg];             // u^n and u^{n-1} of the wavefront's rows
+
     // ---------------------------------------------------------- phase 1: x
     {
         const bool inwin = lane < nl;
-        const int col0 = c0 - kFuKx + lane * kF4Seg;          // first column of the lane
         const int seg = (c0 - kFuKx) / kSeg + (lane >> 1);     // its full-line 8-node segment
         const bool odd = lane & 1;
-        const int voff = inwin ? col0 * 4 : kFuOOB;
         const int qoff = inwin ? seg * 4 : kFuOOB;             // negative segments wrap past the row
         const int eoff = (lane == 0) ? (c0 - kFuKx - 1) * 4 : (lane == nl - 1) ? (c0 + wt + kFuKx) * 4 : kFuOOB;
-        const int row_bytes = nx * 4;
-        constexpr int kR = kFuRows / 16;                       // consecutive x-rows per wavefront (5)
-        const int xr0 = wv * kR;
         float ub[kR + 2][kF4Seg], eb[kR + 2], rb[kR][kF4Seg], qb[kR];
         auto row_ok = [&](int j) { return j >= 0 && j < ny; };
         auto load4 = [&](rsrc_t rs, float (&v)[kF4Seg]) {
@@ -117,6 +120,19 @@ __device__ __forceinline__ void fused4_tile(const FArgs& A, const int tile, FSha
             const float(&u1)[kF4Seg] = ub[it + 2];
             const float(&rc)[kF4Seg] = rb[it];
             const float eC = eb[it + 1];
+            // u^n of the row stays for the update; u^{n-1} of the row is requested now,
+            // for the tile's own nodes only (the halo nodes belong to other tiles)
+#pragma unroll
+            for (int e = 0; e < kF4Seg; ++e) keep_u[it][e] = uc[e];
+            {
+                const bool ok = row_ok(j);
+                const bool own = xr >= kFuKy && xr < kFuKy + kFuHt && lane >= kFuKx / kF4Seg &&
+                                 lane < nl - kFuKx / kF4Seg;
+                const f32x4 pv = __builtin_bit_cast(
+                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(buf(A.up + (size_t)(ok ? j : 0) * nx, ok ? row_bytes : 0),
+                                                                 own ? voff : kFuOOB, 0, kFuNT));
+                keep_p[it][0] = pv.x; keep_p[it][1] = pv.y; keep_p[it][2] = pv.z; keep_p[it][3] = pv.w;
+            }
             // right-hand side: west / east neighbours across lanes, window edges loaded
             float rho[kF4Seg];
             {
@@ -238,32 +254,24 @@ __device__ __forceinline__ void fused4_tile(const FArgs& A, const int tile, FSha
     }
 
     // ------------------------------------------------------ phase 3: update
-    const int nq = wt / 4;                                  // float4 per tile row
-    const int total = kFuHt * nq;
-    const int lim = (int)(npts * 4);
-    const rsrc_t ruc = buf(A.uc, lim);
-    const rsrc_t rup = buf(static_cast<const float*>(A.up), lim);
-    f32x4 cv[kF4Up], pv[kF4Up];
-    int uoff[kF4Up];
-#pragma unroll
-    for (int s = 0; s < kF4Up; ++s) {
-        const int idx = s * 1024 + t;
-        const int orow = idx / nq, oq = idx - orow * nq;
-        const int j = r0 + orow, i = c0 + 4 * oq;
-        uoff[s] = (idx < total && j < ny && i < nx) ? (j * nx + i) * 4 : kFuOOB;
-        cv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ruc, uoff[s], 0, kFuNT));
-        pv[s] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rup, uoff[s], 0, kFuNT));
-    }
     __syncthreads();
+    {
+        const bool outlane = lane >= kFuKx / kF4Seg && lane < nl - kFuKx / kF4Seg;
 #pragma unroll
-    for (int s = 0; s < kF4Up; ++s) {
-        const int idx = s * 1024 + t;
-        if (idx < total) {
-            const int orow = idx / nq, oq = idx - orow * nq;
-            const float4 dv = *reinterpret_cast<const float4*>(sh.w + (kFuKy + orow) * wt + 4 * oq);
-            const f32x4 o = {fma_rn(2.f, cv[s].x, -pv[s].x) + dv.x, fma_rn(2.f, cv[s].y, -pv[s].y) + dv.y,
-                             fma_rn(2.f, cv[s].z, -pv[s].z) + dv.z, fma_rn(2.f, cv[s].w, -pv[s].w) + dv.w};
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, o), rup, uoff[s], 0, kFuNT);
+        for (int it = 0; it < kR; ++it) {
+            const int xr = xr0 + it;
+            const int j = r0 - kFuKy + xr;
+            if (xr >= kFuKy && xr < kFuKy + kFuHt && outlane) {
+                const float4 dv = *reinterpret_cast<const float4*>(sh.w + xr * wt + (lane - kFuKx / kF4Seg) * kF4Seg);
+                const f32x4 o = {fma_rn(2.f, keep_u[it][0], -keep_p[it][0]) + dv.x,
+                                 fma_rn(2.f, keep_u[it][1], -keep_p[it][1]) + dv.y,
+                                 fma_rn(2.f, keep_u[it][2], -keep_p[it][2]) + dv.z,
+                                 fma_rn(2.f, keep_u[it][3], -keep_p[it][3]) + dv.w};
+                const bool ok = j >= 0 && j < ny;
+                __builtin_amdgcn_raw_buffer_store_b128(
+                    __builtin_bit_cast(i32x4, o), buf(static_cast<const float*>(A.up) + (size_t)(ok ? j : 0) * nx, ok ? row_bytes : 0),
+                    voff, 0, kFuNT);
+            }
         }
     }
 }

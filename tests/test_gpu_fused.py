@@ -100,20 +100,28 @@ def widest(nx, wmax=496):
     return (-(-nx // tx) + 7) // 8 * 8
 
 
-def balanced_width(nx, ny, ncu):
-    """the plan's tile width: least rounds * (max(300, window) + width)"""
-    best, cost = widest(nx), None
-    tx = -(-nx // 496)
+def plan(nx, ny, ncu, wmax, ta, tb):
+    """the plan's width for one lane variant: least rounds * (ta + tb * width)"""
+    best, cost = None, None
+    tx0 = -(-nx // wmax)
+    tx = tx0
     while tx <= -(-nx // 64):
         wt = (-(-nx // tx) + 7) // 8 * 8
-        if wt < 64 and tx > -(-nx // 496):
+        if wt < 64 and tx > tx0:
             break
         tiles = -(-nx // wt) * -(-ny // 64)
-        c = -(-tiles // ncu) * (max(300, wt + 16) + wt)
+        c = -(-tiles // ncu) * (ta + tb * wt)
         if cost is None or c < cost:
             best, cost = wt, c
         tx += 1
-    return best
+    return best, cost
+
+
+def balanced(nx, ny, ncu):
+    """(nodes per lane, width) the plan picks: the cheaper of the two variants"""
+    w8, c8 = plan(nx, ny, ncu, 496, 16000, 30)
+    w4, c4 = plan(nx, ny, ncu, 240, 12000, 15)
+    return (4, w4) if c4 < c8 else (8, w8)
 
 
 @pytest.mark.parametrize("nx,ny", [(480, 64), (488, 65), (1000, 700), (960, 130), (64, 64), (2048, 300),
@@ -180,11 +188,10 @@ def test_tile_width_plan(adw):
     """The plan balances the tiles over the device's compute units; the width can
     be forced and set back to automatic; bad widths are rejected."""
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    for n in (8192, 4096, 2048, 1024):
+    for n in (8192, 6144, 4096, 2048, 1024):
         w = adw.Wave(n, n, 1.0 / (n + 1), 0.5 / (n + 1), c=1.0, dtype=torch.float32)
         i = w.info()
-        assert i["fused_tile_cols"] == balanced_width(n, n, ncu), (n, i)
-        assert i["fused_lane_nodes"] == (4 if balanced_width(n, n, ncu) <= 128 else 8)
+        assert (i["fused_lane_nodes"], i["fused_tile_cols"]) == balanced(n, n, ncu), (n, i)
         assert i["fused_tiles"] == -(-n // i["fused_tile_cols"]) * -(-n // 64)
         w.set_tuning(fused_lane_nodes=8, fused_tile_cols=488)
         assert w.info()["fused_tile_cols"] == 488 and w.info()["fused_lane_nodes"] == 8
