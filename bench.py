@@ -97,10 +97,31 @@ def cpu_baseline(prob, steps: int):
     t0 = time.perf_counter()
     oracle.run(kappa, up, uc, prob.h, prob.dt, steps, src_idx=si, src_amp=amp)
     t = time.perf_counter() - t0
+    # one host thread, on a 2048 x 2048 corner of the same fields (one step)
+    n1 = min(2048, prob.nx, prob.ny)
+    k1 = np.ascontiguousarray(np.broadcast_to(kappa, (prob.ny, prob.nx))[:n1, :n1]) \
+        if np.ndim(kappa) else kappa
+    t1 = time.perf_counter()
+    oracle.run(k1, np.ascontiguousarray(up[:n1, :n1]), np.ascontiguousarray(uc[:n1, :n1]), prob.h, prob.dt, 1,
+               threads=1)
+    t1 = time.perf_counter() - t1
     return {"value": prob.nx * prob.ny * steps / t / 1e6, "unit": "Mpts/s",
             "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"{steps} ADI steps of the same {prob.nx}x{prob.ny} workload, FP64, "
-                      f"{t:.1f} s wall"}
+                      f"{t:.1f} s wall",
+            "one_thread": {"value": round(n1 * n1 / t1 / 1e6, 2), "unit": "Mpts/s",
+                           "sample": f"1 step of a {n1}x{n1} corner of the same fields, FP64, {t1:.1f} s"},
+            "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_batched(adw, torch, steps: int, warmup: int, plain_value: float):
