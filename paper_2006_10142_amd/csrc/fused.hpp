@@ -69,40 +69,6 @@ struct FShared {
     int src_n;             // -1: more than kFuSrc in this tile
 };
 
-// Wavefront scans of affine maps with each DPP lane move folded into the
-// composing multiply-add / multiply: a lane whose source lane does not exist (or
-// lies in a row outside the mask) is left as it is, which is composition with the
-// identity map, so the results are those of wave_scan_fwd / row_scan_bwd bit for
-// bit (the same fused roundings) in a third of the instructions.  A DPP read of a
-// register written by the previous VALU instruction needs two wait states: the
-// s_nop before, between and after the steps provide them.
-#define ADW_FU_STEP(CTRL, MASK) \
-    "v_fmac_f32_dpp %0, %0, %1 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t" \
-    "v_mul_f32_dpp %1, %1, %1 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t" \
-    "s_nop 0\n\t"
-
-// inclusive prefix (lanes 0..l) over the wavefront
-__device__ __forceinline__ void fu_scan_fwd(float& a, float& b)
-{
-    asm volatile("s_nop 1\n\t"
-                 ADW_FU_STEP("row_shr:1", "0xf") ADW_FU_STEP("row_shr:2", "0xf")
-                 ADW_FU_STEP("row_shr:4", "0xf") ADW_FU_STEP("row_shr:8", "0xf")
-                 ADW_FU_STEP("row_bcast:15", "0xa") ADW_FU_STEP("row_bcast:31", "0xc")
-                 "s_nop 1"
-                 : "+v"(a), "+v"(b));
-}
-
-// inclusive suffix over each row of 16 lanes (lanes l..16k+15)
-__device__ __forceinline__ void fu_row_scan_bwd(float& a, float& b)
-{
-    asm volatile("s_nop 1\n\t"
-                 ADW_FU_STEP("row_shl:1", "0xf") ADW_FU_STEP("row_shl:2", "0xf")
-                 ADW_FU_STEP("row_shl:4", "0xf") ADW_FU_STEP("row_shl:8", "0xf")
-                 "s_nop 1"
-                 : "+v"(a), "+v"(b));
-}
-#undef ADW_FU_STEP
-
 // inclusive suffix (lanes l..63) of two-component affine maps over the wavefront
 __device__ __forceinline__ void wave_scan_bwd2(float& a, float& b, int lane)
 {

@@ -123,6 +123,57 @@ __device__ __forceinline__ void compose3_dpp(T& a0, T& a1, T& b)
     b = b * b2;
 }
 
+// Wavefront scans of affine maps with each DPP lane move folded into the
+// composing multiply-add / multiply: a lane whose source lane does not exist (or
+// lies in a row outside the mask) is left as it is, which is composition with the
+// identity map, so the results are those of wave_scan_fwd / row_scan_bwd bit for
+// bit (the same fused roundings) in a third of the instructions.  A DPP read of a
+// register written by the previous VALU instruction needs two wait states: the
+// s_nop before, between and after the steps provide them.
+#define ADW_FU_STEP(CTRL, MASK) \
+    "v_fmac_f32_dpp %0, %0, %1 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t" \
+    "v_mul_f32_dpp %1, %1, %1 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t" \
+    "s_nop 0\n\t"
+
+// inclusive prefix (lanes 0..l) over the wavefront
+__device__ __forceinline__ void fu_scan_fwd(float& a, float& b)
+{
+    asm volatile("s_nop 1\n\t"
+                 ADW_FU_STEP("row_shr:1", "0xf") ADW_FU_STEP("row_shr:2", "0xf")
+                 ADW_FU_STEP("row_shr:4", "0xf") ADW_FU_STEP("row_shr:8", "0xf")
+                 ADW_FU_STEP("row_bcast:15", "0xa") ADW_FU_STEP("row_bcast:31", "0xc")
+                 "s_nop 1"
+                 : "+v"(a), "+v"(b));
+}
+
+// inclusive suffix over each row of 16 lanes (lanes l..16k+15)
+__device__ __forceinline__ void fu_row_scan_bwd(float& a, float& b)
+{
+    asm volatile("s_nop 1\n\t"
+                 ADW_FU_STEP("row_shl:1", "0xf") ADW_FU_STEP("row_shl:2", "0xf")
+                 ADW_FU_STEP("row_shl:4", "0xf") ADW_FU_STEP("row_shl:8", "0xf")
+                 "s_nop 1"
+                 : "+v"(a), "+v"(b));
+}
+#define ADW_FU_STEP3(CTRL) \
+    "v_fmac_f32_dpp %0, %0, %2 " CTRL " row_mask:0xf bank_mask:0xf\n\t" \
+    "v_fmac_f32_dpp %1, %1, %2 " CTRL " row_mask:0xf bank_mask:0xf\n\t" \
+    "v_mul_f32_dpp %2, %2, %2 " CTRL " row_mask:0xf bank_mask:0xf\n\t"
+
+// inclusive suffix over each row of 16 lanes of three-component maps (a0 + a1 C, b):
+// between a register's write and its next DPP read stand the two other
+// components' instructions, the two wait states needed
+__device__ __forceinline__ void fu_row_scan_bwd3(float& a0, float& a1, float& b)
+{
+    asm volatile("s_nop 1\n\t"
+                 ADW_FU_STEP3("row_shl:1") ADW_FU_STEP3("row_shl:2")
+                 ADW_FU_STEP3("row_shl:4") ADW_FU_STEP3("row_shl:8")
+                 "s_nop 1"
+                 : "+v"(a0), "+v"(a1), "+v"(b));
+}
+#undef ADW_FU_STEP3
+#undef ADW_FU_STEP
+
 // prefix over each row of 16 lanes (lanes 16k..l)
 template <typename T>
 __device__ __forceinline__ void row_scan_fwd(T& a, T& b)
@@ -146,19 +197,27 @@ __device__ __forceinline__ void row_scan_bwd(T& a, T& b)
 template <typename T>
 __device__ __forceinline__ void wave_scan_fwd(T& a, T& b)
 {
-    row_scan_fwd(a, b);
-    compose_dpp<kRowBcast15, 0xa>(a, b);
-    compose_dpp<kRowBcast31, 0xc>(a, b);
+    if constexpr (sizeof(T) == 4) {
+        fu_scan_fwd(a, b);
+    } else {
+        row_scan_fwd(a, b);
+        compose_dpp<kRowBcast15, 0xa>(a, b);
+        compose_dpp<kRowBcast31, 0xc>(a, b);
+    }
 }
 
 // inclusive suffix (lanes l..63) of three-component maps (a0 + a1 C, b)
 template <typename T>
 __device__ __forceinline__ void wave_scan_bwd3(T& a0, T& a1, T& b, int lane)
 {
-    compose3_dpp<kRowShl + 1, 0xf>(a0, a1, b);
-    compose3_dpp<kRowShl + 2, 0xf>(a0, a1, b);
-    compose3_dpp<kRowShl + 4, 0xf>(a0, a1, b);
-    compose3_dpp<kRowShl + 8, 0xf>(a0, a1, b);
+    if constexpr (sizeof(T) == 4) {
+        fu_row_scan_bwd3(a0, a1, b);
+    } else {
+        compose3_dpp<kRowShl + 1, 0xf>(a0, a1, b);
+        compose3_dpp<kRowShl + 2, 0xf>(a0, a1, b);
+        compose3_dpp<kRowShl + 4, 0xf>(a0, a1, b);
+        compose3_dpp<kRowShl + 8, 0xf>(a0, a1, b);
+    }
     const T p16 = readlane(a0, 16), q16 = readlane(a1, 16), b16 = readlane(b, 16);
     const T p32 = readlane(a0, 32), q32 = readlane(a1, 32), b32 = readlane(b, 32);
     const T p48 = readlane(a0, 48), q48 = readlane(a1, 48), b48 = readlane(b, 48);
