@@ -252,6 +252,9 @@ typedef struct {
                                  2 (set only): exact two-pass step, 0 (set): keep */
     int fused_allowed;        /* read-only: the one-pass step is allowed for the batch */
     int fused_items;          /* read-only: one-pass tiles over all simulations */
+    int fused_lane_nodes;     /* one-pass x-line nodes per lane: 8 (default) or 4 (narrower
+                                 tiles with r kept in LDS), 0 (set) = keep; the autotuner
+                                 times both */
 } adi_batch_plan;
 adi_status adi_batch_get_plan(adi_batch_t b, adi_batch_plan* p);
 adi_status adi_batch_set_plan(adi_batch_t b, const adi_batch_plan* p);

@@ -245,6 +245,7 @@ struct adi_wave_s {
     int f_wt_user = 0;   // tile width set through adi_wave_set_tuning (0: chosen here)
     int f_lane = 8;      // nodes per lane of the one-pass x-lines (8: fused.hpp, 4: fused4.hpp)
     int f_lane_user = 0; // nodes per lane set through adi_wave_set_tuning (0: chosen here)
+    int f4_wt = 0, f4_tx = 0, f4_tiles = 0;   // widest four-node tiles (used by the batched step)
     // cyclic-reduction baseline (line_solver = 2): coefficient arrays a, b, c
     int cr = 0;
     void* cr_abc = nullptr;   // 3 * nx * ny values
@@ -489,6 +490,12 @@ void fused_plan(adi_wave_s* w)
     const int wmax = w->f_lane == 4 ? kF4Wmax : kFuWmax;
     w->f_wt = w->f_wt_user > 0 ? std::min(w->f_wt_user, wmax) : (w->f_lane == 4 ? w4 : w8);
     w->f_tx = (w->nx + w->f_wt - 1) / w->f_wt;
+    {
+        long long c = 0;
+        w->f4_wt = fused_width(w->nx, w->ny, 0, kF4Wmax, kFuT4a, kFuT4b, &c);
+        w->f4_tx = (w->nx + w->f4_wt - 1) / w->f4_wt;
+        w->f4_tiles = w->f4_tx * ((w->ny + kFuHt - 1) / kFuHt);
+    }
     w->f_tiles = w->f_tx * ((w->ny + kFuHt - 1) / kFuHt);
     w->f_grid = (w->f_tiles + 7) / 8 * 8;
 }

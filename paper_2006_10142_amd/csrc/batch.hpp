@@ -17,6 +17,7 @@ template <typename T>
 struct SimDesc {
     int nx, ny, nseg, K, nxp, vec;
     int f_wt, f_tx, f_tiles;   // one-pass tiles (see fused.hpp)
+    int f4_wt, f4_tx, f4_tiles;   // one-pass tiles with four nodes per lane (fused4.hpp)
     T* r;
     T* w;
     T* qin;
@@ -65,6 +66,28 @@ __global__ void __launch_bounds__(1024) k_fused_batch(FBatchArgs B)
     A.tiles_x = __builtin_amdgcn_readfirstlane(S.f_tx);
     A.tiles = __builtin_amdgcn_readfirstlane(S.f_tiles);
     fused_tile(A, __builtin_amdgcn_readfirstlane(wi.y), sh);
+}
+
+// the same with four nodes per lane (each simulation's fused4.hpp tiles)
+__global__ void __launch_bounds__(1024) k_fused4_batch(FBatchArgs B)
+{
+    __shared__ FShared4 sh;
+    const int it = xcd_band(blockIdx.x);
+    if (it >= B.nitems) return;
+    const int2 wi = B.items[it];
+    const SimDesc<float>& S = B.sims[wi.x];
+    FArgs A{};
+    A.uc = S.lev[B.u_slot];
+    A.up = S.lev[B.out_slot];
+    A.r = S.r;
+    A.qin = S.qin;
+    A.nx = __builtin_amdgcn_readfirstlane(S.nx);
+    A.ny = __builtin_amdgcn_readfirstlane(S.ny);
+    A.nseg = __builtin_amdgcn_readfirstlane(S.nseg);
+    A.wt = __builtin_amdgcn_readfirstlane(S.f4_wt);
+    A.tiles_x = __builtin_amdgcn_readfirstlane(S.f4_tx);
+    A.tiles = __builtin_amdgcn_readfirstlane(S.f4_tiles);
+    fused4_tile(A, __builtin_amdgcn_readfirstlane(wi.y), sh);
 }
 
 template <typename T, int TR>
@@ -183,8 +206,9 @@ struct adi_batch_s {
     long long nodes = 0;
     // one-pass step: allowed when every simulation allows it (FP32, bound holds)
     int fused_ok = 0, fused = 0;
-    int2* fitems = nullptr;         // (simulation, tile)
-    int nf_items = 0;
+    int flane = 8;                  // nodes per lane of the one-pass tiles (8 or 4)
+    int2* fitems = nullptr;         // (simulation, tile) of the eight-node tiles, then the four-node ones
+    int nf_items = 0, nf4_items = 0;
 };
 
 namespace {
@@ -214,6 +238,7 @@ void fill_desc(adi_batch_s* b)
         const adi_wave_s& w = b->sims[s];
         d[s].nx = w.nx; d[s].ny = w.ny; d[s].nseg = w.nseg; d[s].K = w.K; d[s].nxp = w.nxp;
         d[s].f_wt = w.f_wt; d[s].f_tx = w.f_tx; d[s].f_tiles = w.f_tiles;
+        d[s].f4_wt = w.f4_wt; d[s].f4_tx = w.f4_tx; d[s].f4_tiles = w.f4_tiles;
         d[s].vec = ((size_t)w.nx * sizeof(T)) % 16 == 0;
         d[s].r = (T*)w.r; d[s].w = (T*)w.w; d[s].qin = (T*)w.qin; d[s].sum = (T*)w.sum; d[s].X = (T*)w.X;
         d[s].lev[0] = b->bound ? (T*)b->lev0[s] : nullptr;
@@ -303,6 +328,12 @@ adi_status queue_batch_solve(adi_batch_s* b, int u_slot, int v_slot, int out_slo
 adi_status batch_step_once(adi_batch_s* b, hipStream_t st, int parity)
 {
     const int p = parity;
+    if (b->fused && b->flane == 4) {
+        FBatchArgs a{static_cast<const SimDesc<float>*>(b->desc), b->fitems + b->nf_items, b->nf4_items, p ^ 1, p};
+        hipLaunchKernelGGL(k_fused4_batch, dim3((b->nf4_items + 7) / 8 * 8), dim3(1024), 0, st, a);
+        ADI_LAUNCHED("fused_batch");
+        return ADI_OK;
+    }
     if (b->fused) {
         FBatchArgs a{static_cast<const SimDesc<float>*>(b->desc), b->fitems, b->nf_items, p ^ 1, p};
         hipLaunchKernelGGL(k_fused_batch, dim3((b->nf_items + 7) / 8 * 8), dim3(1024), 0, st, a);
@@ -479,8 +510,11 @@ adi_status adi_batch_create(adi_batch_t* out, int count, const int* nx, const in
             if (!b->sims[s].fused_ok) b->fused_ok = 0;
             for (int tl = 0; tl < b->sims[s].f_tiles; ++tl) fi.push_back(make_int2(s, tl));
         }
+        b->nf_items = (int)fi.size();
+        for (int s = 0; s < count && b->fused_ok; ++s)
+            for (int tl = 0; tl < b->sims[s].f4_tiles; ++tl) fi.push_back(make_int2(s, tl));
+        b->nf4_items = (int)fi.size() - b->nf_items;
         if (b->fused_ok) {
-            b->nf_items = (int)fi.size();
             if (hipMalloc(&b->fitems, fi.size() * sizeof(int2)) != hipSuccess) {
                 (void)hipGetLastError();
                 b->fitems = nullptr;
@@ -595,7 +629,8 @@ adi_status adi_batch_get_plan(adi_batch_t b, adi_batch_plan* p)
     p->ysolve_items = b->nyv_items;
     p->fused_step = b->fused;
     p->fused_allowed = b->fused_ok;
-    p->fused_items = b->nf_items;
+    p->fused_items = b->flane == 4 ? b->nf4_items : b->nf_items;
+    p->fused_lane_nodes = b->flane;
     return ADI_OK;
 }
 
@@ -612,7 +647,10 @@ adi_status adi_batch_set_plan(adi_batch_t b, const adi_batch_plan* p)
     if (p->fused_step < 0 || p->fused_step > 2) return fail(ADI_EINVAL, "fused_step must be 0, 1 or 2");
     if (p->fused_step == 1 && !b->fused_ok)
         return fail(ADI_EUNSUPPORTED, "the one-pass step is not allowed for every simulation of the batch");
+    if (p->fused_lane_nodes != 0 && p->fused_lane_nodes != 4 && p->fused_lane_nodes != 8)
+        return fail(ADI_EINVAL, "fused_lane_nodes must be 0, 4 or 8");
     if (p->fused_step > 0) b->fused = p->fused_step == 1 ? 1 : 0;
+    if (p->fused_lane_nodes) b->flane = p->fused_lane_nodes;
     b->x_tr = tr;
     b->x_grid = p->x_grid;
     b->ys_grid = p->yscan_grid;
@@ -670,8 +708,15 @@ adi_status adi_batch_autotune(adi_batch_t b, int trial_steps, double* best_ms)
     int btr = b->x_tr, bxg = b->x_grid, bsg = b->ys_grid, bvg = b->yv_grid;
     static const int grids[] = {0, 256, 512, 1024, 2048, 4096};
     if (st == ADI_OK && b->fused) {
-        double ms = 0;
-        if ((st = trial(ms)) == ADI_OK) best = ms;
+        // the one-pass step: the faster of its two tile kinds
+        int blane = b->flane;
+        for (int lane : {8, 4}) {
+            b->flane = lane;
+            double ms = 0;
+            if ((st = trial(ms)) != ADI_OK) break;
+            if (ms < best) { best = ms; blane = lane; }
+        }
+        b->flane = blane;
     } else if (st == ADI_OK) {
         for (int tr : {128, 256, 1024}) {
             if (8LL * tr < b->max_nx || !batch_fits(tr, b->dtype)) continue;

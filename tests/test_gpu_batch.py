@@ -93,20 +93,23 @@ def test_batch_matches_oracle(adw, oracle_lib, dtype):
 SIZES4 = [(64, 64), (100, 37), (4, 9), (8, 1), (256, 256), (300, 211), (1000, 50), (36, 517)]
 
 
-def test_batch_one_pass_matches_oracle(adw, oracle_lib):
+@pytest.mark.parametrize("lane", [8, 4])
+def test_batch_one_pass_matches_oracle(adw, oracle_lib, lane):
     sims = make_batch("f32", sizes=SIZES4, seed=5)
-    say("batch one-pass f32, 25 steps")
-    got, info = run_batch(adw, sims, "f32", 25)
+    say(f"batch one-pass f32, {lane} nodes per lane, 25 steps")
+    got, info = run_batch(adw, sims, "f32", 25, plan=dict(fused_lane_nodes=lane))
     assert info["fused_allowed"] == 1 and info["fused_step"] == 1 and info["fused_items"] > len(sims)
+    assert info["fused_lane_nodes"] == lane
     for s, g in zip(sims, got):
         assert rel_l2(g, oracle_run(oracle_lib, s, 25)) <= TOL["f32"], (s["nx"], s["ny"])
 
 
-def test_batch_one_pass_graph_and_exact_step(adw):
+@pytest.mark.parametrize("lane", [8, 4])
+def test_batch_one_pass_graph_and_exact_step(adw, lane):
     sims = make_batch("f32", sizes=SIZES4, seed=6)
-    say("batch one-pass graph / exact")
-    eager, _ = run_batch(adw, sims, "f32", 11)
-    graph, info = run_batch(adw, sims, "f32", 11, graph=True)
+    say(f"batch one-pass graph / exact, {lane} nodes per lane")
+    eager, _ = run_batch(adw, sims, "f32", 11, plan=dict(fused_lane_nodes=lane))
+    graph, info = run_batch(adw, sims, "f32", 11, graph=True, plan=dict(fused_lane_nodes=lane))
     assert info["graph"] == 1
     exact, info2 = run_batch(adw, sims, "f32", 11, plan=dict(fused_step=False))
     assert info2["fused_step"] == 0
