@@ -94,8 +94,9 @@ def cpu_baseline(prob, steps: int):
         uc = up.copy()
     amp = None if prob.src_amp is None else np.asarray(prob.src_amp)[:steps]
     si = prob.src_idx if prob.src_idx.size else None
+    cores = oracle.max_threads()
     t0 = time.perf_counter()
-    oracle.run(kappa, up, uc, prob.h, prob.dt, steps, src_idx=si, src_amp=amp)
+    oracle.run(kappa, up, uc, prob.h, prob.dt, steps, src_idx=si, src_amp=amp, threads=cores)
     t = time.perf_counter() - t0
     # one host thread, on a 2048 x 2048 corner of the same fields (one step)
     n1 = min(2048, prob.nx, prob.ny)
@@ -106,7 +107,7 @@ def cpu_baseline(prob, steps: int):
                threads=1)
     t1 = time.perf_counter() - t1
     return {"value": prob.nx * prob.ny * steps / t / 1e6, "unit": "Mpts/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{steps} ADI steps of the same {prob.nx}x{prob.ny} workload, FP64, "
                       f"{t:.1f} s wall",
             "one_thread": {"value": round(n1 * n1 / t1 / 1e6, 2), "unit": "Mpts/s",
