@@ -34,6 +34,15 @@ struct AdjArgs {
     T* grad;         // dJ/dkappa, accumulated
     int nx, ny;
     T c1, c2;        // dt^2 / h^2, beta / h^2
+    // point terms of the step (see k_adjoint_points), folded into the same launch:
+    const int* rmap;     // per node: first receiver of the node (>= nrec: none)
+    const int* rnext;    // per receiver: next receiver of the same node, or -1
+    const T* rvals;      // this step's receiver values (NULL: none)
+    const int* sidx;     // source nodes (NULL: no source gradient)
+    T* gout;             // dJ/d(source value) of this step
+    int nsrc, nrec;
+    T tau2;
+    long long npts;
 };
 
 template <typename T>
@@ -41,6 +50,13 @@ __global__ void __launch_bounds__(256) k_adjoint_update(AdjArgs<T> A)
 {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (A.sidx && blockIdx.x == 0 && blockIdx.y == 0) {
+        // dJ/d(source value) = tau^2 t / r at the source node (every thread of the block)
+        for (int s = threadIdx.x; s < A.nsrc; s += 256) {
+            const int id = A.sidx[s];
+            A.gout[s] = (id >= 0 && id < A.npts) ? A.tau2 * A.t[id] / A.r[id] : T(0);
+        }
+    }
     if (i >= A.nx || j >= A.ny) return;
     const int nx = A.nx, ny = A.ny;
     const size_t p = (size_t)j * nx + i;
@@ -60,7 +76,31 @@ __global__ void __launch_bounds__(256) k_adjoint_update(AdjArgs<T> A)
     const T mu = tc / rp;
     const T nu = A.z[p] / rp;
     A.grad[p] += mu * (A.c1 * s5u + A.c2 * sxw) + nu * (A.c2 * syd);
-    A.lam2[p] = (T(2) * A.lam1[p] - A.lam2[p]) + T(2) * s5t;
+    T lam = (T(2) * A.lam1[p] - A.lam2[p]) + T(2) * s5t;
+    if (A.rvals) {
+        // the receivers of this node, in increasing index (the order of k_adjoint_points)
+        const int j0 = A.rmap[p];
+        for (int j = j0 < A.nrec ? j0 : -1; j >= 0; j = A.rnext[j]) lam += A.rvals[j];
+    }
+    A.lam2[p] = lam;
+}
+
+// receiver map of the reverse pass: rmap[node] = smallest receiver index at the
+// node (rmap filled beforehand with a value above every index, so that a node
+// without receivers keeps it), rnext[k] = next receiver at the same node or -1
+__global__ void __launch_bounds__(256) k_receiver_map(const int* __restrict__ ridx, int nrec, long long npts,
+                                                      int* rmap, int* rnext)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= nrec) return;
+    const int id = ridx[k];
+    int nxt = -1;
+    if (id >= 0 && id < npts) {
+        atomicMin(&rmap[id], k);
+        for (int j = k + 1; j < nrec; ++j)
+            if (ridx[j] == id) { nxt = j; break; }
+    }
+    rnext[k] = nxt;
 }
 
 // Point terms of one reverse step, one thread per receiver / source index k:
@@ -115,7 +155,8 @@ struct adi_adjoint_s {
     void* ck = nullptr;          // 2 * ncheck fields: (u^{k0-1}, u^{k0}) of every segment
     void* seg = nullptr;         // 2 * K fields: levels u^{k0+1..k0+K}, then w^{k0..k0+K-1}
     void* work = nullptr;        // 6 fields: forward levels (2), lambda (2), t, z
-    size_t ck_cap = 0, seg_cap = 0, work_cap = 0;
+    void* rmap = nullptr;        // nx*ny ints + receiver count ints: receiver map of the reverse pass
+    size_t ck_cap = 0, seg_cap = 0, work_cap = 0, rmap_cap = 0;
 };
 
 namespace {
@@ -126,6 +167,7 @@ void adjoint_free(adi_adjoint_s* a)
     if (a->ck) (void)hipFree(a->ck);
     if (a->seg) (void)hipFree(a->seg);
     if (a->work) (void)hipFree(a->work);
+    if (a->rmap) (void)hipFree(a->rmap);
     delete a;
 }
 
@@ -262,7 +304,25 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     }
     const int nsrc = (grad_amp && f) ? f->count : 0;
     const double beta = 0.5 * w->dt * w->dt;
+    int* rmap = nullptr;
+    int* rnext = nullptr;
+    if (nrec > 0) {
+        if (adi_status s = grow(&a->rmap, &a->rmap_cap, ((size_t)npts + nrec) * sizeof(int))) return s;
+        rmap = static_cast<int*>(a->rmap);
+        rnext = rmap + npts;
+        ADI_HIP(hipMemsetAsync(rmap, 0x7f, (size_t)npts * sizeof(int), w->stream));   // 0x7f7f7f7f: no receiver
+        hipLaunchKernelGGL(k_receiver_map, dim3((nrec + 255) / 256), dim3(256), 0, w->stream, rec->idx, nrec, npts,
+                           rmap, rnext);
+        ADI_LAUNCHED("receiver_map");
+    }
     AdjArgs<T> ua{};
+    ua.rmap = rmap;
+    ua.rnext = rnext;
+    ua.sidx = nsrc > 0 ? f->idx : nullptr;
+    ua.nsrc = nsrc;
+    ua.nrec = nrec;
+    ua.tau2 = (T)(w->dt * w->dt);
+    ua.npts = npts;
     ua.r = static_cast<const T*>(w->r);
     ua.grad = static_cast<T*>(grad_kappa);
     ua.nx = w->nx;
@@ -297,18 +357,10 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
             ua.uk = static_cast<const T*>(lev(m + 1));
             ua.up = static_cast<const T*>(lev(m + 2));
             ua.wk = static_cast<const T*>(wst(m));
+            ua.rvals = (k >= 2 && nrec > 0) ? gt + (size_t)(k - 2) * nrec : nullptr;
+            ua.gout = nsrc > 0 ? static_cast<T*>(grad_amp) + (size_t)(k - 1) * nsrc : nullptr;
             hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
             ADI_LAUNCHED("adjoint_update");
-            const int nr = k >= 2 ? nrec : 0;
-            if (nr > 0 || nsrc > 0) {
-                hipLaunchKernelGGL((k_adjoint_points<T>), dim3((std::max(nr, nsrc) + 255) / 256), dim3(256), 0,
-                                   w->stream, nr > 0 ? lam2 : nullptr, nr > 0 ? rec->idx : nullptr,
-                                   nr > 0 ? gt + (size_t)(k - 2) * nrec : nullptr, nr, tt,
-                                   static_cast<const T*>(w->r), nsrc > 0 ? f->idx : nullptr,
-                                   nsrc > 0 ? static_cast<T*>(grad_amp) + (size_t)(k - 1) * nsrc : nullptr, nsrc,
-                                   (T)(w->dt * w->dt), npts);
-                ADI_LAUNCHED("adjoint_points");
-            }
             std::swap(lam1, lam2);
         }
     }

@@ -99,6 +99,19 @@ def test_adjoint_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
     assert rel_l2(ga, ra) <= tol
 
 
+@pytest.mark.parametrize("nx,ny", [(30, 50), (7, 90), (130, 9)])
+def test_adjoint_narrow_grids(adw, oracle_lib, nx, ny):
+    """Grids narrower than one 64-wide block of the reverse kernels (and wide, short
+    ones): gradients of kappa and of the source values against the oracle (FP64)."""
+    c = case("f64", nx=nx, ny=ny, nsteps=24, seed=nx + ny)
+    say(f"adjoint narrow {nx}x{ny}")
+    gk, ga, tr = gpu_grad(adw, c, 5)
+    rk, ra, rtr = oracle_grad(oracle_lib, c)
+    assert np.abs(ra).max() > 0
+    assert rel_l2(gk, rk) <= 1e-10
+    assert rel_l2(ga, ra) <= 1e-10
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_shared_receiver_nodes(adw, oracle_lib, dtype):
     """300 receivers (more than one 256-wide tile) with repeated nodes, one of them on a
