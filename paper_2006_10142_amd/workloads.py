@@ -3,7 +3,7 @@
 This module only *draws* inputs: coefficient fields, initial states, source
 time series and receiver positions.  It holds none of the scheme's arithmetic
 (no stencil, no line solve, no time stepping), so the HIP library and the FP64
-CPU checker can both consume exactly the same arrays.
+CPU oracle can both consume exactly the same arrays.
 
 Conventions (the paper's grid, Sec. 2 eq. (f6), with N interior points per axis):
   * interior cell (i, j), 0-based, sits at x = (i+1) h, y = (j+1) h with
@@ -15,7 +15,7 @@ Conventions (the paper's grid, Sec. 2 eq. (f6), with N interior points per axis)
     f = s(t)/h**2 at that cell (a discrete delta), evaluated at t_n = n*dt,
     the level whose right-hand side it enters (eq. (CN1) uses f^k).
 
-Inputs for an FP32 run are rounded to FP32 once, here; the checker receives
+Inputs for an FP32 run are rounded to FP32 once, here; the oracle receives
 those same values promoted to FP64, so a parity error measures solver error
 only.
 """
