@@ -265,8 +265,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
-              "build (see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; runs on several GPUs are not supported "
+              "(--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
