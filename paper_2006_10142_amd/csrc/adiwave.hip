@@ -252,6 +252,11 @@ struct adi_wave_s {
     // time-dependent coefficient steps: r at the previous level, right-hand side
     void* r_prev = nullptr;
     void* rho_buf = nullptr;
+    // receivers of the previous step, recorded by the next step's first launch
+    // (set by do_step around one queued step, empty otherwise)
+    int tap_n = 0;
+    const int* tap_idx = nullptr;
+    void* tap_out = nullptr;
 };
 
 namespace {
@@ -355,6 +360,9 @@ XArgs<T> make_x(const adi_wave_s* w, const void* u, const adi_source* f, int k, 
         a.src_idx = f->idx;
         a.src_amp = static_cast<const T*>(f->amp) + (size_t)k * f->count;
     }
+    a.nrec = w->tap_n;
+    a.rec_idx = w->tap_idx;
+    a.rec_out = static_cast<T*>(w->tap_out);
     return a;
 }
 
@@ -557,6 +565,9 @@ adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const ad
         a.src_idx = f->idx;
         a.src_amp = static_cast<const float*>(f->amp) + (size_t)k * f->count;
     }
+    a.nrec = w->tap_n;
+    a.rec_idx = w->tap_idx;
+    a.rec_out = static_cast<float*>(w->tap_out);
     if (w->f_lane == 4)
         hipLaunchKernelGGL(k_fused4, dim3(w->f_grid), dim3(1024), 0, w->stream, a);
     else
@@ -639,20 +650,34 @@ adi_status do_step(adi_wave_s* w, void** u_prev, void** u_curr, const adi_source
 {
     const bool cr = allow_fused && w->cr;
     const bool fused = !cr && sizeof(T) == 4 && allow_fused && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
+    const bool recs = rec && rec->count > 0;
+    auto record = [&](int k, const void* level) -> adi_status {
+        hipLaunchKernelGGL((k_record<T>), dim3((rec->count + 255) / 256), dim3(256), 0, w->stream,
+                           static_cast<const T*>(level), rec->idx,
+                           static_cast<T*>(rec->traces) + (size_t)k * rec->count, rec->count,
+                           (long long)w->nx * w->ny);
+        ADI_LAUNCHED("record");
+        return ADI_OK;
+    };
     for (int k = 0; k < nsteps; ++k) {
+        // the x-sweep and one-pass launches record the previous step's receivers
+        if (recs && !cr && k > 0) {
+            w->tap_n = rec->count;
+            w->tap_idx = rec->idx;
+            w->tap_out = static_cast<T*>(rec->traces) + (size_t)(k - 1) * rec->count;
+        }
         adi_status s = cr      ? queue_cr_step<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1))
                        : fused ? queue_fused(w, *u_curr, *u_prev, f, k)
                                : queue_solve<T>(w, *u_curr, *u_prev, *u_prev, T(2), T(-1), f, k, T(1), nullptr);
+        w->tap_n = 0;
+        w->tap_idx = nullptr;
+        w->tap_out = nullptr;
         if (s != ADI_OK) return s;
-        if (rec && rec->count > 0) {
-            hipLaunchKernelGGL((k_record<T>), dim3((rec->count + 255) / 256), dim3(256), 0, w->stream,
-                               static_cast<const T*>(*u_prev), rec->idx,
-                               static_cast<T*>(rec->traces) + (size_t)k * rec->count, rec->count,
-                               (long long)w->nx * w->ny);
-            ADI_LAUNCHED("record");
-        }
+        if (recs && cr)
+            if (adi_status s2 = record(k, *u_prev)) return s2;
         std::swap(*u_prev, *u_curr);
     }
+    if (recs && !cr && nsteps > 0) return record(nsteps - 1, *u_curr);
     return ADI_OK;
 }
 

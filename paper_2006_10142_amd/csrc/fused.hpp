@@ -60,6 +60,9 @@ struct FArgs {
     int nsrc;
     const int* src_idx;
     const float* src_amp;
+    int nrec;            // receivers of the previous step, sampled from uc (see rec_tap)
+    const int* rec_idx;
+    float* rec_out;
 };
 
 struct FShared {
@@ -347,6 +350,7 @@ __device__ __forceinline__ void fused_tile(const FArgs& A, const int tile, FShar
 __global__ void __launch_bounds__(1024) k_fused(FArgs A)
 {
     __shared__ FShared sh;
+    rec_tap<float>(A.uc, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
     const int tile = A.xcd_map ? xcd_band(blockIdx.x) : (int)blockIdx.x;
     if (tile >= A.tiles) return;
     fused_tile(A, tile, sh);

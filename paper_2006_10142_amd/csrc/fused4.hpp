@@ -279,6 +279,7 @@ __device__ __forceinline__ void fused4_tile(const FArgs& A, const int tile, FSha
 __global__ void __launch_bounds__(1024) k_fused4(FArgs A)
 {
     __shared__ FShared4 sh;
+    rec_tap<float>(A.uc, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
     const int tile = A.xcd_map ? xcd_band(blockIdx.x) : (int)blockIdx.x;
     if (tile >= A.tiles) return;
     fused4_tile(A, tile, sh);

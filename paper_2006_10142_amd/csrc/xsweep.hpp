@@ -249,6 +249,10 @@ struct XArgs {
     // fused y-chunk elimination: a strip is a whole number of y-chunks of M rows
     T* sum;              // summary planes (blocked by 16 columns, see kernels.hpp)
     int K, M, nxp;
+    // receivers of the previous step, sampled from u (see rec_tap)
+    int nrec;
+    const int* rec_idx;
+    T* rec_out;
 };
 
 constexpr int kSeg = 8;   // nodes per x-line segment (one segment per thread)
@@ -705,9 +709,24 @@ __device__ __forceinline__ void xsweep_strip(const XArgs<T>& A, const int strip,
     else xsweep_strip_impl<T, TR, FUSE, STENCIL, false>(A, strip, t, sh);
 }
 
+// Receiver values of the level a step launch reads: that level is the previous
+// step's result and stays unchanged during this step, so the first workgroup of
+// the step's first launch records it (out[k] = u[idx[k]]; an offset outside
+// [0, npts) records NaN), and the previous step needs no launch of its own.
+template <typename T>
+__device__ __forceinline__ void rec_tap(const T* u, const int* idx, T* out, int n, long long npts)
+{
+    if (n > 0 && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int id = idx[k];
+            out[k] = (id >= 0 && id < npts) ? u[id] : T(NAN);
+        }
+}
+
 template <typename T, int TR, bool FUSE, bool STENCIL = true>
 __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
 {
+    rec_tap<T>(A.u, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
     constexpr int G = (TR >= 256 ? TR : 256) / TR;
     __shared__ XShared<T, TR, FUSE> sh[G];
     const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / TR);   // one group per wavefront or more

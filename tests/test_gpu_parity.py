@@ -280,6 +280,55 @@ def test_step_rotation_and_determinism(adw):
     assert g2 is g and h2 is h_ and torch.equal(h2, u1)
 
 
+@pytest.mark.parametrize("path", ["one_pass", "two_pass", "two_pass_f64", "cyclic_reduction"])
+def test_receiver_traces_every_path(adw, path):
+    """Traces of a multi-step call equal those of one-step calls bit for bit, and equal
+    each level sampled on the host.  Within a call, a step's receivers are recorded by
+    the next step's first launch, and the last step's by a launch of its own.  The test
+    uses 1500 receivers (more than one workgroup's threads), with repeated nodes and
+    offsets outside the grid, which record NaN."""
+    nx, ny, nsteps = 512, 300, 6
+    f64 = path == "two_pass_f64"
+    dt_ = torch.float64 if f64 else torch.float32
+    h = 1.0 / (max(nx, ny) + 1)
+    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=8).astype(np.float64 if f64 else np.float32)
+    u0 = wl.gaussian_pulse(nx, ny, sigma=0.08).astype(c.dtype)
+    rng = np.random.default_rng(8)
+    ri = rng.integers(0, nx * ny, 1500).astype(np.int32)
+    ri[::97] = ri[1]
+    ri[5], ri[700], ri[1499] = -3, nx * ny, nx * ny + 11
+    valid = (ri >= 0) & (ri < nx * ny)
+    src = np.array([(ny // 2) * nx + nx // 2], np.int32)
+    amp = (rng.standard_normal((nsteps, 1)) * 30.0).astype(c.dtype)
+    say(f"receiver traces {path}")
+    wave = adw.Wave(nx, ny, h, 0.4 * h / 3.0, c=dev(c), dtype=dt_)
+    wave.set_tuning(fused_step={"one_pass": True, "two_pass_f64": None}.get(path, False),
+                    cyclic_reduction=True if path == "cyclic_reduction" else None)
+    assert wave.info()["fused_step"] == int(path == "one_pass")
+    assert wave.info()["line_solver"] == (2 if path == "cyclic_reduction" else 1)
+    a0 = dev(u0)
+    b0 = wave.start(a0)
+    ridx = dev(ri)
+    tr_all = torch.zeros((nsteps, ri.size), dtype=dt_, device="cuda")
+    a, b = wave.step(a0.clone(), b0.clone(), nsteps, src_idx=dev(src), src_amp=dev(amp), rec_idx=ridx,
+                     traces=tr_all)
+    tr_one = torch.zeros_like(tr_all)
+    c_, d_ = a0.clone(), b0.clone()
+    levels = []
+    for k in range(nsteps):
+        c_, d_ = wave.step(c_, d_, 1, src_idx=dev(src), src_amp=dev(amp[k:k + 1]), rec_idx=ridx,
+                           traces=tr_one[k])
+        levels.append(d_.clone())
+    torch.cuda.synchronize()
+    wave.close()
+    assert torch.equal(b, d_)
+    ta, to = tr_all.cpu().numpy(), tr_one.cpu().numpy()
+    assert np.isnan(ta[:, ~valid]).all() and np.isnan(to[:, ~valid]).all()
+    assert np.array_equal(ta[:, valid], to[:, valid])
+    for k in range(nsteps):
+        assert np.array_equal(ta[k, valid], levels[k].cpu().numpy().ravel()[ri[valid]])
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("tr,rs,fused,m", [(64, 3, False, 16), (64, 1, True, 32), (256, 2, False, 32),
                                            (256, 5, True, 16), (1024, 32, False, 32),
