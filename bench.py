@@ -26,6 +26,15 @@ if ROOT not in sys.path:
 
 METRIC = "Mpts/s per ADI step + HBM GB/s (% peak); batched & adjoint vs plain, same GPU"
 HBM_PEAK_GBPS = 8000.0
+# The paper's own timings (Table 1: total seconds for 50 FP64 time steps of its
+# cyclic-reduction ADI solver on an RTX 2080 Ti with an i7-9800X host), converted
+# to Mpts/s per step.  Context only: other hardware, precision and solver design.
+PAPER_TABLE1 = {
+    "source": "Table 1, 50 FP64 steps, c = 1; RTX 2080 Ti + i7-9800X (3.8 GHz)",
+    "unit": "Mpts/s per step",
+    "8192x8192": {"cpu": 1.03, "gpu": 7.70, "gpu_openmp": 14.01, "gpu_openmp_mpi_8_cores": 21.04},
+    "2048x2048": {"cpu": 1.11, "gpu": 4.66, "gpu_openmp": 4.66, "gpu_openmp_mpi_8_cores": 6.93},
+}
 
 # Algorithmic bytes per grid node per launch (element size E, per-node coefficient):
 #   x_sweep_rhs     reads u^n and r, writes w                      3E
@@ -423,6 +432,7 @@ def main():
         out["cr_baseline"] = bench_cr(adw, torch, prob, 10, value)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
+    out["paper_context"] = PAPER_TABLE1
     print(json.dumps(out), flush=True)
 
 
