@@ -59,7 +59,7 @@ def kernel_source_hash() -> str:
     """Hash of the sources that define the plain step's kernels and their launches
     (the batched and adjoint forms live in their own headers)."""
     h = hashlib.sha256()
-    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp", "xsweep.hpp", "fused.hpp", "fused4.hpp"):
+    for f in ("adiwave.hip", "kernels.hpp", "line_solver.hpp", "xsweep.hpp", "fused.hpp", "fused4.hpp", "fusedr.hpp"):
         with open(os.path.join(ROOT, "paper_2006_10142_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

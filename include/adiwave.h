@@ -307,6 +307,9 @@ typedef struct {
     int fused_tiles;          /* one-pass step: tiles per step (one workgroup each) */
     int fused_lane_nodes;     /* one-pass step: x-line nodes per lane (8, or 4 on tiles of at
                                  most 240 columns whose r stays in LDS for the y-lines) */
+    int fused_segment_rows;   /* one-pass step on column strips: output rows per strip
+                                 segment (one workgroup each, fused_tile_cols wide);
+                                 0 when the step runs on 64-row tiles */
 } adi_wave_info;
 
 adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);
@@ -329,6 +332,9 @@ typedef struct {
                                  nodes per lane); -1 = back to the automatic choice, 0 = keep */
     int fused_lane_nodes;     /* one-pass x-line nodes per lane: 8 or 4; -1 = back to the
                                  automatic choice (4 where the tiles come out narrow), 0 = keep */
+    int fused_segment_rows;   /* one-pass step on column strips (at most 240 columns, four
+                                 nodes per lane) with this many output rows per segment (>= 8),
+                                 -2 = on 64-row tiles, -1 = back to the automatic choice, 0 = keep */
 } adi_tuning;
 adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t);
 

@@ -287,20 +287,22 @@ class Wave:
 
     def set_tuning(self, x_threads_per_line=0, x_rows_per_strip=0, y_fused=None,
                    y_chunk_rows=0, fused_step=None, cyclic_reduction=None, fused_tile_cols=0,
-                   fused_lane_nodes=0):
+                   fused_lane_nodes=0, fused_segment_rows=0):
         """Override the launch plan (0 / None keeps the current value).  fused_step:
         True = one-pass step (FP32, when its truncation bound holds), False = exact
         two-pass step.  cyclic_reduction: True = the paper's cyclic-reduction line
         solver (one launch per level, for comparison), False = the default solvers.
         fused_tile_cols: one-pass tile width (multiple of 8, <= 496; -1 = automatic).
         fused_lane_nodes: one-pass x-line nodes per lane, 8 or 4 (4: tiles of at most
-        240 columns that keep r in LDS for the y-lines)."""
+        240 columns that keep r in LDS for the y-lines).  fused_segment_rows: one-pass
+        step on column strips (<= 240 columns), each workgroup marching down this many output rows (>= 8);
+        -2 = 64-row tiles, -1 = automatic."""
         self._sync_stream()
         f = 0 if y_fused is None else (1 if y_fused else 2)
         fs = 0 if fused_step is None else (1 if fused_step else 2)
         ls = 0 if cyclic_reduction is None else (2 if cyclic_reduction else 1)
         t = _lib.AdiTuning(x_threads_per_line, x_rows_per_strip, f, y_chunk_rows, fs, ls,
-                           fused_tile_cols, fused_lane_nodes)
+                           fused_tile_cols, fused_lane_nodes, fused_segment_rows)
         _lib.check(_lib.load().adi_wave_set_tuning(self._h, ctypes.byref(t)))
 
     def close(self):

@@ -37,14 +37,16 @@ class AdiWaveInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("fused_step", ctypes.c_int),
                 ("fused_allowed", ctypes.c_int), ("r_max", ctypes.c_double),
                 ("line_solver", ctypes.c_int), ("fused_tile_cols", ctypes.c_int),
-                ("fused_tiles", ctypes.c_int), ("fused_lane_nodes", ctypes.c_int)]
+                ("fused_tiles", ctypes.c_int), ("fused_lane_nodes", ctypes.c_int),
+                ("fused_segment_rows", ctypes.c_int)]
 
 
 class AdiTuning(ctypes.Structure):
     _fields_ = [("x_threads_per_line", ctypes.c_int), ("x_rows_per_strip", ctypes.c_int),
                 ("y_fused", ctypes.c_int), ("y_chunk_rows", ctypes.c_int),
                 ("fused_step", ctypes.c_int), ("line_solver", ctypes.c_int),
-                ("fused_tile_cols", ctypes.c_int), ("fused_lane_nodes", ctypes.c_int)]
+                ("fused_tile_cols", ctypes.c_int), ("fused_lane_nodes", ctypes.c_int),
+                ("fused_segment_rows", ctypes.c_int)]
 
 
 class AdiBatchPlan(ctypes.Structure):

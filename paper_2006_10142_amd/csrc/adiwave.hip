@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 #include "fused.hpp"
 #include "fused4.hpp"
+#include "fusedr.hpp"
 #include "cr.hpp"
 
 using namespace adw;
@@ -245,6 +246,8 @@ struct adi_wave_s {
     int f_wt_user = 0;   // tile width set through adi_wave_set_tuning (0: chosen here)
     int f_lane = 8;      // nodes per lane of the one-pass x-lines (8: fused.hpp, 4: fused4.hpp)
     int f_lane_user = 0; // nodes per lane set through adi_wave_set_tuning (0: chosen here)
+    int f_hs = 0;        // output rows per column-strip segment (fusedr.hpp); 0: 64-row tiles
+    int f_hs_user = 0;   // set through adi_wave_set_tuning: > 0 strips, -2 tiles, 0 chosen here
     int f4_wt = 0, f4_tx = 0, f4_tiles = 0;   // widest four-node tiles (used by the batched step)
     // cyclic-reduction baseline (line_solver = 2): coefficient arrays a, b, c
     int cr = 0;
@@ -506,6 +509,27 @@ void fused_plan(adi_wave_s* w)
     }
     w->f_tiles = w->f_tx * ((w->ny + kFuHt - 1) / kFuHt);
     w->f_grid = (w->f_tiles + 7) / 8 * 8;
+    // Column strips (fusedr.hpp): the widest strips of at most 240 columns, one
+    // segment of hs rows per compute unit.  Chosen automatically when that gives
+    // every segment at least kFrHmin rows (measured faster than the tiles from
+    // 4096^2 to 8192^2), or set through adi_wave_set_tuning.
+    w->f_hs = 0;
+    long long c = 0;
+    const int wt4 = fused_width(w->nx, w->ny, 0, kF4Wmax, kFuT4a, kFuT4b, &c);
+    int hs = w->f_hs_user > 0 ? w->f_hs_user : 0;
+    if (w->f_hs_user == 0 && w->f_ncu > 0 && w->f_wt_user == 0 && w->f_lane_user == 0) {
+        const int g = w->f_ncu / ((w->nx + wt4 - 1) / wt4);
+        const int h = g > 0 ? (w->ny + g - 1) / g : 0;
+        if (g > 0 && h >= kFrHmin) hs = h;
+    }
+    if (hs > 0) {
+        w->f_lane = 4;
+        w->f_wt = w->f_wt_user > 0 ? std::min(w->f_wt_user, kF4Wmax) : wt4;
+        w->f_tx = (w->nx + w->f_wt - 1) / w->f_wt;
+        w->f_hs = hs;
+        w->f_tiles = w->f_tx * ((w->ny + hs - 1) / hs);
+        w->f_grid = w->f_tiles;
+    }
 }
 
 // largest r of an FP32 handle (synchronises the stream); X is free scratch here
@@ -568,7 +592,10 @@ adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const ad
     a.nrec = w->tap_n;
     a.rec_idx = w->tap_idx;
     a.rec_out = static_cast<float*>(w->tap_out);
-    if (w->f_lane == 4)
+    a.hs = w->f_hs;
+    if (w->f_hs > 0)
+        hipLaunchKernelGGL(k_fusedr, dim3(w->f_grid), dim3(kFrThreads), 0, w->stream, a);
+    else if (w->f_lane == 4)
         hipLaunchKernelGGL(k_fused4, dim3(w->f_grid), dim3(1024), 0, w->stream, a);
     else
         hipLaunchKernelGGL(k_fused, dim3(w->f_grid), dim3(1024), 0, w->stream, a);
@@ -848,6 +875,7 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->fused_tile_cols = w->f_wt;
     info->fused_tiles = w->f_tiles;
     info->fused_lane_nodes = w->f_lane;
+    info->fused_segment_rows = w->f_hs;
     return ADI_OK;
 }
 
@@ -878,11 +906,19 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
     const int wt_req = t->fused_tile_cols > 0 ? t->fused_tile_cols : 0;
     if (wt_req > 0 && (wt_req % 8 != 0 || wt_req > wmax))
         return fail(ADI_EINVAL, "fused_tile_cols must be a multiple of 8 and at most 496 (240 with 4 nodes per lane)");
+    if (t->fused_segment_rows < -2 || (t->fused_segment_rows > 0 && t->fused_segment_rows < 8))
+        return fail(ADI_EINVAL, "fused_segment_rows must be -2, -1, 0 or at least 8");
+    if (t->fused_segment_rows > 0 && t->fused_lane_nodes == 8)
+        return fail(ADI_EINVAL, "column strips take four nodes per lane");
+    if (t->fused_segment_rows > 0 && wt_req > kF4Wmax)
+        return fail(ADI_EINVAL, "column strips are at most 240 columns wide");
     if (t->fused_step > 0) w->fused_mode = t->fused_step;
+    if (t->fused_segment_rows) w->f_hs_user = t->fused_segment_rows == -1 ? 0 : t->fused_segment_rows;
     if (t->fused_tile_cols > 0) w->f_wt_user = t->fused_tile_cols;
     if (t->fused_tile_cols == -1) w->f_wt_user = 0;
     if (t->fused_lane_nodes) w->f_lane_user = t->fused_lane_nodes > 0 ? t->fused_lane_nodes : 0;
-    if (t->fused_step > 0 || t->fused_tile_cols > 0 || t->fused_tile_cols == -1 || t->fused_lane_nodes)
+    if (t->fused_step > 0 || t->fused_tile_cols > 0 || t->fused_tile_cols == -1 || t->fused_lane_nodes ||
+        t->fused_segment_rows)
         fused_plan(w);
     if (t->line_solver < 0 || t->line_solver > 2) return fail(ADI_EINVAL, "line_solver must be 0, 1 or 2");
     if (t->line_solver == 2 && !w->cr_abc) {

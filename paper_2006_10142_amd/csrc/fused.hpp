@@ -56,6 +56,7 @@ struct FArgs {
     int wt;              // output columns per tile (multiple of 8)
     int tiles_x, tiles;  // tiles across, total tiles
     int xcd_map;         // 1: block -> tile map that keeps neighbours on one XCD
+    int hs;              // column strips (fusedr.hpp): output rows per strip segment
     float tau2;
     int nsrc;
     const int* src_idx;

@@ -1,0 +1,358 @@
+// fusedr.hpp -- the one-pass step (FP32) on column strips with the work split by
+// role, so that the y-lines run while the next x-rows are solved and loaded.
+// Included by adiwave.hip after fused4.hpp, whose x-row scheme it uses.
+//
+// A workgroup owns a strip of Wt output columns (a multiple of 8, <= 240) and hs
+// output rows, and walks down it in bands of 24 x-rows; band k holds the x-rows
+// [r0 - 8 + 24k, r0 + 16 + 24k).
+//   x-role (8 wavefronts): three x-rows each per band, four nodes per lane, on
+//     the window [c0 - 8, c0 + Wt + 8) exactly as fused4.hpp; w and r of the
+//     central columns go to a ring of 56 rows in LDS.  The inputs of band k + 1
+//     are in registers, and those of band k + 2 are requested as soon as band k
+//     is solved.
+//   y-role (4 wavefronts, one thread per column): in the same pass, band k - 1.
+//     The forward elimination of each y-line continues down the strip from row
+//     r0 - 8 (zero carries: the upper cut, 9 rows above the first output row),
+//     over the band's 24 rows (g and the pivots replace w and r in the ring).  The back
+//     substitution starts at the band's last row with a zero value (the lower
+//     cut, 9 rows below the band's last output row), runs up through the band
+//     and through the 8 look-ahead rows kept in the ring by the band before, and
+//     updates the output rows [r0 - 16 + 24k, r0 + 8 + 24k) (band 0: [r0, r0 + 8))
+//     as it goes: u^{n+1} = 2 u^n - u^{n-1} + d, whose operands were requested a
+//     pass ahead.  The band's last 8 rows (g and pivots) stay in the ring.
+// Each output row is the solution of a y-window whose cuts are at least 9 rows
+// away, and each x-row that of an x-window cut 9 columns away, so the truncation
+// bound of fused.hpp holds unchanged.  A barrier separates the passes: the
+// ring's 56 rows hold the band being solved (24), the band being eliminated (24)
+// and the look-ahead rows before it (8), and these never overlap.
+
+namespace adw {
+
+constexpr int kFrB = 24;                   // x-rows per band
+constexpr int kFrR = 2 * kFrB + kFuKy;     // ring rows (56)
+constexpr int kFrY = 4;                    // y-role wavefronts (one thread per column)
+constexpr int kFrX = 8;                    // x-role wavefronts
+constexpr int kFrXr = kFrB / kFrX;         // x-rows per x-role wavefront per band (3)
+constexpr int kFrThreads = 64 * (kFrY + kFrX);   // workgroup size (768: 168 VGPRs a thread)
+constexpr int kFrS = kF4Wmax;              // ring row stride (240)
+constexpr int kFrHmin = 256;               // shortest strip segment the plan picks by itself
+
+struct FRShared {
+    float w[kFrR * kFrS];   // w; the look-ahead rows then hold g
+    float r[kFrR * kFrS];   // r; the look-ahead rows then hold the pivots
+    float src_add[kFuSrc];
+    int src_row[kFuSrc];
+    int src_wc[kFuSrc];
+    int src_n;              // -1: more than kFuSrc in this strip
+};
+
+// x-role inputs of one band: u^n rows j-1 .. j+kFrXr and r rows j .. j+kFrXr-1
+// of the wavefront's x-rows, with the window-edge values and entry pivots
+struct FRIn {
+    float u[kFrXr + 2][kF4Seg];
+    float e[kFrXr + 2];
+    float r[kFrXr][kF4Seg];
+    float q[kFrXr];
+};
+
+__global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
+{
+    __shared__ FRShared sh;
+    rec_tap<float>(A.uc, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
+    const int blk = blockIdx.x;
+    if (blk >= A.tiles) return;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int nx = A.nx, ny = A.ny, wt = A.wt;
+    const int c0 = (blk % A.tiles_x) * wt;
+    const int r0 = (blk / A.tiles_x) * A.hs;
+    const int r1 = min(r0 + A.hs, ny);
+    const int nb = r1 - r0 <= kFuKy ? 1 : 1 + (r1 - r0 - kFuKy + kFrB - 1) / kFrB;
+    const int nl = (wt + 2 * kFuKx) / kF4Seg;            // lanes of the x-window
+    const long long npts = (long long)nx * ny;
+    const int xr_lo = r0 - kFuKy, xr_hi = xr_lo + kFrB * nb;   // x-rows of the strip
+    auto slot = [&](int j) { return (j - xr_lo) % kFrR; };
+
+    // ---- point sources of the strip's x-rows and x-window, in source order
+    if (t < 64) {
+        int n = 0;
+        for (int base = 0; base < A.nsrc; base += 64) {
+            const int qq = base + t;
+            int id = -1;
+            float amp = 0.f;
+            if (qq < A.nsrc) { id = A.src_idx[qq]; amp = A.src_amp[qq]; }
+            const int row = (id >= 0 && id < npts) ? id / nx : -1;
+            const int col = row >= 0 ? id - row * nx : 0;
+            const int wc = col - (c0 - kFuKx);
+            const bool hit = row >= 0 && row >= xr_lo && row < xr_hi && wc >= 0 && wc < nl * kF4Seg;
+            const unsigned long long mask = __ballot(hit);
+            const int before = __popcll(mask & ((1ull << t) - 1ull));
+            if (hit && n + before < kFuSrc) {
+                sh.src_add[n + before] = A.tau2 * amp;
+                sh.src_row[n + before] = row;
+                sh.src_wc[n + before] = wc;
+            }
+            n += __popcll(mask);
+        }
+        if (t == 0) sh.src_n = n <= kFuSrc ? n : -1;
+    }
+    __syncthreads();
+    const int ns = sh.src_n;
+    const int row_bytes = nx * 4;
+    auto row_ok = [&](int j) { return j >= 0 && j < ny; };
+
+    // ---- x-role constants
+    const int xw = wv - kFrY;                               // x-role wavefront index
+    const bool inwin = lane < nl;
+    const int col0 = c0 - kFuKx + lane * kF4Seg;            // first column of the lane
+    const int voff = inwin ? col0 * 4 : kFuOOB;
+    const int seg = (c0 - kFuKx) / kSeg + (lane >> 1);      // its full-line 8-node segment
+    const bool odd = lane & 1;
+    const int qoff = inwin ? seg * 4 : kFuOOB;              // negative segments wrap past the row
+    const int eoff = (lane == 0) ? (c0 - kFuKx - 1) * 4 : (lane == nl - 1) ? (c0 + wt + kFuKx) * 4 : kFuOOB;
+    auto load4 = [&](rsrc_t rs, float (&v)[kF4Seg]) {
+        const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    };
+    // pieces of band k's inputs: u^n row j-1+i (with its window-edge values), and
+    // r row j+i with its entry pivots, j = the wavefront's first x-row of band k
+    auto load_u = [&](int k, int i, FRIn& P) {
+        const int jj = xr_lo + kFrB * k + kFrXr * xw - 1 + i;
+        const bool ok = row_ok(jj);
+        const rsrc_t rs = buf(A.uc + (size_t)(ok ? jj : 0) * nx, ok ? row_bytes : 0);
+        load4(rs, P.u[i]);
+        P.e[i] = bload1<float>(rs, eoff);
+    };
+    auto load_r = [&](int k, int i, FRIn& P) {
+        const int jj = xr_lo + kFrB * k + kFrXr * xw + i;
+        const bool ok = row_ok(jj);
+        load4(buf(A.r + (size_t)(ok ? jj : 0) * nx, ok ? row_bytes : 0), P.r[i]);
+        P.q[i] = bload1<float>(buf(A.qin + (size_t)(ok ? jj : 0) * A.nseg, ok ? A.nseg * 4 : 0), qoff);
+    };
+    auto load_band = [&](int k, FRIn& P) {
+#pragma unroll
+        for (int i = 0; i < kFrXr + 2; ++i) load_u(k, i, P);
+#pragma unroll
+        for (int i = 0; i < kFrXr; ++i) load_r(k, i, P);
+    };
+    // the x-rows of band k from P; w and r of the central columns to the ring
+    auto x_band = [&](int k, const FRIn& P) {
+#pragma unroll
+        for (int it = 0; it < kFrXr; ++it) {
+            const int j = xr_lo + kFrB * k + kFrXr * xw + it;
+            const float(&um)[kF4Seg] = P.u[it];
+            const float(&uc)[kF4Seg] = P.u[it + 1];
+            const float(&u1)[kF4Seg] = P.u[it + 2];
+            const float(&rc)[kF4Seg] = P.r[it];
+            const float eC = P.e[it + 1];
+            float rho[kF4Seg];
+            {
+                const float west = dpp<kWaveShr1>(0.f, uc[kF4Seg - 1]);
+                const float east = dpp<kWaveShl1>(0.f, uc[0]);
+                const float w0 = lane == 0 ? eC : west;
+                const float eL = lane == nl - 1 ? eC : east;
+#pragma unroll
+                for (int e = 0; e < kF4Seg; ++e) {
+                    const float uw = e == 0 ? w0 : uc[e - 1];
+                    const float ue = e == kF4Seg - 1 ? eL : uc[e + 1];
+                    rho[e] = 2.f * (rc[e] * (((uw + ue) + (um[e] + u1[e])) - 4.f * uc[e]));
+                }
+            }
+            if (ns > 0) {
+                for (int s = 0; s < ns; ++s) {
+                    if (sh.src_row[s] == j) {
+                        const int i = sh.src_wc[s] - lane * kF4Seg;
+                        const float add = sh.src_add[s];
+#pragma unroll
+                        for (int e = 0; e < kF4Seg; ++e)
+                            if (e == i) rho[e] += add;
+                    }
+                }
+            } else if (ns < 0 && row_ok(j)) {
+                for (int s = 0; s < A.nsrc; ++s) {
+                    const int id = A.src_idx[s];
+                    if (id >= 0 && id < npts && id / nx == j) {
+                        const int i = id - j * nx - col0;
+                        const float add = A.tau2 * A.src_amp[s];
+#pragma unroll
+                        for (int e = 0; e < kF4Seg; ++e)
+                            if (e == i && inwin) rho[e] += add;
+                    }
+                }
+            }
+            // entry pivot: the segment's full-line pivot, carried by odd lanes over
+            // the four nodes of the even lane before them
+            float q = P.q[it];
+            {
+                float qo = q;
+#pragma unroll
+                for (int e = 0; e < kF4Seg; ++e) (void)pivot_step<float>(dpp<kRowShr + 1>(0.f, rc[e]), qo);
+                q = odd ? qo : q;
+            }
+            float Ge[kF4Seg], qe[kF4Seg], Qe[kF4Seg];
+            float fG, fQ, H, Ev;
+            {
+                float Gv = 0.f, Qv = 1.f, h = 0.f, ee = 0.f;
+#pragma unroll
+                for (int e = 0; e < kF4Seg; ++e) {
+                    const float m = pivot_step<float>(rc[e], q);
+                    const float Pq = Qv;
+                    Gv = fma_rn(m, rho[e], q * Gv);
+                    Qv = q * Qv;
+                    h = fma_rn(Pq, Gv, h);
+                    ee = fma_rn(Pq, Qv, ee);
+                    Ge[e] = Gv;
+                    qe[e] = q;
+                    Qe[e] = Qv;
+                }
+                fG = Gv; fQ = Qv; H = h; Ev = ee;
+            }
+            float a = fG, b = fQ;
+            fu_scan_fwd(a, b);
+            const float gin = dpp<kWaveShr1>(0.f, a);
+            float ba = inwin ? fma_rn(Ev, gin, H) : 0.f, bb = inwin ? fQ : 1.f;
+            wave_scan_bwd2(ba, bb, lane);
+            const float dbelow = dpp<kWaveShl1>(0.f, ba);
+            float wout[kF4Seg];
+            {
+                float x = dbelow;
+#pragma unroll
+                for (int e = kF4Seg - 1; e >= 0; --e) {
+                    x = fma_rn(qe[e], x, fma_rn(Qe[e], gin, Ge[e]));
+                    wout[e] = x;
+                }
+            }
+            if (lane >= kFuKx / kF4Seg && lane < nl - kFuKx / kF4Seg) {
+                const int o = slot(j) * kFrS + (lane - kFuKx / kF4Seg) * kF4Seg;
+                *reinterpret_cast<float4*>(sh.w + o) = make_float4(wout[0], wout[1], wout[2], wout[3]);
+                *reinterpret_cast<float4*>(sh.r + o) = make_float4(rc[0], rc[1], rc[2], rc[3]);
+            }
+        }
+    };
+
+    // ---- y-role constants: column c0 + t of the strip (t < wt)
+    const bool ycol = t < wt && c0 + t < nx;
+    const int lim = (int)(npts * 4);
+    const rsrc_t ruc = buf(A.uc, lim);
+    const rsrc_t rup = buf(static_cast<const float*>(A.up), lim);
+    float gcar = 0.f, qcar = 0.f;                           // forward carries of the column
+    float cu[kFrB], pu[kFrB];                                // u^n, u^{n-1} of the next band's output rows
+    // the update operands and results of output row o of band b (row xb - 8 + o):
+    // the column's byte offset in a VGPR (out of range for threads past the strip)
+    // and the row's in the scalar offset; rows outside the band's output rows are
+    // loaded clamped into the grid (unused) and not stored (a uniform test)
+    const int vcol = ycol ? (c0 + t) * 4 : kFuOOB;
+    const int rowb = nx * 4;
+    auto out_row = [&](int b, int o) {
+        const int j = xr_lo + kFrB * b - kFuKy + o;
+        return j >= max(r0, xr_lo + kFrB * b - kFuKy) && j < min(r1, xr_lo + kFrB * b + 2 * kFuKy);
+    };
+    auto srow = [&](int b, int o) {
+        const int j = xr_lo + kFrB * b - kFuKy + o;
+        return (j < 0 ? 0 : j >= ny ? ny - 1 : j) * rowb;
+    };
+    auto load_upd = [&](int b) {
+#pragma unroll
+        for (int o = 0; o < kFrB; ++o) {
+            const int so = srow(b, o);
+            cu[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ruc, vcol, so, kFuNT));
+            pu[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rup, vcol, so, kFuNT));
+        }
+    };
+    // band b: its update operands (requested one pass earlier) are combined first,
+    // and band b+1's are requested at once, so they have a whole pass to arrive;
+    // then the forward elimination over the band's rows (g and the pivots replace
+    // w and r in the ring), and the back substitution with the update
+    auto y_band = [&](int b) {
+        const int xb = xr_lo + kFrB * b;
+        float base[kFrB];                                    // 2 u^n - u^{n-1} of the output rows
+#pragma unroll
+        for (int o = 0; o < kFrB; ++o) base[o] = fma_rn(2.f, cu[o], -pu[o]);
+        load_upd(b + 1);                                     // past the last band: out of range
+        const int s0 = slot(xb);
+        // ring slot s (< 2 kFrR) of this column; threads past the strip read a valid
+        // column and write nothing, so every thread issues the same memory operations
+        const int ty = t < wt ? t : wt - 1;
+        auto at = [&](int s) { return (s >= kFrR ? s - kFrR : s) * kFrS + ty; };
+        constexpr int kG = 8;                                // rows per group of LDS reads
+#pragma unroll
+        for (int c = 0; c < kFrB / kG; ++c) {
+            float rr[kG], ww[kG];
+#pragma unroll
+            for (int e = 0; e < kG; ++e) {
+                rr[e] = sh.r[at(s0 + kG * c + e)];
+                ww[e] = sh.w[at(s0 + kG * c + e)];
+            }
+#pragma unroll
+            for (int e = 0; e < kG; ++e) {
+                const float m = pivot_step<float>(rr[e], qcar);
+                gcar = fma_rn(m, ww[e], qcar * gcar);
+                if (t < wt) {
+                    sh.w[at(s0 + kG * c + e)] = gcar;
+                    sh.r[at(s0 + kG * c + e)] = qcar;
+                }
+            }
+        }
+        // back substitution from the band's last row, up through the look-ahead rows
+        // of the band before (rows xb - 8 .. xb - 1; band 0 has none: zeros, and its
+        // rows there are above the strip, so nothing is stored for them)
+        const int sl = slot(xb + kFrR - kFuKy);                // = slot(xb - 8)
+        float d = 0.f;
+#pragma unroll
+        for (int c = 0; c < (kFrB + kFuKy) / kG; ++c) {
+            // group c covers rows xb + 16 - 8c .. xb + 23 - 8c (c = 3: the look-ahead rows)
+            const bool prev = c == kFrB / kG;
+            const int sg = prev ? sl : s0 + kFrB - kG * (c + 1);
+            float gg[kG], qq[kG];
+#pragma unroll
+            for (int e = 0; e < kG; ++e) {
+                gg[e] = sh.w[at(sg + e)];
+                qq[e] = sh.r[at(sg + e)];
+                if (prev && b == 0) { gg[e] = 0.f; qq[e] = 0.f; }
+            }
+            const int o0 = kFrB - kG * c;                       // output index of the group's first row
+#pragma unroll
+            for (int e = kG - 1; e >= 0; --e) {
+                d = fma_rn(qq[e], d, gg[e]);
+                const int o = o0 + e;                           // rows xb - 8 + o
+                if (o < kFrB && out_row(b, o)) {
+                    const float v = base[o] + d;
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), rup, vcol, srow(b, o), kFuNT);
+                }
+            }
+        }
+    };
+
+    // pass k: the x-role solves band k, the y-role band k - 1.  The two roles run
+    // separate loops over the same passes with two barriers per iteration, so
+    // every wavefront meets the same barriers and each role has its own registers.
+    if (wv < kFrY) {
+        // one barrier per pass: pass 0 (band 0 being solved), then band b in pass
+        // b + 1, and a last barrier when the x-role's loop makes an odd count
+        load_upd(0);
+        __syncthreads();
+        for (int b = 0; b < nb; ++b) {
+            y_band(b);
+            __syncthreads();
+        }
+        if ((nb & 1) == 0) __syncthreads();
+    } else {
+        // the loads are issued on every path (rows past the strip's last band read
+        // as zero or are never used), so the outstanding-load count is the same at
+        // every point of the loop and each wait covers only the band it needs
+        FRIn PA, PB;
+        load_band(0, PA);
+        load_band(1, PB);
+        for (int k = 0; k <= nb; k += 2) {
+            if (k < nb) x_band(k, PA);
+            load_band(k + 2, PA);
+            __syncthreads();
+            if (k + 1 < nb) x_band(k + 1, PB);
+            load_band(k + 3, PB);
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace adw

@@ -1,6 +1,6 @@
-"""The one-pass FP32 step (truncated line solves on overlapping tiles): its plan
-selection and truncation-bound switch, parity with the FP64 oracle (the exact
-two-pass scheme) over tile layouts with ragged edges, point sources and receivers,
+"""The one-pass FP32 step (truncated line solves on overlapping tiles and on column
+strips): its plan selection and truncation-bound switch, parity with the FP64 oracle (the exact
+two-pass scheme) over tile and strip layouts with ragged edges, point sources and receivers,
 and agreement with the GPU's exact two-pass step.
 
 The truncation error of one step is kept below 2^-24 of max|w| by the plan (it
@@ -52,7 +52,8 @@ def case(nx, ny, cfl=0.4, seed=3, nsteps=30, nsrc=2, nrec=6):
 
 def gpu(adw, k, one_pass):
     wave = adw.Wave(k["nx"], k["ny"], k["h"], k["dt"], c=dev(k["c"]), dtype=torch.float32)
-    wave.set_tuning(fused_step=one_pass, fused_lane_nodes=k.get("lane", 0), fused_tile_cols=k.get("tile_cols", 0))
+    wave.set_tuning(fused_step=one_pass, fused_lane_nodes=k.get("lane", 0), fused_tile_cols=k.get("tile_cols", 0),
+                    fused_segment_rows=k.get("hs", 0))
     info = wave.info()
     assert info["fused_step"] == int(one_pass)
     a = dev(k["u0"])
@@ -118,27 +119,50 @@ def plan(nx, ny, ncu, wmax, ta, tb):
 
 
 def balanced(nx, ny, ncu):
-    """(nodes per lane, width) the plan picks: the cheaper of the two variants"""
+    """(nodes per lane, width) of the tile plan: the cheaper of the two variants"""
     w8, c8 = plan(nx, ny, ncu, 496, 16000, 30)
     w4, c4 = plan(nx, ny, ncu, 240, 12000, 15)
     return (4, w4) if c4 < c8 else (8, w8)
 
 
+def auto_plan(nx, ny, ncu):
+    """(nodes per lane, width, strip segment rows or 0) the plan picks: column strips
+    (the widest of at most 240 columns, one segment per compute unit) when every
+    segment gets at least 256 rows, else the tile plan"""
+    w4 = widest(nx, 240)
+    g = ncu // -(-nx // w4)
+    if g > 0 and -(-ny // g) >= 256:
+        return 4, w4, -(-ny // g)
+    return balanced(nx, ny, ncu) + (0,)
+
+
+STRIP_LAYOUTS = {"strips_h8": 8, "strips_h30": 30, "strips_h1000": 1000}
+
+
 @pytest.mark.parametrize("nx,ny", [(480, 64), (488, 65), (1000, 700), (960, 130), (64, 64), (2048, 300),
                                    (4, 200), (1504, 33)])
-@pytest.mark.parametrize("layout", ["auto", "lane8", "lane8_widest", "lane4", "lane4_widest"])
+@pytest.mark.parametrize("layout", ["auto", "lane8", "lane8_widest", "lane4", "lane4_widest"] + sorted(STRIP_LAYOUTS))
 def test_one_pass_matches_oracle(adw, oracle_lib, nx, ny, layout):
     """layouts: the automatic plan; eight or four nodes per lane (four: r kept in LDS
-    for the y-lines), each on the plan's width and on the widest tiles"""
+    for the y-lines), each on the plan's width and on the widest tiles; column strips
+    with 8, 30 and 1000 output rows per segment (bands cut anywhere, segments shorter
+    than a band, a strip longer than the grid)"""
     k = case(nx, ny, seed=nx + ny)
-    k["lane"] = {"auto": -1, "lane8": 8, "lane8_widest": 8, "lane4": 4, "lane4_widest": 4}[layout]
+    strips = layout in STRIP_LAYOUTS
+    k["lane"] = {"auto": -1, "lane8": 8, "lane8_widest": 8, "lane4": 4, "lane4_widest": 4}.get(layout, 0)
     k["tile_cols"] = widest(nx, 240 if k["lane"] == 4 else 496) if layout.endswith("widest") else -1
+    k["hs"] = STRIP_LAYOUTS[layout] if strips else (-1 if layout == "auto" else -2)
     say(f"one-pass {nx}x{ny} {layout}")
     got, tr, info = gpu(adw, k, True)
     if layout.endswith("widest"):
         assert info["fused_tile_cols"] == widest(nx, 240 if k["lane"] == 4 else 496)
     if k["lane"] > 0:
         assert info["fused_lane_nodes"] == k["lane"]
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    assert info["fused_segment_rows"] == (k["hs"] if strips else auto_plan(nx, ny, ncu)[2] if layout == "auto" else 0)
+    if strips:
+        assert info["fused_lane_nodes"] == 4 and info["fused_tile_cols"] == widest(nx, 240)
+        assert info["fused_tiles"] == -(-nx // info["fused_tile_cols"]) * -(-ny // k["hs"])
     ref, rtr = oracle(oracle_lib, k)
     assert rel_l2(got, ref) <= TOL
     assert rel_l2(tr, rtr) <= TOL
@@ -153,7 +177,7 @@ def test_one_pass_equals_two_pass_on_gpu(adw):
     assert rel_l2(ta, tb) <= 3e-6
 
 
-@pytest.mark.parametrize("lane", [8, 4])
+@pytest.mark.parametrize("lane", [8, 4, "strips"])
 def test_one_pass_near_the_bound(adw, oracle_lib, lane):
     """r_max = 0.17, just inside the bound (the truncation is then closest to 2^-24)."""
     nx = ny = 512
@@ -161,8 +185,8 @@ def test_one_pass_near_the_bound(adw, oracle_lib, lane):
     dt = np.sqrt(2 * 0.17) * h / 3.0
     k = case(nx, ny, seed=5, nsteps=80)
     k["dt"] = dt
-    k["lane"] = lane
-    say("one-pass near bound")
+    k["lane"], k["hs"] = (0, 100) if lane == "strips" else (lane, -2)
+    say(f"one-pass near bound {lane}")
     got, tr, info = gpu(adw, k, True)
     assert 0.165 < info["r_max"] < 0.175
     ref, rtr = oracle(oracle_lib, k)
@@ -170,12 +194,12 @@ def test_one_pass_near_the_bound(adw, oracle_lib, lane):
     assert rel_l2(tr, rtr) <= TOL
 
 
-@pytest.mark.parametrize("lane", [8, 4])
+@pytest.mark.parametrize("lane", [8, 4, "strips"])
 def test_one_pass_many_sources_in_a_tile(adw, oracle_lib, lane):
     """More point sources in one tile than it stages (read from memory instead),
     including repeated nodes."""
     k = case(480, 64, seed=11, nsteps=20, nsrc=40)
-    k["lane"] = lane
+    k["lane"], k["hs"] = (0, 64) if lane == "strips" else (lane, -2)
     k["src_idx"][5] = k["src_idx"][3]
     say("one-pass 40 sources")
     got, tr, _ = gpu(adw, k, True)
@@ -185,37 +209,57 @@ def test_one_pass_many_sources_in_a_tile(adw, oracle_lib, lane):
 
 
 def test_tile_width_plan(adw):
-    """The plan balances the tiles over the device's compute units; the width can
-    be forced and set back to automatic; bad widths are rejected."""
+    """The plan: column strips where each compute unit gets a segment of at least 256
+    rows, else tiles balanced over the compute units; widths, lanes and segment rows
+    can be forced and set back to automatic; bad values are rejected."""
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     for n in (8192, 6144, 4096, 2048, 1024):
         w = adw.Wave(n, n, 1.0 / (n + 1), 0.5 / (n + 1), c=1.0, dtype=torch.float32)
         i = w.info()
-        assert (i["fused_lane_nodes"], i["fused_tile_cols"]) == balanced(n, n, ncu), (n, i)
-        assert i["fused_tiles"] == -(-n // i["fused_tile_cols"]) * -(-n // 64)
+        lane, wt, hs = auto_plan(n, n, ncu)
+        assert (i["fused_lane_nodes"], i["fused_tile_cols"], i["fused_segment_rows"]) == (lane, wt, hs), (n, i)
+        assert i["fused_tiles"] == -(-n // wt) * -(-n // (hs if hs else 64))
         w.set_tuning(fused_lane_nodes=8, fused_tile_cols=488)
-        assert w.info()["fused_tile_cols"] == 488 and w.info()["fused_lane_nodes"] == 8
+        j = w.info()
+        assert j["fused_tile_cols"] == 488 and j["fused_lane_nodes"] == 8 and j["fused_segment_rows"] == 0
         with pytest.raises(RuntimeError):
             w.set_tuning(fused_lane_nodes=4, fused_tile_cols=248)     # 4 nodes per lane: <= 240
         w.set_tuning(fused_lane_nodes=-1, fused_tile_cols=-1)
-        assert w.info()["fused_tile_cols"] == i["fused_tile_cols"]
-        assert w.info()["fused_lane_nodes"] == i["fused_lane_nodes"]
+        j = w.info()
+        assert (j["fused_lane_nodes"], j["fused_tile_cols"], j["fused_segment_rows"]) == (lane, wt, hs)
         for bad in (500, 100):
             with pytest.raises(RuntimeError):
                 w.set_tuning(fused_tile_cols=bad)
+        w.set_tuning(fused_segment_rows=100)
+        j = w.info()
+        assert (j["fused_lane_nodes"], j["fused_tile_cols"], j["fused_segment_rows"]) == (4, widest(n, 240), 100)
+        assert j["fused_tiles"] == -(-n // widest(n, 240)) * -(-n // 100)
+        w.set_tuning(fused_segment_rows=-2)
+        assert w.info()["fused_segment_rows"] == 0
+        w.set_tuning(fused_segment_rows=-1)
+        j = w.info()
+        assert (j["fused_lane_nodes"], j["fused_tile_cols"], j["fused_segment_rows"]) == (lane, wt, hs)
+        for bad in ({"fused_segment_rows": 5}, {"fused_segment_rows": -3},
+                    {"fused_segment_rows": 100, "fused_lane_nodes": 8},
+                    {"fused_segment_rows": 100, "fused_tile_cols": 248}):
+            with pytest.raises(RuntimeError):
+                w.set_tuning(**bad)
         w.close()
 
 
 def test_forced_widths_agree(adw):
-    """Different tile layouts truncate at different places: each stays within
-    the bound of the exact step."""
+    """Different tile and strip layouts truncate at different places: each stays
+    within the bound of the exact step."""
     k = case(1000, 700, cfl=0.5, seed=4, nsteps=40)
     ref, rtr, _ = gpu(adw, k, False)
-    for wt, lane in ((64, 8), (136, 8), (256, 8), (496, 8), (64, 4), (120, 4), (240, 4)):
+    for wt, lane, hs in ((64, 8, -2), (136, 8, -2), (256, 8, -2), (496, 8, -2), (64, 4, -2), (120, 4, -2),
+                         (240, 4, -2), (64, 0, 40), (120, 0, 333), (240, 0, 8), (200, 0, 701)):
         k["tile_cols"] = wt
         k["lane"] = lane
-        say(f"one-pass 1000x700 width {wt}, {lane} nodes per lane")
+        k["hs"] = hs
+        say(f"one-pass 1000x700 width {wt}, {lane} nodes per lane, segment rows {hs}")
         got, tr, info = gpu(adw, k, True)
-        assert info["fused_tile_cols"] == wt and info["fused_lane_nodes"] == lane
+        assert info["fused_tile_cols"] == wt and info["fused_lane_nodes"] == (lane or 4)
+        assert info["fused_segment_rows"] == max(hs, 0)
         assert rel_l2(got, ref) <= 3e-6
         assert rel_l2(tr, rtr) <= 3e-6
