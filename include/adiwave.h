@@ -301,14 +301,16 @@ typedef struct {
     int fused_allowed;        /* 1: the one-pass step's truncation bound holds (FP32) */
     double r_max;             /* largest r = dt^2 kappa / (2 h^2) (FP32 handles) */
     int line_solver;          /* 1: partition / scan solvers, 2: cyclic-reduction baseline */
-    int fused_tile_cols;      /* one-pass step: output columns per tile (64 rows each);
-                                 chosen to balance the tiles over the device's compute
-                                 units unless set through adi_wave_set_tuning */
-    int fused_tiles;          /* one-pass step: tiles per step (one workgroup each) */
+    int fused_tile_cols;      /* one-pass step: output columns per tile (64 rows each) or per
+                                 column strip; chosen for the device's compute units unless
+                                 set through adi_wave_set_tuning */
+    int fused_tiles;          /* one-pass step: tiles, or strip segments, per step (one
+                                 workgroup each) */
     int fused_lane_nodes;     /* one-pass step: x-line nodes per lane (8, or 4 on tiles of at
                                  most 240 columns whose r stays in LDS for the y-lines) */
-    int fused_segment_rows;   /* one-pass step on column strips: output rows per strip
-                                 segment (one workgroup each, fused_tile_cols wide);
+    int fused_segment_rows;   /* one-pass step on column strips (chosen where every compute
+                                 unit gets a segment of >= 256 rows): output rows per strip
+                                 segment (fused_tile_cols wide, four nodes per lane);
                                  0 when the step runs on 64-row tiles */
 } adi_wave_info;
 
