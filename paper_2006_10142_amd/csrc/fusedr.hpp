@@ -38,8 +38,8 @@ constexpr int kFrS = kF4Wmax;              // ring row stride (240)
 constexpr int kFrHmin = 256;               // shortest strip segment the plan picks by itself
 
 struct FRShared {
-    float w[kFrR * kFrS];   // w; the look-ahead rows then hold g
-    float r[kFrR * kFrS];   // r; the look-ahead rows then hold the pivots
+    float w[kFrR * kFrS];   // w of the x-rows, then g once the y-role has eliminated them
+    float r[kFrR * kFrS];   // r of the x-rows, then the y-lines' pivots
     float src_add[kFuSrc];
     int src_row[kFuSrc];
     int src_wc[kFuSrc];
