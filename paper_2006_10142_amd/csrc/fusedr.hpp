@@ -325,8 +325,10 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
     };
 
     // pass k: the x-role solves band k, the y-role band k - 1.  The two roles run
-    // separate loops over the same passes with two barriers per iteration, so
-    // every wavefront meets the same barriers and each role has its own registers.
+    // separate loops over the same passes (the x-role two passes per iteration, the
+    // y-role one), each meeting one barrier per pass: nb + 2 barriers for even nb,
+    // nb + 1 for odd, after the one above.  Every wavefront thus meets the same
+    // barriers, and each role has its own registers.
     if (wv < kFrY) {
         // one barrier per pass: pass 0 (band 0 being solved), then band b in pass
         // b + 1, and a last barrier when the x-role's loop makes an odd count
