@@ -140,7 +140,7 @@ STRIP_LAYOUTS = {"strips_h8": 8, "strips_h30": 30, "strips_h1000": 1000}
 
 
 @pytest.mark.parametrize("nx,ny", [(480, 64), (488, 65), (1000, 700), (960, 130), (64, 64), (2048, 300),
-                                   (4, 200), (1504, 33)])
+                                   (4, 200), (1504, 33), (64, 1), (40, 3)])
 @pytest.mark.parametrize("layout", ["auto", "lane8", "lane8_widest", "lane4", "lane4_widest"] + sorted(STRIP_LAYOUTS))
 def test_one_pass_matches_oracle(adw, oracle_lib, nx, ny, layout):
     """layouts: the automatic plan; eight or four nodes per lane (four: r kept in LDS
