@@ -38,8 +38,8 @@ constexpr int kFrS = kF4Wmax;              // ring row stride (240)
 constexpr int kFrHmin = 256;               // shortest strip segment the plan picks by itself
 
 struct FRShared {
-    float w[kFrR * kFrS];   // w of the x-rows, then g once the y-role has eliminated them
-    float r[kFrR * kFrS];   // r of the x-rows, then the y-lines' pivots
+    alignas(16) float w[kFrR * kFrS];   // w of the x-rows, then g once the y-role has eliminated them
+    alignas(16) float r[kFrR * kFrS];   // r of the x-rows, then the y-lines' pivots
     float src_add[kFuSrc];
     int src_row[kFuSrc];
     int src_wc[kFuSrc];
@@ -224,9 +224,11 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
                 }
             }
             if (lane >= kFuKx / kF4Seg && lane < nl - kFuKx / kF4Seg) {
-                const int o = slot(j) * kFrS + (lane - kFuKx / kF4Seg) * kF4Seg;
-                *reinterpret_cast<float4*>(sh.w + o) = make_float4(wout[0], wout[1], wout[2], wout[3]);
-                *reinterpret_cast<float4*>(sh.r + o) = make_float4(rc[0], rc[1], rc[2], rc[3]);
+                // indexed in float4 units, so that each lane's four values are one 16-byte
+                // LDS write (contiguous across the wavefront, free of bank conflicts)
+                const int o4 = slot(j) * (kFrS / 4) + (lane - kFuKx / kF4Seg);
+                reinterpret_cast<float4*>(sh.w)[o4] = make_float4(wout[0], wout[1], wout[2], wout[3]);
+                reinterpret_cast<float4*>(sh.r)[o4] = make_float4(rc[0], rc[1], rc[2], rc[3]);
             }
         }
     };
