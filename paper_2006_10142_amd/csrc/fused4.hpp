@@ -29,8 +29,8 @@ constexpr int kF4Nb = kF4Hb + 2 * kFuKy;       // rows of a y-window (32)
 constexpr int kF4Win = kFuHt / kF4Hb;          // y-windows per column (4)
 
 struct FShared4 {
-    float w[kFuRows * kF4Wmax];
-    float r[kFuRows * kF4Wmax];
+    alignas(16) float w[kFuRows * kF4Wmax];
+    alignas(16) float r[kFuRows * kF4Wmax];
     float src_add[kFuSrc];
     int src_pos[kFuSrc];   // (x-row << 16) | window column
     int src_n;             // -1: more than kFuSrc in this tile
@@ -218,9 +218,10 @@ __device__ __forceinline__ void fused4_tile(const FArgs& A, const int tile, FSha
             }
             // central columns of w and r to LDS (lanes 2 .. nl-3 hold columns c0 .. c0+wt-1)
             if (lane >= kFuKx / kF4Seg && lane < nl - kFuKx / kF4Seg) {
-                const int o = xr * wt + (lane - kFuKx / kF4Seg) * kF4Seg;
-                *reinterpret_cast<float4*>(sh.w + o) = make_float4(wout[0], wout[1], wout[2], wout[3]);
-                *reinterpret_cast<float4*>(sh.r + o) = make_float4(rc[0], rc[1], rc[2], rc[3]);
+                // in float4 units (wt is a multiple of 8): one 16-byte LDS write per lane
+                const int o4 = xr * (wt / 4) + (lane - kFuKx / kF4Seg);
+                reinterpret_cast<float4*>(sh.w)[o4] = make_float4(wout[0], wout[1], wout[2], wout[3]);
+                reinterpret_cast<float4*>(sh.r)[o4] = make_float4(rc[0], rc[1], rc[2], rc[3]);
             }
         }
     }
@@ -262,7 +263,7 @@ __device__ __forceinline__ void fused4_tile(const FArgs& A, const int tile, FSha
             const int xr = xr0 + it;
             const int j = r0 - kFuKy + xr;
             if (xr >= kFuKy && xr < kFuKy + kFuHt && outlane) {
-                const float4 dv = *reinterpret_cast<const float4*>(sh.w + xr * wt + (lane - kFuKx / kF4Seg) * kF4Seg);
+                const float4 dv = reinterpret_cast<const float4*>(sh.w)[xr * (wt / 4) + (lane - kFuKx / kF4Seg)];
                 const f32x4 o = {fma_rn(2.f, keep_u[it][0], -keep_p[it][0]) + dv.x,
                                  fma_rn(2.f, keep_u[it][1], -keep_p[it][1]) + dv.y,
                                  fma_rn(2.f, keep_u[it][2], -keep_p[it][2]) + dv.z,
