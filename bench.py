@@ -178,6 +178,38 @@ def bench_batched(adw, torch, steps: int, warmup: int, plain_value: float):
             "vs_plain": round(value / plain_value, 4), "finite": finite}
 
 
+def bench_tridiag(adw, torch, n: int = 8192, batch: int = 8192, reps: int = 5):
+    """The ABI's batched general line solve on random strictly diagonally dominant FP32
+    systems: n unknowns, batch systems, contiguous (system after system) and interleaved
+    (unknown k of every system side by side).  Algorithmic bytes per unknown: a, b, c, d
+    read and d written (20 B)."""
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(7)
+    total = n * batch
+    a = torch.rand(total, device="cuda", generator=g) - 0.5
+    c = torch.rand(total, device="cuda", generator=g) - 0.5
+    b = a.abs() + c.abs() + 0.5
+    d0 = torch.rand(total, device="cuda", generator=g)
+    for layout, ss, es in (("contiguous", n, 1), ("interleaved", 1, batch)):
+        d = d0.clone()
+        adw.tridiag_solve_batched(a, b, c, d, n, batch, ss, es)      # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            adw.tridiag_solve_batched(a, b, c, d, n, batch, ss, es)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbps = 20 * total / (ms / 1e3) / 1e9
+        out[layout] = {"n": n, "batch": batch, "ms": round(ms, 4), "algorithmic_GBps": round(gbps, 1),
+                       "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
+                       "finite": bool(torch.isfinite(d).all().item())}
+    del a, b, c, d0
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_cr(adw, torch, prob, steps: int, plain_value: float):
     """The paper's line solver (cyclic reduction, one launch per level for all lines of
     a sweep) on the same workload, same GPU: a short timed run."""
@@ -269,6 +301,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cr", action="store_true", help="skip the cyclic-reduction baseline leg")
+    ap.add_argument("--no-tridiag", action="store_true", help="skip the batched line-solve leg")
     ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
 
@@ -428,6 +461,8 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(adw, torch, value)
         out["adjoint"]["vs_two_pass"] = round(out["adjoint"]["value"] / tp_value, 4)
+    if not args.no_tridiag:
+        out["tridiag"] = bench_tridiag(adw, torch)
     if not args.no_cr and dtype == "f32":
         out["cr_baseline"] = bench_cr(adw, torch, prob, 10, value)
     if not args.no_cpu:

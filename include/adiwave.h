@@ -277,8 +277,12 @@ adi_status adi_batch_destroy(adi_batch_t b);
  * the systems must be solvable by Gaussian elimination without pivoting
  * (e.g. strictly diagonally dominant), as the paper's line systems are.
  * Contiguous systems (elem_stride == 1, n <= 16384 / 8192 for f64) are solved
- * one per workgroup on chip; other layouts one per thread, with a library
- * workspace of batch*n values allocated on first use and kept.
+ * one per workgroup on chip.  Other layouts take a partition solve in three
+ * launches (chunks of 32 rows for f32, 16 for f64, eliminated onto their last
+ * row, the chunk-boundary system solved per system, then the chunks again),
+ * with a library workspace of 6*ceil(n/chunk)*batch values allocated on first
+ * use (or growth) and kept; a call that needs more synchronises the stream
+ * before it replaces the workspace, and ADI_ENOMEM if that allocation fails.
  * hip_stream: stream to queue on (NULL = default). */
 adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* a,
                                  const void* b, const void* c, void* d,

@@ -17,6 +17,7 @@
 #include "fused4.hpp"
 #include "fusedr.hpp"
 #include "cr.hpp"
+#include "tridiag_part.hpp"
 
 using namespace adw;
 
@@ -1060,11 +1061,11 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
         bool ok;
         if (dtype == ADI_F32) {
             TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
-                             sys_stride, elem_stride, vec, nullptr};
+                             sys_stride, elem_stride, vec};
             ok = launch_tri<float>(p, batch, t, st);
         } else {
             TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
-                              sys_stride, elem_stride, vec, nullptr};
+                              sys_stride, elem_stride, vec};
             ok = launch_tri<double>(p, batch, t, st);
         }
         if (!ok) return fail(ADI_EUNSUPPORTED, "no batched kernel for this size");
@@ -1073,7 +1074,8 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
     }
     int dev = 0;
     ADI_HIP(hipGetDevice(&dev));
-    const size_t need = (size_t)n * batch * es;
+    const size_t need = (dtype == ADI_F32 ? tri_part_workspace<float>(n, batch)
+                                          : tri_part_workspace<double>(n, batch)) * es;
     void* scr = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_scr_mu);
@@ -1092,17 +1094,16 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
         }
         scr = slot.first;
     }
-    const unsigned grid = (unsigned)((batch + 255) / 256);
     if (dtype == ADI_F32) {
         TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
-                         sys_stride, elem_stride, 0, (float*)scr};
-        hipLaunchKernelGGL((k_tridiag_thread<float>), dim3(grid), dim3(256), 0, st, t);
+                         sys_stride, elem_stride, 0};
+        launch_tri_part<float>(t, (float*)scr, st);
     } else {
         TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
-                          sys_stride, elem_stride, 0, (double*)scr};
-        hipLaunchKernelGGL((k_tridiag_thread<double>), dim3(grid), dim3(256), 0, st, t);
+                          sys_stride, elem_stride, 0};
+        launch_tri_part<double>(t, (double*)scr, st);
     }
-    ADI_LAUNCHED("tridiag_thread");
+    ADI_LAUNCHED("tridiag_part");
     return ADI_OK;
 }
 

@@ -381,7 +381,6 @@ struct TriArgs {
     int n, batch;
     long long sys_stride, elem_stride;
     int vec;
-    T* scratch;          // per-thread path: batch * n values
 };
 
 // One workgroup (TR threads) per contiguous system, nodes in registers.
@@ -409,40 +408,6 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_tridiag_wg(TriArgs<T> 
     for (int k = 0; k < S; ++k) if (k >= L) b[k] = T(1);
     partition_solve<T, S, TR>(d, CoefABC<T, S>{a, b, c}, L, t, nact, lds_all + g * partition_lds_slots<TR>(), 1);
     if (L > 0) store_seg<T, S>(A.d + off, L, vec, d);
-}
-
-// One thread per system, any strides (Thomas with a global scratch row).
-template <typename T>
-__global__ void __launch_bounds__(256) k_tridiag_thread(TriArgs<T> A)
-{
-    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (s >= A.batch) return;
-    const long long es = A.elem_stride;
-    const T* a = A.a + s * A.sys_stride;
-    const T* b = A.b + s * A.sys_stride;
-    const T* c = A.c + s * A.sys_stride;
-    T* d = A.d + s * A.sys_stride;
-    // scratch laid out [k][s] so that neighbouring threads touch neighbouring words
-    T* cp = A.scratch + s;
-    const long long cs = A.batch;
-    T m = T(1) / b[0];
-    T cpv = c[0] * m;
-    T dpv = d[0] * m;
-    cp[0] = cpv;
-    d[0] = dpv;
-    for (int k = 1; k < A.n; ++k) {
-        const T ak = a[k * es];
-        m = T(1) / (b[k * es] - ak * cpv);
-        cpv = c[k * es] * m;
-        dpv = (d[k * es] - ak * dpv) * m;
-        cp[k * cs] = cpv;
-        d[k * es] = dpv;
-    }
-    T x = dpv;
-    for (int k = A.n - 2; k >= 0; --k) {
-        x = d[k * es] - cp[k * cs] * x;
-        d[k * es] = x;
-    }
 }
 
 // ------------------------------------------------------------------- copy ----

@@ -74,11 +74,23 @@ def test_tridiag_contiguous(adw, oracle_lib, dtype, n, batch):
     assert np.array_equal(A.cpu().numpy(), a)        # coefficients untouched
 
 
+STRIDED = {  # layout: (n, batch, sys_stride, elem_stride)
+    "interleaved": (300, 257, 1, 257),
+    "padded": (77, 19, 3 * 77 + 5, 3),
+    "long": (20000, 3, 20000, 1),
+    "one_row_tail": (33, 65, 1, 65),      # FP32 chunks of 32: the last chunk is one row
+    "one_row_tail_f64": (17, 40, 1, 40),  # FP64 chunks of 16
+    "single_chunk": (5, 70, 1, 70),
+    "n1": (1, 9, 2, 1),
+    "n2": (2, 9, 1, 9),
+    "long_strided": (9001, 2, 1, 2),
+}
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("layout", ["interleaved", "padded", "long"])
+@pytest.mark.parametrize("layout", list(STRIDED))
 def test_tridiag_strided(adw, oracle_lib, dtype, layout):
-    n, batch = {"interleaved": (300, 257), "padded": (77, 19), "long": (20000, 3)}[layout]
-    ss, es = {"interleaved": (1, batch), "padded": (3 * n + 5, 3), "long": (n, 1)}[layout]
+    n, batch, ss, es = STRIDED[layout]
     say(f"tridiag {layout} {dtype} n={n} batch={batch}")
     size = (batch - 1) * ss + (n - 1) * es + 1
     rng = np.random.default_rng(5)
@@ -93,6 +105,33 @@ def test_tridiag_strided(adw, oracle_lib, dtype, layout):
     for s in range(batch):
         mask[s * ss + np.arange(n) * es] = False
     assert np.array_equal(got[mask], d[mask])        # gaps untouched
+
+
+def test_tridiag_interleaved_full_size(adw, oracle_lib):
+    """8192 interleaved FP32 systems of 8192 unknowns (the measured line-solve case):
+    sampled systems against the oracle, and the residual of all of them."""
+    n = batch = 8192
+    say(f"tridiag interleaved full size f32 n={n} batch={batch}")
+    g = torch.Generator(device="cuda").manual_seed(11)
+    A = torch.rand(n * batch, device="cuda", generator=g) - 0.5
+    C = torch.rand(n * batch, device="cuda", generator=g) - 0.5
+    B = A.abs() + C.abs() + 0.5
+    D0 = torch.rand(n * batch, device="cuda", generator=g)
+    D = D0.clone()
+    adw.tridiag_solve_batched(A, B, C, D, n, batch, 1, batch)
+    torch.cuda.synchronize()
+    a, b, c, d, x = (t.view(n, batch) for t in (A, B, C, D0, D))
+    res = b * x - d
+    res[1:] += a[1:] * x[:-1]
+    res[:-1] += c[:-1] * x[1:]
+    assert (res.norm() / d.norm()).item() <= 1e-6
+    cols = [0, 1, 63, 64, 4095, 8190, 8191]
+    sub = [t[:, cols].double().t().contiguous().cpu().numpy().ravel() for t in (a, b, c, d)]
+    ref = oracle_lib.tridiag_batched(*sub, n, len(cols), n, 1)
+    got = x[:, cols].double().t().contiguous().cpu().numpy().ravel()
+    assert rel_l2(got, ref) <= TOL_ONE["f32"]
+    del A, B, C, D0, D, a, b, c, d, x, res
+    torch.cuda.empty_cache()
 
 
 # ------------------------------------------------------------- one step ----
