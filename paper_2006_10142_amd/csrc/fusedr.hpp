@@ -6,8 +6,8 @@
 // output rows, and walks down it in bands of 24 x-rows; band k holds the x-rows
 // [r0 - 8 + 24k, r0 + 16 + 24k).
 //   x-role (8 wavefronts): three x-rows each per band, four nodes per lane, on
-//     the window [c0 - 8, c0 + Wt + 8) exactly as fused4.hpp; w and r of the
-//     central columns go to a ring of 56 rows in LDS.  The inputs of band k + 1
+//     the window [c0 - 8, c0 + Wt + 8) exactly as fused4.hpp; w, r and u^n of
+//     the central columns go to rings of 56 rows in LDS.  The inputs of band k + 1
 //     are in registers, and those of band k + 2 are requested as soon as band k
 //     is solved.
 //   y-role (4 wavefronts, one thread per column): in the same pass, band k - 1.
@@ -18,8 +18,9 @@
 //     cut, 9 rows below the band's last output row), runs up through the band
 //     and through the 8 look-ahead rows kept in the ring by the band before, and
 //     updates the output rows [r0 - 16 + 24k, r0 + 8 + 24k) (band 0: [r0, r0 + 8))
-//     as it goes: u^{n+1} = 2 u^n - u^{n-1} + d, whose operands were requested a
-//     pass ahead.  The band's last 8 rows (g and pivots) stay in the ring.
+//     as it goes: u^{n+1} = 2 u^n - u^{n-1} + d, with u^n from its ring (the
+//     x-role had it in registers) and u^{n-1} requested a pass ahead.  The
+//     band's last 8 rows (g, pivots and u^n) stay in the rings.
 // Each output row is the solution of a y-window whose cuts are at least 9 rows
 // away, and each x-row that of an x-window cut 9 columns away, so the truncation
 // bound of fused.hpp holds unchanged.  A barrier separates the passes: the
@@ -40,11 +41,14 @@ constexpr int kFrHmin = 256;               // shortest strip segment the plan pi
 struct FRShared {
     alignas(16) float w[kFrR * kFrS];   // w of the x-rows, then g once the y-role has eliminated them
     alignas(16) float r[kFrR * kFrS];   // r of the x-rows, then the y-lines' pivots
+    alignas(16) float u[kFrR * kFrS];   // u^n of the x-rows, read again by the update
     float src_add[kFuSrc];
     int src_row[kFuSrc];
     int src_wc[kFuSrc];
     int src_n;              // -1: more than kFuSrc in this strip
 };
+
+static_assert(sizeof(FRShared) <= 160 * 1024, "the strip ring exceeds the LDS of a workgroup");
 
 // x-role inputs of one band: u^n rows j-1 .. j+kFrXr and r rows j .. j+kFrXr-1
 // of the wavefront's x-rows, with the window-edge values and entry pivots
@@ -229,6 +233,7 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
                 const int o4 = slot(j) * (kFrS / 4) + (lane - kFuKx / kF4Seg);
                 reinterpret_cast<float4*>(sh.w)[o4] = make_float4(wout[0], wout[1], wout[2], wout[3]);
                 reinterpret_cast<float4*>(sh.r)[o4] = make_float4(rc[0], rc[1], rc[2], rc[3]);
+                reinterpret_cast<float4*>(sh.u)[o4] = make_float4(uc[0], uc[1], uc[2], uc[3]);
             }
         }
     };
@@ -236,10 +241,9 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
     // ---- y-role constants: column c0 + t of the strip (t < wt)
     const bool ycol = t < wt && c0 + t < nx;
     const int lim = (int)(npts * 4);
-    const rsrc_t ruc = buf(A.uc, lim);
     const rsrc_t rup = buf(static_cast<const float*>(A.up), lim);
     float gcar = 0.f, qcar = 0.f;                           // forward carries of the column
-    float cu[kFrB], pu[kFrB];                                // u^n, u^{n-1} of the next band's output rows
+    float pu[kFrB];                                          // u^{n-1} of the next band's output rows
     // the update operands and results of output row o of band b (row xb - 8 + o):
     // the column's byte offset in a VGPR (out of range for threads past the strip)
     // and the row's in the scalar offset; rows outside the band's output rows are
@@ -258,19 +262,18 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
 #pragma unroll
         for (int o = 0; o < kFrB; ++o) {
             const int so = srow(b, o);
-            cu[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ruc, vcol, so, kFuNT));
             pu[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rup, vcol, so, kFuNT));
         }
     };
-    // band b: its update operands (requested one pass earlier) are combined first,
-    // and band b+1's are requested at once, so they have a whole pass to arrive;
+    // band b: its u^{n-1} (requested one pass earlier) is taken first, and band
+    // b+1's is requested at once, so that it has a whole pass to arrive;
     // then the forward elimination over the band's rows (g and the pivots replace
     // w and r in the ring), and the back substitution with the update
     auto y_band = [&](int b) {
         const int xb = xr_lo + kFrB * b;
-        float base[kFrB];                                    // 2 u^n - u^{n-1} of the output rows
+        float base[kFrB];                                    // -u^{n-1} of the output rows
 #pragma unroll
-        for (int o = 0; o < kFrB; ++o) base[o] = fma_rn(2.f, cu[o], -pu[o]);
+        for (int o = 0; o < kFrB; ++o) base[o] = -pu[o];
         load_upd(b + 1);                                     // past the last band: out of range
         const int s0 = slot(xb);
         // ring slot s (< 2 kFrR) of this column; threads past the strip read a valid
@@ -306,11 +309,12 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
             // group c covers rows xb + 16 - 8c .. xb + 23 - 8c (c = 3: the look-ahead rows)
             const bool prev = c == kFrB / kG;
             const int sg = prev ? sl : s0 + kFrB - kG * (c + 1);
-            float gg[kG], qq[kG];
+            float gg[kG], qq[kG], uu[kG];
 #pragma unroll
             for (int e = 0; e < kG; ++e) {
                 gg[e] = sh.w[at(sg + e)];
                 qq[e] = sh.r[at(sg + e)];
+                uu[e] = sh.u[at(sg + e)];
                 if (prev && b == 0) { gg[e] = 0.f; qq[e] = 0.f; }
             }
             const int o0 = kFrB - kG * c;                       // output index of the group's first row
@@ -319,7 +323,7 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
                 d = fma_rn(qq[e], d, gg[e]);
                 const int o = o0 + e;                           // rows xb - 8 + o
                 if (o < kFrB && out_row(b, o)) {
-                    const float v = base[o] + d;
+                    const float v = fma_rn(2.f, uu[e], base[o]) + d;
                     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), rup, vcol, srow(b, o), kFuNT);
                 }
             }
