@@ -5,7 +5,7 @@
 // A workgroup owns a strip of Wt output columns (a multiple of 8, <= 240) and hs
 // output rows, and walks down it in bands of 24 x-rows; band k holds the x-rows
 // [r0 - 8 + 24k, r0 + 16 + 24k).
-//   x-role (8 wavefronts): three x-rows each per band, four nodes per lane, on
+//   x-role (12 wavefronts): two x-rows each per band, four nodes per lane, on
 //     the window [c0 - 8, c0 + Wt + 8) exactly as fused4.hpp; w, r and u^n of
 //     the central columns go to rings of 56 rows in LDS.  The inputs of band k + 1
 //     are in registers, and those of band k + 2 are requested as soon as band k
@@ -32,9 +32,10 @@ namespace adw {
 constexpr int kFrB = 24;                   // x-rows per band
 constexpr int kFrR = 2 * kFrB + kFuKy;     // ring rows (56)
 constexpr int kFrY = 4;                    // y-role wavefronts (one thread per column)
-constexpr int kFrX = 8;                    // x-role wavefronts
-constexpr int kFrXr = kFrB / kFrX;         // x-rows per x-role wavefront per band (3)
-constexpr int kFrThreads = 64 * (kFrY + kFrX);   // workgroup size (768: 168 VGPRs a thread)
+constexpr int kFrX = 12;                   // x-role wavefronts (8, with three x-rows each, measured slower)
+constexpr int kFrXr = kFrB / kFrX;         // x-rows per x-role wavefront per band (2)
+constexpr int kFrThreads = 64 * (kFrY + kFrX);   // workgroup size (1024: at most 128 VGPRs a thread)
+static_assert(kFrB % kFrX == 0, "every x-role wavefront takes the same number of x-rows");
 constexpr int kFrS = kF4Wmax;              // ring row stride (240)
 constexpr int kFrHmin = 256;               // shortest strip segment the plan picks by itself
 
