@@ -18,7 +18,8 @@
 // dominant, so plain elimination stays safe on it as on the full system.
 //
 //   k_tri_part_reduce   one thread per (system, chunk): interior elimination,
-//                       keeps (y, v, w) at the first and last interior rows;
+//                       then the interface equations' coefficients from the
+//                       (y, v, w) at the first and last interior rows;
 //   k_tri_part_iface    one thread per system: forms and solves the interface
 //                       system, writes X_p into d and into the workspace;
 //   k_tri_part_expand   one thread per (system, chunk): the interior again with
@@ -27,7 +28,7 @@
 // triple is (0, 0, -1) (that row is X_p itself) and its last-row triple
 // (0, -1, 0) (the row before it is X_{p-1}).  Neighbouring threads take
 // neighbouring systems, so interleaved systems (sys_stride 1) load whole lines.
-// Workspace: 6 values per (chunk, system), slot q of (p, s) at (q P + p) batch + s.
+// Workspace: 6 values per (chunk, system), slot q of record (p, s) at (q P + p) batch + s.
 
 namespace adw {
 
@@ -56,6 +57,15 @@ __device__ __forceinline__ int tp_load(const TriArgs<T>& A, long long s, int p, 
     return li;
 }
 
+// The interface row of chunk p is r = min(n, (p+1) M) - 1.  With primes for chunk
+// p+1's first-row triple, its equation in X_{p-1}, X_p, X_{p+1} is
+//   (-a_r v_l) X_{p-1} + (b_r - a_r w_l - c_r v'_f) X_p + (-c_r w'_f) X_{p+1}
+//       = d_r - a_r y_l - c_r y'_f,
+// with a_r = 0 for r = 0 and c_r = 0 on the last chunk.  The reduce launch writes
+// it pre-combined, so that the serial solve reads six coalesced values a row:
+// the thread of chunk p writes slots 0..2 of record p (-a_r v_l, b_r - a_r w_l,
+// d_r - a_r y_l); the thread of chunk p+1 writes slots 3..5 of record p
+// (c_r v'_f, -c_r w'_f, c_r y'_f), and the last chunk zeros its own.
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_tri_part_reduce(TriArgs<T> A, int P, T* __restrict__ red)
 {
@@ -67,6 +77,14 @@ __global__ void __launch_bounds__(256) k_tri_part_reduce(TriArgs<T> A, int P, T*
     T ca[M - 1], cb[M - 1], cc[M - 1], cd[M - 1];
     long long base;
     const int li = tp_load<T, M>(A, s, p, ca, cb, cc, cd, base);
+    // the chunk's interface row, and c of the row before the chunk
+    const long long es = A.elem_stride;
+    const int r = p * M + li;
+    const long long orow = s * A.sys_stride + (long long)r * es;
+    const T ar = r > 0 ? A.a[orow] : T(0);
+    const T br = A.b[orow];
+    const T dr = A.d[orow];
+    const T cprv = p > 0 ? A.c[orow - (long long)(li + 1) * es] : T(0);
     T yf = T(0), vf = T(0), wf = T(-1), yl = T(0), vl = T(-1), wl = T(0);
     if (li > 0) {
         // forward elimination of the interior; c' over c, d' over d, v' over a
@@ -104,51 +122,40 @@ __global__ void __launch_bounds__(256) k_tri_part_reduce(TriArgs<T> A, int P, T*
     }
     const long long q = (long long)P * nb;
     T* o = red + (long long)p * nb + s;
-    o[0] = yf;
-    o[q] = vf;
-    o[2 * q] = wf;
-    o[3 * q] = yl;
-    o[4 * q] = vl;
-    o[5 * q] = wl;
-}
-
-// Interface row of chunk p: r = min(n, (p+1) M) - 1.  With primes for chunk p+1's
-// first-row triple, its equation in X_{p-1}, X_p, X_{p+1} is
-//   (-a_r v_l) X_{p-1} + (b_r - a_r w_l - c_r v'_f) X_p + (-c_r w'_f) X_{p+1}
-//       = d_r - a_r y_l - c_r y'_f,
-// with a_r = 0 for r = 0 and c_r = 0 on the last chunk.  Forward values go over
-// slots 3 and 4 of chunk p (read only at step p), the solution into slot 5.
-template <typename T>
-struct TpRow { T a, b, c, d, yl, vl, wl, yf, vf, wf; };
-
-template <typename T>
-__device__ __forceinline__ TpRow<T> tp_row(const TriArgs<T>& A, const T* red, long long s, int p, int P, int M,
-                                           long long q)
-{
-    TpRow<T> t;
-    const long long nb = A.batch;
-    const int r = min(A.n, (p + 1) * M) - 1;
-    const long long o = s * A.sys_stride + (long long)r * A.elem_stride;
-    const bool more = p + 1 < P;
-    t.a = r > 0 ? A.a[o] : T(0);
-    t.b = A.b[o];
-    t.c = more ? A.c[o] : T(0);
-    t.d = A.d[o];
-    const T* g = red + (long long)p * nb + s;
-    t.yl = g[3 * q];
-    t.vl = g[4 * q];
-    t.wl = g[5 * q];
-    t.yf = more ? g[nb] : T(0);
-    t.vf = more ? g[nb + q] : T(0);
-    t.wf = more ? g[nb + 2 * q] : T(0);
-    return t;
+    o[0] = -ar * vl;
+    o[q] = br - ar * wl;
+    o[2 * q] = dr - ar * yl;
+    if (p > 0) {
+        T* g = o - nb;                                       // record p - 1
+        g[3 * q] = cprv * vf;
+        g[4 * q] = -cprv * wf;
+        g[5 * q] = cprv * yf;
+    }
+    if (p == P - 1) {
+        o[3 * q] = T(0);
+        o[4 * q] = T(0);
+        o[5 * q] = T(0);
+    }
 }
 
 // The recurrence is serial in p, but its loads are not: rows are fetched kTpAhead
 // ahead into a register ring (static indices after unrolling), so that many
-// loads of one thread are in flight at once.
+// loads of one thread are in flight at once.  Forward values go over slots 0 and 1
+// of record p (read only at step p), the solution X_p into slot 2 and into d.
 constexpr int kTpAhead = 4;         // 8 ahead, or 64-thread workgroups, measured slower
 constexpr int kTpIfaceThreads = 256;
+
+// the six raw values of a record; they are combined only where they are used, so
+// that a prefetch does not wait for its own loads
+template <typename T>
+struct TpRow { T a, b, d, bc, c, dc; };
+
+template <typename T>
+__device__ __forceinline__ TpRow<T> tp_row(const T* red, long long s, int p, long long nb, long long q)
+{
+    const T* g = red + (long long)p * nb + s;
+    return TpRow<T>{g[0], g[q], g[2 * q], g[3 * q], g[4 * q], g[5 * q]};
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kTpIfaceThreads) k_tri_part_iface(TriArgs<T> A, int P, int M, T* __restrict__ red)
@@ -161,24 +168,20 @@ __global__ void __launch_bounds__(kTpIfaceThreads) k_tri_part_iface(TriArgs<T> A
     TpRow<T> ring[kTpAhead];
 #pragma unroll
     for (int j = 0; j < kTpAhead; ++j)
-        if (j < P) ring[j] = tp_row<T>(A, red, s, j, P, M, q);
+        if (j < P) ring[j] = tp_row<T>(red, s, j, nb, q);
     for (int p0 = 0; p0 < P; p0 += kTpAhead) {
 #pragma unroll
         for (int j = 0; j < kTpAhead; ++j) {
             const int p = p0 + j;
             if (p < P) {
                 const TpRow<T> t = ring[j];
-                if (p + kTpAhead < P) ring[j] = tp_row<T>(A, red, s, p + kTpAhead, P, M, q);
-                const T ap = -t.a * t.vl;
-                const T bp = t.b - t.a * t.wl - t.c * t.vf;
-                const T cp = -t.c * t.wf;
-                const T dp = t.d - t.a * t.yl - t.c * t.yf;
-                const T m = T(1) / (bp - ap * cprev);
-                cprev = cp * m;
-                dprev = (dp - ap * dprev) * m;
+                if (p + kTpAhead < P) ring[j] = tp_row<T>(red, s, p + kTpAhead, nb, q);
+                const T m = T(1) / ((t.b - t.bc) - t.a * cprev);
+                cprev = t.c * m;
+                dprev = ((t.d - t.dc) - t.a * dprev) * m;
                 T* g = red + (long long)p * nb + s;
-                g[3 * q] = cprev;
-                g[4 * q] = dprev;
+                g[0] = cprev;
+                g[q] = dprev;
             }
         }
     }
@@ -190,13 +193,13 @@ __global__ void __launch_bounds__(kTpIfaceThreads) k_tri_part_iface(TriArgs<T> A
         const int p = P - 2 - j;
         if (p >= 0) {
             const T* g = red + (long long)p * nb + s;
-            rc[j] = g[3 * q];
-            rd[j] = g[4 * q];
+            rc[j] = g[0];
+            rd[j] = g[q];
         }
     }
     {
         T* g = red + (long long)(P - 1) * nb + s;
-        g[5 * q] = x;
+        g[2 * q] = x;
         A.d[s * A.sys_stride + (long long)(A.n - 1) * A.elem_stride] = x;
     }
     for (int p0 = P - 2; p0 >= 0; p0 -= kTpAhead) {
@@ -208,11 +211,11 @@ __global__ void __launch_bounds__(kTpIfaceThreads) k_tri_part_iface(TriArgs<T> A
                 const int pn = p - kTpAhead;
                 if (pn >= 0) {
                     const T* gn = red + (long long)pn * nb + s;
-                    rc[j] = gn[3 * q];
-                    rd[j] = gn[4 * q];
+                    rc[j] = gn[0];
+                    rd[j] = gn[q];
                 }
                 T* g = red + (long long)p * nb + s;
-                g[5 * q] = x;
+                g[2 * q] = x;
                 const int r = (p + 1) * M - 1;
                 A.d[s * A.sys_stride + (long long)r * A.elem_stride] = x;
             }
@@ -229,9 +232,9 @@ __global__ void __launch_bounds__(256) k_tri_part_expand(TriArgs<T> A, int P, co
     const int p = (int)(gid / nb);
     const long long s = gid - (long long)p * nb;
     if (min(A.n, p * M + M) - p * M <= 1) return;          // no interior
-    const long long q5 = 5 * (long long)P * nb;
-    const T xl = p > 0 ? red[q5 + (long long)(p - 1) * nb + s] : T(0);
-    const T xh = red[q5 + (long long)p * nb + s];
+    const long long q2 = 2 * (long long)P * nb;          // slot 2: X of each chunk
+    const T xl = p > 0 ? red[q2 + (long long)(p - 1) * nb + s] : T(0);
+    const T xh = red[q2 + (long long)p * nb + s];
     T ca[M - 1], cb[M - 1], cc[M - 1], cd[M - 1];
     long long base;
     const int li = tp_load<T, M>(A, s, p, ca, cb, cc, cd, base);
