@@ -259,11 +259,22 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
         const int j = xr_lo + kFrB * b - kFuKy + o;
         return (j < 0 ? 0 : j >= ny ? ny - 1 : j) * rowb;
     };
+    // a band whose 24 output rows all lie inside the segment (most of them) takes a
+    // path with no per-row bound tests or clamps; both paths issue the same loads
+    auto band_full = [&](int b) {
+        const int j0 = xr_lo + kFrB * b - kFuKy;
+        return j0 >= r0 && j0 + kFrB <= r1;
+    };
     auto load_upd = [&](int b) {
+        if (band_full(b)) {
+            const int so0 = (xr_lo + kFrB * b - kFuKy) * rowb;
 #pragma unroll
-        for (int o = 0; o < kFrB; ++o) {
-            const int so = srow(b, o);
-            pu[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rup, vcol, so, kFuNT));
+            for (int o = 0; o < kFrB; ++o)
+                pu[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rup, vcol, so0 + o * rowb, kFuNT));
+        } else {
+#pragma unroll
+            for (int o = 0; o < kFrB; ++o)
+                pu[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rup, vcol, srow(b, o), kFuNT));
         }
     };
     // band b: its u^{n-1} (requested one pass earlier) is taken first, and band
@@ -304,31 +315,38 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
         // of the band before (rows xb - 8 .. xb - 1; band 0 has none: zeros, and its
         // rows there are above the strip, so nothing is stored for them)
         const int sl = slot(xb + kFrR - kFuKy);                // = slot(xb - 8)
-        float d = 0.f;
+        const int so0 = (xb - kFuKy) * rowb;
+        auto back = [&](auto full_c) {
+            constexpr bool kFull = decltype(full_c)::value;
+            float d = 0.f;
 #pragma unroll
-        for (int c = 0; c < (kFrB + kFuKy) / kG; ++c) {
-            // group c covers rows xb + 16 - 8c .. xb + 23 - 8c (c = 3: the look-ahead rows)
-            const bool prev = c == kFrB / kG;
-            const int sg = prev ? sl : s0 + kFrB - kG * (c + 1);
-            float gg[kG], qq[kG], uu[kG];
+            for (int c = 0; c < (kFrB + kFuKy) / kG; ++c) {
+                // group c covers rows xb + 16 - 8c .. xb + 23 - 8c (c = 3: the look-ahead rows)
+                const bool prev = c == kFrB / kG;
+                const int sg = prev ? sl : s0 + kFrB - kG * (c + 1);
+                float gg[kG], qq[kG], uu[kG];
 #pragma unroll
-            for (int e = 0; e < kG; ++e) {
-                gg[e] = sh.w[at(sg + e)];
-                qq[e] = sh.r[at(sg + e)];
-                uu[e] = sh.u[at(sg + e)];
-                if (prev && b == 0) { gg[e] = 0.f; qq[e] = 0.f; }
-            }
-            const int o0 = kFrB - kG * c;                       // output index of the group's first row
+                for (int e = 0; e < kG; ++e) {
+                    gg[e] = sh.w[at(sg + e)];
+                    qq[e] = sh.r[at(sg + e)];
+                    uu[e] = sh.u[at(sg + e)];
+                    if (prev && b == 0) { gg[e] = 0.f; qq[e] = 0.f; }
+                }
+                const int o0 = kFrB - kG * c;                       // output index of the group's first row
 #pragma unroll
-            for (int e = kG - 1; e >= 0; --e) {
-                d = fma_rn(qq[e], d, gg[e]);
-                const int o = o0 + e;                           // rows xb - 8 + o
-                if (o < kFrB && out_row(b, o)) {
-                    const float v = fma_rn(2.f, uu[e], base[o]) + d;
-                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), rup, vcol, srow(b, o), kFuNT);
+                for (int e = kG - 1; e >= 0; --e) {
+                    d = fma_rn(qq[e], d, gg[e]);
+                    const int o = o0 + e;                           // rows xb - 8 + o
+                    if (o < kFrB && (kFull || out_row(b, o))) {
+                        const float v = fma_rn(2.f, uu[e], base[o]) + d;
+                        const int so = kFull ? so0 + o * rowb : srow(b, o);
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), rup, vcol, so, kFuNT);
+                    }
                 }
             }
-        }
+        };
+        if (band_full(b)) back(std::true_type{});
+        else back(std::false_type{});
     };
 
     // pass k: the x-role solves band k, the y-role band k - 1.  The two roles run
