@@ -364,3 +364,75 @@ def test_adjoint_dot_product_identity(oracle_lib):
     lhs = float(np.sum(Ff * d))
     rhs = float(np.sum(amp * Ftd))
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300)
+
+
+# ------------------------------------------------------- start with sources ----
+def _start_case(seed=21, nx=7, ny=5):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / 8.0
+    dt = 0.9 * h
+    kappa = rng.uniform(1.0, 9.0, (ny, nx))
+    u0 = rng.standard_normal((ny, nx))
+    psi = rng.standard_normal((ny, nx))
+    src_idx = np.array([2 * nx + 3, 4 * nx + 0], np.int32)
+    amp0 = np.array([40.0, -25.0])
+    return h, dt, kappa, u0, psi, src_idx, amp0
+
+
+def test_ghost_start_with_velocity_and_sources_dense(oracle_lib):
+    """Ghost start with psi != 0 and two level-0 sources on a heterogeneous 7x5 grid.
+
+    Two dense routes, neither reusing the oracle's formulas:
+      (1) u^1 = u^0 + dt psi + e, (I - beta K Lxx)(I - beta K Lyy) e = (dt^2/2)(K Lap u^0 + f^0);
+      (2) the defining property: one step of the scheme at n = 0 from the ghost level
+          u^{-1} = u^1 - 2 dt psi and u^0 reproduces u^1 (eq. (CN1) factored as in
+          eqs. (fr1)-(fr2), with the source of level 0 in the right-hand side)."""
+    h, dt, kappa, u0, psi, si, amp0 = _start_case()
+    ny, nx = u0.shape
+    Lx, Ly = dense_ops(nx, ny, h)
+    K = np.diag(kappa.ravel())
+    beta = 0.5 * dt * dt
+    I = np.eye(nx * ny)
+    M = (I - beta * K @ Lx) @ (I - beta * K @ Ly)
+    f0 = np.zeros(nx * ny)
+    f0[si] = amp0
+    e = np.linalg.solve(M, 0.5 * dt * dt * (K @ (Lx + Ly) @ u0.ravel() + f0))
+    ref = u0.ravel() + dt * psi.ravel() + e
+    got = oracle_lib.start(kappa, u0, h, dt, psi=psi, mode="ghost", src_idx=si, src_amp0=amp0)
+    assert rel_l2(got.ravel(), ref) < 1e-13
+    assert np.max(np.abs(got.ravel() - ref)) < 1e-13 * np.max(np.abs(ref))
+    # (2): the step from (u^{-1}, u^0) with f^0 lands on u^1 again
+    ghost = got.ravel() - 2 * dt * psi.ravel()
+    again = 2 * u0.ravel() - ghost + np.linalg.solve(M, dt * dt * (K @ (Lx + Ly) @ u0.ravel() + f0))
+    assert rel_l2(again, got.ravel()) < 1e-13
+    # the sources matter at the size of the signal: halving only the stencil part, or
+    # dropping f^0, moves u^1 far above rounding
+    e_slip = np.linalg.solve(M, dt * dt * (0.5 * K @ (Lx + Ly) @ u0.ravel() + f0))
+    assert rel_l2(u0.ravel() + dt * psi.ravel() + e_slip, ref) > 1e-3
+    e_nof = np.linalg.solve(M, 0.5 * dt * dt * (K @ (Lx + Ly) @ u0.ravel()))
+    assert rel_l2(u0.ravel() + dt * psi.ravel() + e_nof, ref) > 1e-3
+
+
+def test_ghost_start_source_only_dense(oracle_lib):
+    """u^0 = 0, psi = 0: the ghost start is (dt^2/2) M^{-1} f^0, the response to the
+    level-0 sources alone (per-cell kappa, sources at an interior node and a wall node)."""
+    h, dt, kappa, u0, _, si, amp0 = _start_case(seed=22)
+    ny, nx = u0.shape
+    Lx, Ly = dense_ops(nx, ny, h)
+    K = np.diag(kappa.ravel())
+    beta = 0.5 * dt * dt
+    I = np.eye(nx * ny)
+    M = (I - beta * K @ Lx) @ (I - beta * K @ Ly)
+    f0 = np.zeros(nx * ny)
+    f0[si] = amp0
+    ref = np.linalg.solve(M, 0.5 * dt * dt * f0)
+    got = oracle_lib.start(kappa, np.zeros((ny, nx)), h, dt, mode="ghost", src_idx=si, src_amp0=amp0)
+    assert rel_l2(got.ravel(), ref) < 1e-13
+    assert np.max(np.abs(got.ravel() - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_paper_start_ignores_level0_sources(oracle_lib):
+    """Eq. (CN2) uses only u^0 and psi: u^1 = u^0 + dt psi, whatever f^0 is."""
+    h, dt, kappa, u0, psi, si, amp0 = _start_case(seed=23)
+    got = oracle_lib.start(kappa, u0, h, dt, psi=psi, mode="paper", src_idx=si, src_amp0=amp0)
+    assert np.array_equal(got, u0 + dt * psi)
