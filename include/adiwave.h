@@ -142,19 +142,27 @@ adi_status adi_wave_destroy(adi_wave_t w);
 /* Forward run of nsteps steps from (u_prev, u_curr) (not modified) with
  * sources and receivers exactly as adi_wave_step, keeping the level pair every
  * checkpoint_every steps in handle-owned device memory (allocated here on
- * first use or growth: 2 * ceil(nsteps / checkpoint_every) + 6 fields). */
+ * first use or growth: 2 * ceil(nsteps / checkpoint_every) + 6 fields).
+ * The handle keeps ONE forward record: this call replaces the previous one,
+ * and a coefficient change (adi_wave_set_kappa, adi_wave_step_tdc) discards it.
+ * record (may be NULL) receives the id of the new record (never 0). */
 adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_curr,
                                const adi_source* f, const adi_receivers* rec, int nsteps,
-                               int checkpoint_every);
+                               int checkpoint_every, unsigned long long* record);
 
-/* Reverse pass of the last adi_adjoint_forward (same f and rec).
+/* Reverse pass of the stored forward record (same f and rec as that run).
+ * record: the id adi_adjoint_forward returned, or 0 for whatever record is
+ * stored; ADI_EINVAL when no record is stored, when the coefficient changed
+ * since the forward run, or when record names a run that a later forward run
+ * replaced (nothing is written then).
  * grad_traces: device, nsteps x rec->count values of dJ/d(trace).
  * grad_kappa: device nx*ny, overwritten with dJ/dkappa.
  * grad_amp: device nsteps x f->count, overwritten with dJ/d(source value),
  * or NULL.  Each segment between checkpoints is recomputed once (allocates
  * 2 * checkpoint_every fields on first use or growth). */
-adi_status adi_adjoint_backward(adi_wave_t w, const adi_source* f, const adi_receivers* rec,
-                                const void* grad_traces, void* grad_kappa, void* grad_amp);
+adi_status adi_adjoint_backward(adi_wave_t w, unsigned long long record, const adi_source* f,
+                                const adi_receivers* rec, const void* grad_traces,
+                                void* grad_kappa, void* grad_amp);
 
 /* One step of eq. (CN1) with a coefficient that changes in time (Sec. 2: the
  * c^{k+1} and c^{k-1} of the scheme).  kappa_prev multiplies the Laplacian of

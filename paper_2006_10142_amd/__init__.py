@@ -255,15 +255,19 @@ class Wave:
         nrec = 0 if rec_idx is None else rec_idx.numel()
         traces = torch.zeros((nsteps, nrec), dtype=self.dtype, device=u_curr.device)
         rec = self._receivers(rec_idx, traces, nsteps)
+        rid = ctypes.c_ulonglong(0)
         _lib.check(_lib.load().adi_adjoint_forward(self._h, a, b, ctypes.byref(src) if src else None,
                                                    ctypes.byref(rec) if rec else None, int(nsteps),
-                                                   int(checkpoint_every)))
+                                                   int(checkpoint_every), ctypes.byref(rid)))
         self._adj_steps = int(nsteps)
+        self.adjoint_record = int(rid.value)
         return traces
 
     def adjoint_backward(self, grad_traces, src_idx=None, src_amp=None, rec_idx=None,
-                         want_amp: bool = False):
-        """Reverse pass of the last adjoint_forward: returns (dJ/dkappa, dJ/d source values or None)."""
+                         want_amp: bool = False, record: int = 0):
+        """Reverse pass of the stored forward run: returns (dJ/dkappa, dJ/d source values or None).
+        record: the id adjoint_forward left in self.adjoint_record (0: the stored run);
+        raises AdiError when that run was replaced or the coefficient changed since."""
         torch = _torch()
         self._sync_stream()
         nsteps = self._adj_steps
@@ -275,7 +279,8 @@ class Wave:
         if want_amp and src is not None:
             ga = torch.zeros((nsteps, src_idx.numel()), dtype=self.dtype, device=gt.device)
         _lib.check(_lib.load().adi_adjoint_backward(
-            self._h, ctypes.byref(src) if src else None, ctypes.byref(rec) if rec else None,
+            self._h, ctypes.c_ulonglong(int(record)), ctypes.byref(src) if src else None,
+            ctypes.byref(rec) if rec else None,
             ctypes.c_void_p(gt.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
             None if ga is None else ctypes.c_void_p(ga.data_ptr())))
         return gk, ga
@@ -459,7 +464,9 @@ class ADIWaveFunction:
     Forward: set the handle's coefficient to kappa, run nsteps steps with
     checkpoints, return the receiver traces (nsteps, nrec).  Backward: the
     adjoint reverse pass gives dJ/dkappa (and dJ/d src_amp).  One forward per
-    handle may be pending a backward at a time.
+    handle may be pending a backward at a time: a second forward on the same
+    handle (or a coefficient change) before the first backward makes that
+    backward raise AdiError instead of returning another run's gradient.
     """
     _fn = None
 
@@ -481,6 +488,7 @@ class ADIWaveFunction:
                     tr = wave.adjoint_forward(u_prev, u_curr, nsteps, src_idx=src_idx, src_amp=amp,
                                               rec_idx=rec_idx, checkpoint_every=checkpoint_every)
                     ctx.wave, ctx.src_idx, ctx.rec_idx, ctx.amp = wave, src_idx, rec_idx, amp
+                    ctx.record = wave.adjoint_record
                     return tr
 
                 @staticmethod
@@ -488,7 +496,7 @@ class ADIWaveFunction:
                     want_amp = ctx.amp is not None and ctx.needs_input_grad[1]
                     gk, ga = ctx.wave.adjoint_backward(grad_traces, src_idx=ctx.src_idx,
                                                        src_amp=ctx.amp, rec_idx=ctx.rec_idx,
-                                                       want_amp=want_amp)
+                                                       want_amp=want_amp, record=ctx.record)
                     return gk, ga, None, None, None, None, None, None, None
 
             cls._fn = _F

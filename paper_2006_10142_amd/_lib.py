@@ -95,9 +95,9 @@ _SIGNATURES = {
     "adi_batch_autotune": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
     "adi_batch_destroy": [_vp],
     "adi_adjoint_forward": [_vp, _vp, _vp, ctypes.POINTER(AdiSource), ctypes.POINTER(AdiReceivers),
-                            ctypes.c_int, ctypes.c_int],
-    "adi_adjoint_backward": [_vp, ctypes.POINTER(AdiSource), ctypes.POINTER(AdiReceivers), _vp, _vp,
-                             _vp],
+                            ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_ulonglong)],
+    "adi_adjoint_backward": [_vp, ctypes.c_ulonglong, ctypes.POINTER(AdiSource),
+                             ctypes.POINTER(AdiReceivers), _vp, _vp, _vp],
 }
 
 _lib = None

@@ -238,6 +238,9 @@ struct adi_wave_s {
     YScanPlan yq{};
     size_t bytes = 0;
     adi_adjoint_s* adj = nullptr;   // created by the first adjoint forward run
+    // bumped by every coefficient change and every adjoint forward run: the
+    // forward run's record id, which a later change invalidates
+    unsigned long long gen = 0;
     // one-pass step (FP32): allowed when the truncation bound holds for the
     // largest r; mode 0 = automatic, 1 = on when allowed, 2 = off
     float rmax = 0.f;
@@ -550,9 +553,13 @@ adi_status measure_rmax(adi_wave_s* w)
     return ADI_OK;
 }
 
+void adjoint_invalidate(adi_wave_s* w);   // adjoint.hpp
+
 template <typename T>
 adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared, bool measure = true)
 {
+    ++w->gen;
+    adjoint_invalidate(w);   // a stored forward record no longer matches the coefficient
     const long long n = (long long)w->nx * w->ny;
     const double s = w->dt * w->dt / (2.0 * w->h * w->h);
     const int grid = (int)std::min<long long>((n + 255) / 256, 65536);

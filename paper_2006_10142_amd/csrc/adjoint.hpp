@@ -151,6 +151,7 @@ __global__ void __launch_bounds__(256) k_adjoint_points(T* __restrict__ lam, con
 
 struct adi_adjoint_s {
     int nsteps = 0, K = 0, ncheck = 0;
+    unsigned long long record = 0;   // id of the stored forward run (0: none, or invalidated)
     size_t field = 0;            // bytes of one field
     void* ck = nullptr;          // 2 * ncheck fields: (u^{k0-1}, u^{k0}) of every segment
     void* seg = nullptr;         // 2 * K fields: levels u^{k0+1..k0+K}, then w^{k0..k0+K-1}
@@ -160,6 +161,16 @@ struct adi_adjoint_s {
 };
 
 namespace {
+
+// A coefficient change makes the stored forward run (checkpoints of the old
+// trajectory) unusable for a reverse pass.
+void adjoint_invalidate(adi_wave_s* w)
+{
+    if (w->adj) {
+        w->adj->record = 0;
+        w->adj->nsteps = 0;
+    }
+}
 
 void adjoint_free(adi_adjoint_s* a)
 {
@@ -372,8 +383,10 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
 extern "C" {
 
 adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_curr, const adi_source* f,
-                               const adi_receivers* rec, int nsteps, int checkpoint_every)
+                               const adi_receivers* rec, int nsteps, int checkpoint_every,
+                               unsigned long long* record)
 {
+    if (record) *record = 0;
     if (adi_status s = check_handle(w)) return s;
     if (!u_prev || !u_curr) return fail(ADI_EINVAL, "null level pointer");
     if (nsteps < 1) return fail(ADI_EINVAL, "nsteps must be >= 1");
@@ -382,18 +395,30 @@ adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_c
     if (adi_status s = check_rec(rec)) return s;
     if (!w->adj) w->adj = new adi_adjoint_s();
     w->adj->nsteps = 0;
+    w->adj->record = 0;
     adi_status s = w->dtype == ADI_F32
                        ? adj_forward<float>(w, u_prev, u_curr, f, rec, nsteps, checkpoint_every)
                        : adj_forward<double>(w, u_prev, u_curr, f, rec, nsteps, checkpoint_every);
-    if (s != ADI_OK) w->adj->nsteps = 0;
-    return s;
+    if (s != ADI_OK) {
+        w->adj->nsteps = 0;
+        return s;
+    }
+    w->adj->record = ++w->gen;
+    if (record) *record = w->adj->record;
+    return ADI_OK;
 }
 
-adi_status adi_adjoint_backward(adi_wave_t w, const adi_source* f, const adi_receivers* rec,
-                                const void* grad_traces, void* grad_kappa, void* grad_amp)
+adi_status adi_adjoint_backward(adi_wave_t w, unsigned long long record, const adi_source* f,
+                                const adi_receivers* rec, const void* grad_traces, void* grad_kappa,
+                                void* grad_amp)
 {
     if (adi_status s = check_handle(w)) return s;
-    if (!w->adj || w->adj->nsteps < 1) return fail(ADI_EINVAL, "run adi_adjoint_forward first");
+    if (!w->adj || w->adj->record == 0 || w->adj->nsteps < 1)
+        return fail(ADI_EINVAL, "no forward record: run adi_adjoint_forward first (a coefficient "
+                                "change discards the stored forward run)");
+    if (record != 0 && record != w->adj->record)
+        return fail(ADI_EINVAL, "the forward record was replaced by a later adi_adjoint_forward "
+                                "on this handle");
     if (!grad_kappa) return fail(ADI_EINVAL, "grad_kappa is null");
     if (adi_status s = check_src(f)) return s;
     if (adi_status s = check_rec(rec)) return s;

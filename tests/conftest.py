@@ -27,3 +27,11 @@ def oracle_lib():
     import oracle
     oracle.build()
     return oracle
+
+
+def max_rel(a, b) -> float:
+    """max |a - b| / max |b| (the max-norm error relative to the field's size), in FP64."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.max(np.abs(b)) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (nb if nb > 0 else 1.0)) if b.size else 0.0

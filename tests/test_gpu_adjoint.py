@@ -1,15 +1,21 @@
 """Adjoint (reverse-time) gradients on the GPU against the FP64 oracle's adjoint,
 finite differences of the GPU forward, the dot-product identity, checkpoint
-invariance and the autograd Function.
+invariance, the forward-record checks and the autograd Function.
 
-Tolerances: FP64 gradients <= 1e-10 relative L2 against the oracle; FP32
-gradients <= 2e-3 (the adjoint wave accumulates FP32 rounding like the forward
-run, and the loss is quadratic in traces that carry it)."""
+Tolerances (relative L2 against the oracle's adjoint, computed in FP64):
+  FP64 gradients <= 1e-12, FP32 gradients <= 1e-5 (the run's bars).
+Each FP32 case also reports the drift of a correctly rounded FP32 transcription
+of the same recurrences (tests/drift_gauge.py) against the same oracle; the GPU
+error is asserted to stay within 4x that inherent drift as well."""
 import numpy as np
 import pytest
 
+from tests import drift_gauge
 from tests.conftest import rel_l2
 from paper_2006_10142_amd import workloads as wl
+
+TOL_GRAD = {"f64": 1e-12, "f32": 1e-5}
+TOL_TRACE = {"f64": 1e-12, "f32": 1e-5}
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -84,19 +90,40 @@ def oracle_grad(oracle_lib, c):
     return gk, ga, tr
 
 
+def gauge_grad(c):
+    """dJ/dkappa, dJ/dsource of the same case by the float32 transcription."""
+    gk, ga, _ = drift_gauge.misfit_gradient(c["kappa"], c["up"], c["uc"], c["h"], c["dt"], c["nsteps"],
+                                            c["src_idx"], c["amp"], c["rec_idx"], c["target"],
+                                            dtype=np.float32)
+    return gk, ga
+
+
+def check_grads(c, got, ref, what):
+    """Assert the bars; FP32 also against 4x the inherent FP32 drift.  The measured
+    errors are printed and carried in every assertion message."""
+    (gk, ga, tr), (rk, ra, rtr) = got, ref
+    dtype = c["dtype"]
+    e = dict(traces=rel_l2(tr, rtr), kappa=rel_l2(gk, rk), source=rel_l2(ga, ra))
+    msg = f"{what} {dtype}: rel L2 traces {e['traces']:.3e} dJ/dkappa {e['kappa']:.3e} dJ/dsource {e['source']:.3e}"
+    if dtype == "f32":
+        qk, qa = gauge_grad(c)
+        gq = dict(kappa=rel_l2(qk, rk), source=rel_l2(qa, ra))
+        msg += f"; FP32 drift of the same recurrence: dJ/dkappa {gq['kappa']:.3e} dJ/dsource {gq['source']:.3e}"
+    say("  " + msg)
+    assert np.abs(rk).max() > 0, msg
+    assert e["traces"] <= TOL_TRACE[dtype], msg
+    assert e["kappa"] <= TOL_GRAD[dtype], msg
+    assert e["source"] <= TOL_GRAD[dtype], msg
+    if dtype == "f32":
+        assert e["kappa"] <= 4 * gq["kappa"] and e["source"] <= 4 * gq["source"], msg
+
+
 @pytest.mark.parametrize("dtype,K,nonzero", [("f64", 1, False), ("f64", 7, True), ("f64", 50, False),
                                              ("f32", 16, False), ("f32", 50, True)])
 def test_adjoint_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
     c = case(dtype, nonzero=nonzero)
     say(f"adjoint {dtype} K={K} nonzero={nonzero}")
-    gk, ga, tr = gpu_grad(adw, c, K)
-    rk, ra, rtr = oracle_grad(oracle_lib, c)
-    tol = 1e-10 if dtype == "f64" else 2e-3
-    say(f"  rel L2: traces {rel_l2(tr, rtr):.3e}  dJ/dkappa {rel_l2(gk, rk):.3e}  dJ/dsource {rel_l2(ga, ra):.3e}")
-    assert np.abs(rk).max() > 0
-    assert rel_l2(tr, rtr) <= (1e-12 if dtype == "f64" else 1e-5)
-    assert rel_l2(gk, rk) <= tol
-    assert rel_l2(ga, ra) <= tol
+    check_grads(c, gpu_grad(adw, c, K), oracle_grad(oracle_lib, c), f"K={K} nonzero={nonzero}")
 
 
 @pytest.mark.parametrize("nx,ny", [(30, 50), (7, 90), (130, 9)])
@@ -105,11 +132,10 @@ def test_adjoint_narrow_grids(adw, oracle_lib, nx, ny):
     ones): gradients of kappa and of the source values against the oracle (FP64)."""
     c = case("f64", nx=nx, ny=ny, nsteps=24, seed=nx + ny)
     say(f"adjoint narrow {nx}x{ny}")
-    gk, ga, tr = gpu_grad(adw, c, 5)
-    rk, ra, rtr = oracle_grad(oracle_lib, c)
-    assert np.abs(ra).max() > 0
-    assert rel_l2(gk, rk) <= 1e-10
-    assert rel_l2(ga, ra) <= 1e-10
+    got = gpu_grad(adw, c, 5)
+    ref = oracle_grad(oracle_lib, c)
+    assert np.abs(ref[1]).max() > 0
+    check_grads(c, got, ref, f"narrow {nx}x{ny}")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -131,12 +157,7 @@ def test_adjoint_shared_receiver_nodes(adw, oracle_lib, dtype):
     valid = ri < nx * ny
     assert np.isnan(tr[:, ~valid]).all()
     c2 = dict(c, rec_idx=ri[valid], target=c["target"][:, valid])
-    rk, ra, rtr = oracle_grad(oracle_lib, c2)
-    tol = 1e-10 if dtype == "f64" else 2e-3
-    say(f"  rel L2: traces {rel_l2(tr[:, valid], rtr):.3e}  dJ/dkappa {rel_l2(gk, rk):.3e}  dJ/dsource {rel_l2(ga, ra):.3e}")
-    assert rel_l2(tr[:, valid], rtr) <= (1e-12 if dtype == "f64" else 1e-5)
-    assert rel_l2(gk, rk) <= tol
-    assert rel_l2(ga, ra) <= tol
+    check_grads(c2, (gk, ga, tr[:, valid]), oracle_grad(oracle_lib, c2), "shared receivers")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -151,17 +172,22 @@ def test_checkpoint_interval_does_not_change_the_gradient(adw, dtype):
         assert np.array_equal(g1[0], g[0]) and np.array_equal(g1[1], g[1])
 
 
-def test_gradient_matches_finite_differences_on_gpu(adw):
-    """C5's recipe at 128^2 (kappa in [1, 9], Ricker, receivers on the row nearest
-    y = 0.1), FP64, 300 steps: central differences of the GPU loss on 16 cells."""
-    p, kt = wl.config_c5(dtype="f64", nsteps=300, n=128, nrec=16)
+@pytest.mark.parametrize("n,nsteps,nrec", [(128, 300, 16), (1024, 2000, 64)])
+def test_gradient_matches_finite_differences_on_gpu(adw, n, nsteps, nrec):
+    """C5's recipe (kappa in [1, 9], Ricker, receivers on the row nearest y = 0.1,
+    checkpoints every 100 steps), FP64: central differences of the GPU loss, with
+    eps = 1e-5 kappa, agree with the adjoint gradient to 1e-5 on 16 cells: the source
+    node (where dJ/dkappa peaks, hundreds of times above every other node at C5's full
+    size) and 15 seeded cells with |dJ/dkappa| >= 1e-2 of the largest value outside the
+    source's 5x5 neighbourhood.  (1024, 2000, 64) is C5 at its full size."""
+    p, kt = wl.config_c5(dtype="f64", nsteps=nsteps, n=n, nrec=nrec)
     # target: the traces of the run on the second kappa field
     wave = adw.Wave(p.nx, p.ny, p.h, p.dt, dtype=torch.float64, kappa=dev(kt))
     si, ri, amp = dev(p.src_idx), dev(p.rec_idx), dev(p.src_amp)
     zero = dev(p.u_prev)
     target = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
                                   checkpoint_every=100)
-    say("C5-shape FD check")
+    say(f"C5 FD check {n}^2 {nsteps} steps")
 
     def loss(kap):
         wave.set_kappa(dev(kap))
@@ -170,33 +196,56 @@ def test_gradient_matches_finite_differences_on_gpu(adw):
         return float(((tr - target) ** 2).sum()), tr
 
     J0, tr = loss(p.kappa)
+    assert J0 > 0
     gk, _ = wave.adjoint_backward(2.0 * (tr - target), src_idx=si, src_amp=amp, rec_idx=ri)
     g = gk.cpu().numpy()
     rng = np.random.default_rng(6)
-    cand = np.argwhere(np.abs(g) >= 1e-2 * np.abs(g).max())
-    cells = cand[rng.choice(len(cand), size=16, replace=False)]
+    sj, si0 = divmod(int(p.src_idx[0]), p.nx)
+    away = np.abs(g).copy()
+    away[max(sj - 2, 0):sj + 3, max(si0 - 2, 0):si0 + 3] = 0.0
+    cand = np.argwhere(away >= 1e-2 * away.max())
+    cells = [(sj, si0)] + [tuple(c) for c in cand[rng.choice(len(cand), size=15, replace=False)]]
+    worst = 0.0
     for (j, i) in cells:
         eps = 1e-5 * p.kappa[j, i]
         kp = p.kappa.copy(); kp[j, i] += eps
         km = p.kappa.copy(); km[j, i] -= eps
         fd = (loss(kp)[0] - loss(km)[0]) / (2 * eps)
-        assert abs(fd - g[j, i]) <= 1e-5 * abs(fd), (j, i, fd, g[j, i])
+        err = abs(fd - g[j, i]) / abs(fd)
+        worst = max(worst, err)
+        assert err <= 1e-5, (j, i, fd, g[j, i], err)
+    say(f"  FD vs adjoint: worst relative difference over 16 cells {worst:.3e}")
     wave.close()
 
 
-def test_dot_product_identity_on_gpu(adw):
-    """<F f, d> = <f, F^T d> for the map source values -> traces (FP64, zero start)."""
-    c = case("f64", nx=80, ny=60, nsteps=60, seed=8)
-    rng = np.random.default_rng(2)
-    d = rng.standard_normal((c["nsteps"], 8))
+@pytest.mark.parametrize("full", [False, True])
+def test_dot_product_identity_on_gpu(adw, full):
+    """<F f, d> = <f, F^T d> for the linear map source values -> traces (FP64, zero start),
+    to 1e-13 of |<F f, d>|, with d = F f plus seeded noise of the same size.  full: C5 at
+    its full size (1024^2, 2000 steps, 64 receivers, checkpoints every 100 steps)."""
+    if full:
+        p, _ = wl.config_c5(dtype="f64")
+        c = dict(nx=p.nx, ny=p.ny, h=p.h, dt=p.dt, kappa=p.kappa, up=p.u_prev, uc=p.u_curr,
+                 src_idx=p.src_idx, amp=p.src_amp, rec_idx=p.rec_idx, nsteps=p.nsteps)
+        K = 100
+    else:
+        c = case("f64", nx=80, ny=60, nsteps=60, seed=8)
+        K = 13
+    say(f"dot product {'C5 full' if full else '80x60'}")
     wave = adw.Wave(c["nx"], c["ny"], c["h"], c["dt"], dtype=torch.float64, kappa=dev(c["kappa"]))
     si, ri, amp = dev(c["src_idx"]), dev(c["rec_idx"]), dev(c["amp"])
     Ff = wave.adjoint_forward(dev(c["up"]), dev(c["uc"]), c["nsteps"], src_idx=si, src_amp=amp,
-                              rec_idx=ri, checkpoint_every=13)
+                              rec_idx=ri, checkpoint_every=K).cpu().numpy()
+    rng = np.random.default_rng(2)
+    d = Ff + np.sqrt(np.mean(Ff ** 2)) * rng.standard_normal(Ff.shape)
     _, Ftd = wave.adjoint_backward(dev(d), src_idx=si, src_amp=amp, rec_idx=ri, want_amp=True)
-    lhs = float((Ff.cpu().numpy() * d).sum())
+    lhs = float((Ff * d).sum())
     rhs = float((c["amp"] * Ftd.cpu().numpy()).sum())
-    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    rel = abs(lhs - rhs) / abs(lhs)
+    norm = abs(lhs - rhs) / (np.linalg.norm(Ff) * np.linalg.norm(d))
+    say(f"  |lhs - rhs| / |lhs| = {rel:.3e}, / (|Ff| |d|) = {norm:.3e}")
+    assert abs(lhs) > 0
+    assert rel <= 1e-13, (lhs, rhs, rel)
     wave.close()
 
 
@@ -211,6 +260,56 @@ def test_autograd_function(adw, oracle_lib):
     loss = ((tr - dev(c["target"])) ** 2).sum()
     loss.backward()
     rk, ra, _ = oracle_grad(oracle_lib, c)
-    assert rel_l2(kap.grad.cpu().numpy(), rk) <= 1e-10
-    assert rel_l2(amp.grad.cpu().numpy(), ra) <= 1e-10
+    assert rel_l2(kap.grad.cpu().numpy(), rk) <= TOL_GRAD["f64"]
+    assert rel_l2(amp.grad.cpu().numpy(), ra) <= TOL_GRAD["f64"]
+    wave.close()
+
+
+def test_forward_record_is_checked(adw, oracle_lib):
+    """One stored forward run per handle: a backward for a run that a later forward
+    replaced, or after a coefficient change, raises instead of returning another run's
+    gradient; the latest run's backward stays exact."""
+    c = case("f64", nx=40, ny=36, nsteps=20, seed=14)
+    wave = adw.Wave(c["nx"], c["ny"], c["h"], c["dt"], dtype=torch.float64, kappa=dev(c["kappa"]))
+    si, ri, amp = dev(c["src_idx"]), dev(c["rec_idx"]), dev(c["amp"])
+    up, uc = dev(c["up"]), dev(c["uc"])
+    tr1 = wave.adjoint_forward(up, uc, c["nsteps"], src_idx=si, src_amp=amp, rec_idx=ri, checkpoint_every=6)
+    first = wave.adjoint_record
+    amp2 = amp * 0.5
+    tr2 = wave.adjoint_forward(up, uc, c["nsteps"], src_idx=si, src_amp=amp2, rec_idx=ri, checkpoint_every=6)
+    second = wave.adjoint_record
+    assert first != 0 and second != 0 and first != second
+    g = 2.0 * (tr1 - dev(c["target"]))
+    with pytest.raises(adw.AdiError):
+        wave.adjoint_backward(g, src_idx=si, src_amp=amp, rec_idx=ri, record=first)
+    # the second run's backward (by id, and by 0 = the stored run) is the oracle's
+    c2 = dict(c, amp=c["amp"] * 0.5)
+    rk, _, rtr = oracle_grad(oracle_lib, c2)
+    assert rel_l2(tr2.cpu().numpy(), rtr) <= TOL_TRACE["f64"]
+    for rec_id in (second, 0):
+        gk, _ = wave.adjoint_backward(2.0 * (tr2 - dev(c["target"])), src_idx=si, src_amp=amp2, rec_idx=ri,
+                                      record=rec_id)
+        assert rel_l2(gk.cpu().numpy(), rk) <= TOL_GRAD["f64"]
+    # a coefficient change discards the stored run
+    wave.set_kappa(dev(c["kappa"]))
+    with pytest.raises(adw.AdiError):
+        wave.adjoint_backward(g, src_idx=si, src_amp=amp2, rec_idx=ri)
+    wave.close()
+
+
+def test_autograd_two_forwards_before_backward(adw):
+    """Two autograd forwards on one handle before the first backward: that backward
+    raises (the handle keeps only the second run's checkpoints)."""
+    c = case("f64", nx=32, ny=30, nsteps=12, seed=15)
+    wave = adw.Wave(c["nx"], c["ny"], c["h"], c["dt"], dtype=torch.float64, kappa=dev(c["kappa"]))
+    si, ri = dev(c["src_idx"]), dev(c["rec_idx"])
+    kap = dev(c["kappa"]).requires_grad_(True)
+    amp = dev(c["amp"])
+    tr1 = adw.simulate_traces(wave, kap, dev(c["up"]), dev(c["uc"]), c["nsteps"], si, amp, ri, checkpoint_every=5)
+    tr2 = adw.simulate_traces(wave, kap, dev(c["up"]), dev(c["uc"]), c["nsteps"], si, amp * 2, ri,
+                              checkpoint_every=5)
+    with pytest.raises(adw.AdiError):
+        (tr1 ** 2).sum().backward()
+    (tr2 ** 2).sum().backward()           # the stored run's backward works
+    assert torch.isfinite(kap.grad).all() and float(kap.grad.abs().max()) > 0
     wave.close()

@@ -4,7 +4,7 @@ direct plan (bitwise: they change scheduling only)."""
 import numpy as np
 import pytest
 
-from tests.conftest import rel_l2
+from tests.conftest import max_rel, rel_l2
 from paper_2006_10142_amd import workloads as wl
 
 torch = pytest.importorskip("torch")
@@ -147,6 +147,70 @@ def test_batch_c4_sample(adw, oracle_lib):
     got, _ = run_batch(adw, sims, "f32", 40, graph=True)
     for s, g in zip(sims, got):
         assert rel_l2(g, oracle_run(oracle_lib, s, 40)) <= TOL["f32"]
+
+
+def widest(nx, wmax):
+    """the widest one-pass tiles (the batch's layout): fewest across, multiples of 8"""
+    tx = -(-nx // wmax)
+    return (-(-nx // tx) + 7) // 8 * 8
+
+
+def test_batch_c4_full(adw, oracle_lib):
+    """C4 at its full size: 256 simulations (N in 256..1024 step 64, FP32), autotuned
+    plan, graph replay, 20 steps from levels made by each simulation's own ghost start.
+    Every simulation is bitwise equal to the plain solver run on the same tile layout
+    (the batch's widest tiles and its nodes per lane), and 8 seeded simulations (with
+    the smallest and the largest grid) match the oracle to the FP32 bars."""
+    nsteps = 20
+    probs = wl.config_c4(dtype="f32", nsteps=nsteps)
+    assert len(probs) == 256
+    say("batch C4 full: 256 sims, plain ghost starts")
+    u0s, u1s = [], []
+    for p in probs:
+        w = adw.Wave(p.nx, p.ny, p.h, p.dt, c=torch.from_numpy(p.c).cuda(), dtype=torch.float32)
+        u0 = torch.from_numpy(p.u0).cuda()
+        u1s.append(w.start(u0, mode="ghost"))
+        u0s.append(u0)
+        w.close()
+    torch.cuda.synchronize()
+    b = adw.Batch([(p.nx, p.ny) for p in probs], [p.h for p in probs], [p.dt for p in probs],
+                  [torch.from_numpy(p.c).cuda() for p in probs], dtype=torch.float32)
+    b.autotune(trial_steps=3)
+    lv0 = [x.clone() for x in u0s]
+    lv1 = [x.clone() for x in u1s]
+    b.bind(lv0, lv1)
+    b.graph(True)
+    b.step(nsteps)
+    _, curr = b.levels()
+    torch.cuda.synchronize()
+    info = b.plan()
+    assert info["count"] == 256 and info["graph"] == 1 and info["fused_step"] == 1
+    lane = info["fused_lane_nodes"]
+    say(f"  autotuned plan: {lane} nodes per lane, x threads {info['x_threads_per_line']}")
+    got = [x.cpu().numpy() for x in curr]
+    b.close()
+    say("batch C4 full: plain runs on the same tiles")
+    for s, p in enumerate(probs):
+        w = adw.Wave(p.nx, p.ny, p.h, p.dt, c=torch.from_numpy(p.c).cuda(), dtype=torch.float32)
+        w.set_tuning(fused_step=True, fused_lane_nodes=lane, fused_segment_rows=-2,
+                     fused_tile_cols=widest(p.nx, 240 if lane == 4 else 496))
+        a, c = w.step(u0s[s].clone(), u1s[s].clone(), nsteps)
+        torch.cuda.synchronize()
+        assert np.array_equal(c.cpu().numpy(), got[s]), (s, p.nx)
+        w.close()
+    rng = np.random.default_rng(44)
+    sizes = np.array([p.nx for p in probs])
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    while len(pick) < 8:
+        pick.add(int(rng.integers(0, 256)))
+    for s in sorted(pick):
+        p = probs[s]
+        kap = p.c.astype(np.float64) ** 2
+        u1 = oracle_lib.start(kap, p.u0, p.h, p.dt)
+        _, ref, _ = oracle_lib.run(kap, p.u0, u1, p.h, p.dt, nsteps)
+        e2, em = rel_l2(got[s], ref), max_rel(got[s], ref)
+        say(f"  sim {s} ({p.nx}^2): rel L2 {e2:.3e}, max-norm {em:.3e}")
+        assert e2 <= TOL["f32"] and em <= TOL["f32"], (s, e2, em)
 
 
 def test_batch_levels_rotate_and_errors(adw):

@@ -11,7 +11,7 @@ import math
 import numpy as np
 import pytest
 
-from tests.conftest import rel_l2
+from tests.conftest import max_rel, rel_l2
 from paper_2006_10142_amd import workloads as wl
 
 torch = pytest.importorskip("torch")
@@ -250,20 +250,30 @@ def test_c3_shape_at_1024(adw, oracle_lib, dtype, variant):
 
 @pytest.fixture(scope="module")
 def c3p_reference(oracle_lib):
-    p = wl.config_c3p(dtype="f32", nsteps=3)
-    _, ref, _ = oracle_lib.run_problem(p)
-    return p, ref
+    refs = {}
+
+    def get(dtype):
+        if dtype not in refs:
+            p = wl.config_c3p(dtype=dtype, nsteps=3)
+            _, ref, _ = oracle_lib.run_problem(p)
+            refs[dtype] = (p, ref)
+        return refs[dtype]
+    return get
 
 
-@pytest.mark.parametrize("one_pass", [True, False])
-def test_c3_full_size_steps(adw, c3p_reference, one_pass):
-    """C3 at its full size (8192^2 FP32): 3 steps from a Gaussian pulse, compared node
-    by node with the oracle, with the benchmark's default (one-pass) step and with the
-    exact two-pass step."""
-    p, ref = c3p_reference
-    say(f"C3p f32 8192^2 3 steps one_pass={one_pass}")
-    _, got, _ = gpu_run(adw, p, fused_step=one_pass)
-    assert rel_l2(got, ref) <= TOL_RUN["f32"]
+@pytest.mark.parametrize("dtype,one_pass", [("f32", True), ("f32", False), ("f64", False)])
+def test_c3_full_size_steps(adw, c3p_reference, dtype, one_pass):
+    """C3's grid at its full size (8192^2): 3 steps from a Gaussian pulse over the whole
+    field against the oracle, in FP32 with the benchmark's default (one-pass) step and
+    with the exact two-pass step, and in FP64 (the paper's arithmetic, exact step):
+    relative L2 and the max-norm error relative to max|u|."""
+    p, ref = c3p_reference(dtype)
+    say(f"C3p {dtype} 8192^2 3 steps one_pass={one_pass}")
+    _, got, _ = gpu_run(adw, p, fused_step=one_pass if dtype == "f32" else None)
+    e2, em = rel_l2(got, ref), max_rel(got, ref)
+    say(f"  rel L2 {e2:.3e}, max-norm {em:.3e}")
+    assert e2 <= TOL_RUN[dtype]
+    assert em <= TOL_RUN[dtype]
 
 
 # ------------------------------------------------ starts, sources, traces ----
