@@ -117,6 +117,8 @@ def cpu_baseline(prob, steps: int):
     t1 = time.perf_counter() - t1
     return {"value": prob.nx * prob.ny * steps / t / 1e6, "unit": "Mpts/s",
             "cores": cores, "kind": "oracle",
+            "build": "gcc -O2 -fopenmp -ffp-contract=off, no -march; OpenMP over lines; x-lines "
+                     "row by row, y-lines one column at a time (stride nx); untuned",
             "sample": f"{steps} ADI steps of the same {prob.nx}x{prob.ny} workload, FP64, "
                       f"{t:.1f} s wall",
             "one_thread": {"value": round(n1 * n1 / t1 / 1e6, 2), "unit": "Mpts/s",
@@ -248,80 +250,103 @@ def bench_cr(adw, torch, prob, steps: int, plain_value: float):
             "finite": bool(torch.isfinite(b).all())}
 
 
-def bench_adjoint(adw, torch, plain_value: float):
+def bench_adjoint(adw, torch):
     """C5: dJ/dkappa of a receiver misfit on 1024^2 FP32, 2000 steps, checkpoints every 100
-    steps, 64 receivers; target traces from the run on the second kappa field."""
+    steps, 64 receivers; target traces from the run on the second kappa field.
+
+    Algorithmic bytes per node (E = 4 B), each launch's own inputs and outputs once:
+      forward step   8E   the exact two-pass step (x-sweep 3E, y-solve and update 5E),
+                          plus 4E / K for the checkpoint copy every K steps;
+      backward step 26E   the recomputed forward step (8E, its w kept), the transposed
+                          y-lines (reads lambda, r, writes z: 3E), the transposed x-lines
+                          (reads z, r, writes t: 3E) and the update (reads t, z, r, two
+                          lambda levels, three u levels, w, dJ/dkappa; writes dJ/dkappa and
+                          lambda: 12E).
+    vs_plain divides by the plain solver's rate on the same 1024^2 grid (same kappa,
+    source and step count; the handle's default step)."""
+    import numpy as np
     from paper_2006_10142_amd import workloads as wl
     p, kt = wl.config_c5(dtype="f32")
     dev = torch.device("cuda:0")
+    K = 100
     wave = adw.Wave(p.nx, p.ny, p.h, p.dt, dtype=torch.float32, kappa=torch.from_numpy(kt).to(dev))
     si = torch.from_numpy(p.src_idx).to(dev)
     ri = torch.from_numpy(p.rec_idx).to(dev)
     amp = torch.from_numpy(p.src_amp).to(dev)
     zero = torch.zeros((p.ny, p.nx), dtype=torch.float32, device=dev)
     target = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
-                                  checkpoint_every=100)
+                                  checkpoint_every=K)
     wave.set_kappa(torch.from_numpy(p.kappa).to(dev))
     # warm-up pass (allocates the checkpoint and segment storage)
     tr = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
-                              checkpoint_every=100)
+                              checkpoint_every=K)
     wave.adjoint_backward(2.0 * (tr - target), src_idx=si, src_amp=amp, rec_idx=ri)
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    e[0].record()
-    tr = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
-                              checkpoint_every=100)
-    e[1].record()
-    gk, _ = wave.adjoint_backward(2.0 * (tr - target), src_idx=si, src_amp=amp, rec_idx=ri)
-    e[2].record()
-    torch.cuda.synchronize()
-    fwd = e[0].elapsed_time(e[1])
-    bwd = e[1].elapsed_time(e[2])
+    fw, bw = [], []
+    for _ in range(3):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        tr = wave.adjoint_forward(zero, zero, p.nsteps, src_idx=si, src_amp=amp, rec_idx=ri,
+                                  checkpoint_every=K)
+        e[1].record()
+        gk, _ = wave.adjoint_backward(2.0 * (tr - target), src_idx=si, src_amp=amp, rec_idx=ri)
+        e[2].record()
+        torch.cuda.synchronize()
+        fw.append(e[0].elapsed_time(e[1]))
+        bw.append(e[1].elapsed_time(e[2]))
+    fwd, bwd = float(np.median(fw)), float(np.median(bw))
     loss = float(((tr - target) ** 2).sum())
     finite = bool(torch.isfinite(gk).all())
+    # the plain solver on the same grid, coefficient, source and step count
+    a, b = zero.clone(), zero.clone()
+    a, b = wave.step(a, b, 20, src_idx=si, src_amp=amp[:20])
+    pl = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.zero_(); b.zero_()
+        torch.cuda.synchronize()
+        e0.record()
+        a, b = wave.step(a, b, p.nsteps, src_idx=si, src_amp=amp)
+        e1.record()
+        torch.cuda.synchronize()
+        pl.append(e0.elapsed_time(e1))
+    plain_ms = float(np.median(pl))
+    plain_step = "one-pass" if wave.info()["fused_step"] else "two-pass"
     nodes = p.nx * p.ny
     value = nodes * p.nsteps / ((fwd + bwd) / 1e3) / 1e6
+    plain_value = nodes * p.nsteps / (plain_ms / 1e3) / 1e6
+    E = 4
+    fb = (8 + 4.0 / K) * E * nodes
+    bb = 26 * E * nodes
+    f_gbps = fb * p.nsteps / (fwd / 1e3) / 1e9
+    b_gbps = bb * p.nsteps / (bwd / 1e3) / 1e9
     wave.close()
     return {"workload": "c5_adjoint_1024x1024_f32_2000_steps_64_receivers", "value": round(value, 1),
             "unit": "Mpts/s (gradient evaluation: forward with checkpoints + reverse pass)",
             "forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
             "ms_per_step_forward": round(fwd / p.nsteps, 5),
-            "ms_per_step_backward": round(bwd / p.nsteps, 5), "checkpoint_every": 100,
-            "loss": loss, "finite": finite, "vs_plain": round(value / plain_value, 4)}
+            "ms_per_step_backward": round(bwd / p.nsteps, 5), "checkpoint_every": K,
+            "algorithmic_bytes_per_node": {"forward_step": round((8 + 4.0 / K) * E, 2), "backward_step": 26 * E},
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS,
+                         "forward": {"achieved": round(f_gbps, 1), "frac": round(f_gbps / HBM_PEAK_GBPS, 4)},
+                         "backward": {"achieved": round(b_gbps, 1), "frac": round(b_gbps / HBM_PEAK_GBPS, 4)}},
+            "loss": loss, "finite": finite,
+            "plain_same_grid": {"value": round(plain_value, 1), "unit": "Mpts/s", "ms": round(plain_ms, 3),
+                                "step": plain_step},
+            "vs_plain": round(value / plain_value, 4)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-steps", type=int, default=4)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=50)
-    ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-cr", action="store_true", help="skip the cyclic-reduction baseline leg")
-    ap.add_argument("--no-tridiag", action="store_true", help="skip the batched line-solve leg")
-    ap.add_argument("--no-adjoint", action="store_true")
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: the solver runs on one GPU; runs on several GPUs are not supported "
-              "(--gpus must be 1).", file=sys.stderr)
-        sys.exit(2)
-
+def plain_leg(adw, torch, prob, name: str, dtype: str, steps: int, warmup: int, reps: int,
+              profile_steps: int, both: bool = True):
+    """One plain-solver workload: create, initial levels, then the measured step (the
+    handle's default: the one-pass step where allowed) and, with both=True and the
+    one-pass step on, the exact two-pass step too.  Returns (main, two_pass or None,
+    create_ms).  Each measurement: `warmup` untimed steps, then `reps` repetitions of
+    exactly `steps` steps bracketed by synchronisation (the median is the figure), then
+    per-kernel durations from events around every launch on the solver's stream."""
     import numpy as np
-    import torch
-    import paper_2006_10142_amd as adw
-
-    name, dtype, n = WORKLOADS[args.workload]
-    total = args.warmup + args.steps
-    prob = make_problem(args.workload, total)
     tdt = torch.float32 if dtype == "f32" else torch.float64
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
     t0 = time.perf_counter()
     wave = adw.Wave(prob.nx, prob.ny, prob.h, prob.dt, dtype=tdt,
                     c=torch.from_numpy(prob.c).to(dev) if prob.c is not None else prob.c_scalar)
@@ -348,32 +373,35 @@ def main():
     npts = prob.nx * prob.ny
 
     def measure(a, b):
-        """warm-up, then exactly `steps` timed steps bracketed by synchronisation, then
-        per-kernel durations (events around every launch, same stream)"""
-        if args.warmup:
-            a, b = wave.step(a, b, args.warmup, **srcs(0, args.warmup))
+        if warmup:
+            a, b = wave.step(a, b, warmup, **srcs(0, warmup))
         torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        w0 = time.perf_counter()
-        ev0.record()
-        a, b = wave.step(a, b, args.steps, **srcs(args.warmup, args.steps))
-        ev1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        ms = ev0.elapsed_time(ev1)
+        reps_ms, walls = [], []
+        for r in range(reps):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            ev0.record()
+            a, b = wave.step(a, b, steps, **srcs(warmup + r * steps, steps))
+            ev1.record()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - w0)
+            reps_ms.append(ev0.elapsed_time(ev1))
+        ms = float(np.median(reps_ms))
+        wall = float(np.median(walls))
         if not torch.isfinite(b).all():
             print("bench.py: non-finite field after the timed steps", file=sys.stderr)
             sys.exit(1)
-        psteps = max(1, min(args.profile_steps, args.steps))
+        psteps = max(1, min(profile_steps, steps))
         (a, b), kms = wave.profile(a, b, psteps, **srcs(0, psteps))
         dom = max((k for k in kms if k in ALG_BYTES_PER_NODE), key=lambda k: kms[k])
         alg_bytes = ALG_BYTES_PER_NODE[dom] * esz * npts
         achieved = alg_bytes / (kms[dom] / 1e3) / 1e9
         info = wave.info()
         per_node = FUSED_STEP_BYTES_PER_NODE if info["fused_step"] else STEP_BYTES_PER_NODE
-        step_gbps = per_node * esz * npts * args.steps / (ms / 1e3) / 1e9
-        res = {"value": round(npts * args.steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / args.steps, 5),
+        step_gbps = per_node * esz * npts * steps / (ms / 1e3) / 1e9
+        res = {"value": round(npts * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 5),
                "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                             "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                             "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -382,27 +410,85 @@ def main():
                "step_algorithmic_GBps": round(step_gbps, 1),
                "step_frac_of_peak": round(step_gbps / HBM_PEAK_GBPS, 4),
                "kernel_ms": {k: round(v, 5) for k, v in kms.items()},
+               "repeats_ms_per_step": [round(v / steps, 5) for v in reps_ms],
                "launch_plan": info, "wall_s_timed": round(wall, 4)}
         # HBM bytes the counters measured for every launch of a step (committed
         # rocprofv3 summary of the same sources), over the measured step time
         counted = [load_traffic(name, k, 0.0) for k in kms]
         if kms and all(c is not None for c in counted):
             per_step = sum(counted)
-            gbps = per_step / (ms / args.steps / 1e3) / 1e9
+            gbps = per_step / (ms / steps / 1e3) / 1e9
             res["hbm_counted"] = {"bytes_per_step": round(per_step), "GBps": round(gbps, 1),
                                   "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
         return a, b, res
 
     a, b, main = measure(a, b)
     two_pass = None
-    if main["launch_plan"]["fused_step"]:
+    if both and main["launch_plan"]["fused_step"]:
         wave.set_tuning(fused_step=False)
         a, b, two_pass = measure(a, b)
         two_pass.pop("launch_plan")
         wave.set_tuning(fused_step=True)
-    value = main["value"]
-    ms = main["ms_per_step"] * args.steps
+    wave.close()
+    del a, b
+    torch.cuda.empty_cache()
+    return main, two_pass, create_ms
 
+
+def f64_leg(adw, torch, steps: int, warmup: int, reps: int, profile_steps: int):
+    """C3 at the paper's arithmetic: the same 8192^2 heterogeneous Ricker workload in
+    FP64 (speed field and source rounded to FP64), exact two-pass step.  Algorithmic
+    bytes per node and step 8E = 64 B; the HBM roofline is 125,000 Mpts/s."""
+    from paper_2006_10142_amd import workloads as wl
+    name = "c3_heterogeneous_ricker_8192x8192_f64"
+    prob = wl.config_c3(dtype="f64", nsteps=warmup + reps * steps)
+    res, _, create_ms = plain_leg(adw, torch, prob, name, "f64", steps, warmup, reps, profile_steps, both=False)
+    res["workload"] = name
+    res["dtype"] = "f64"
+    res["steps"] = steps
+    res["warmup"] = warmup
+    res["create_ms"] = round(create_ms, 2)
+    res["step"] = "two-pass"
+    res["roofline_Mpts"] = round(HBM_PEAK_GBPS * 1e9 / (STEP_BYTES_PER_NODE * 8) / 1e6, 1)
+    res.pop("launch_plan", None)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed repetitions of --steps steps; the median is reported")
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cr", action="store_true", help="skip the cyclic-reduction baseline leg")
+    ap.add_argument("--no-tridiag", action="store_true", help="skip the batched line-solve leg")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 leg of the workload")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: the solver runs on one GPU; runs on several GPUs are not supported "
+              "(--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2006_10142_amd as adw
+
+    name, dtype, n = WORKLOADS[args.workload]
+    prob = make_problem(args.workload, args.warmup + args.reps * args.steps)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    main, two_pass, create_ms = plain_leg(adw, torch, prob, name, dtype, args.steps, args.warmup, args.reps,
+                                          args.profile_steps, both=True)
+    value = main["value"]
     # achievable copy bandwidth on this GPU (1 GiB read + 1 GiB write)
     x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
@@ -433,7 +519,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "nx": prob.nx, "ny": prob.ny,
                    "coefficient": "per-node" if prob.c is not None else "constant",
-                   "source": "ricker point source" if src else "none",
+                   "source": "ricker point source" if prob.src_amp is not None else "none",
                    "step": "one-pass" if main["launch_plan"]["fused_step"] else "two-pass",
                    "launch_plan": main["launch_plan"]},
         "roofline": main["roofline"],
@@ -442,6 +528,7 @@ def main():
         "step_frac_of_peak": main["step_frac_of_peak"],
         "hbm_counted": main.get("hbm_counted"),
         "kernel_ms": main["kernel_ms"],
+        "repeats_ms_per_step": main["repeats_ms_per_step"],
         "two_pass": two_pass,
         "copy_GBps": round(copy_gbps, 1),
         "create_ms": round(create_ms, 2),
@@ -451,16 +538,17 @@ def main():
         hc = blk.get("hbm_counted") if blk else None
         if hc and copy_gbps > 0:
             hc["frac_of_copy"] = round(hc["GBps"] / copy_gbps, 4)
-    wave.close()
-    del a, b
-    torch.cuda.empty_cache()
     tp_value = two_pass["value"] if two_pass else value
+    if not args.no_f64 and args.workload == "c3":
+        # the paper's arithmetic on the same workload: a short run (the FP64 step is
+        # about twice as slow and its fields twice as large)
+        out["f64"] = f64_leg(adw, torch, min(args.steps, 20), min(args.warmup, 5), args.reps,
+                             min(args.profile_steps, 10))
     if not args.no_batch:
         out["batched"] = bench_batched(adw, torch, args.steps, args.warmup, value)
         out["batched"]["vs_two_pass"] = round(out["batched"]["value"] / tp_value, 4)
     if not args.no_adjoint:
-        out["adjoint"] = bench_adjoint(adw, torch, value)
-        out["adjoint"]["vs_two_pass"] = round(out["adjoint"]["value"] / tp_value, 4)
+        out["adjoint"] = bench_adjoint(adw, torch)
     if not args.no_tridiag:
         out["tridiag"] = bench_tridiag(adw, torch)
     if not args.no_cr and dtype == "f32":

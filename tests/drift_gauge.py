@@ -170,3 +170,22 @@ def misfit_gradient(kappa, u_prev, u_curr, h, dt, nsteps, src_idx, src_amp, rec_
             np.add.at(flat, ri, gtr[k - 2])
             lam1 = flat.reshape(ny, nx)
     return gk, ga, tr
+
+
+def run(kappa, u_prev, u_curr, h, dt, nsteps, dtype=np.float64):
+    """The oracle's forward run (no sources) in `dtype`: returns u^{n+nsteps}."""
+    R = _Arith(dtype)
+    ny, nx = np.shape(u_curr)
+    kap = np.asarray(kappa, dtype=R.dt)
+    if kap.ndim == 0:
+        kap = np.full((ny, nx), kap, dtype=R.dt)
+    ih2 = R.c(1.0 / (h * h))
+    tau2 = R.c(dt * dt)
+    off = R(R.c(0.5 * dt * dt / (h * h)) * kap)
+    um = np.asarray(u_prev, dtype=R.dt).copy()
+    uc = np.asarray(u_curr, dtype=R.dt).copy()
+    for _ in range(nsteps):
+        rho = R(tau2 * R(kap * _lap(R, uc, ih2)))
+        _, d = _solves(R, off, rho)
+        um, uc = uc, R(R(R(R.c(2.0) * uc) - um) + d)
+    return uc

