@@ -297,6 +297,22 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
                                  long long sys_stride, long long elem_stride,
                                  void* hip_stream);
 
+/* The same solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): identical
+ * arguments, kernels and results, but no allocation ever.  Where the partition
+ * solve needs its workspace, it uses a fixed device array of 64 MiB built into
+ * the library (one copy per device, held until the process ends) instead of
+ * allocating one: a layout that needs more (6*ceil(n/chunk)*batch values) is
+ * rejected with ADI_EINVAL before anything is queued.  Every call on a device
+ * shares that device's array, so calls that overlap in time on one device
+ * (different streams or host threads) race and must be serialised by the
+ * caller; calls queued on one stream are ordered and safe.  The first call on
+ * a device looks the array's address up (no allocation). */
+adi_status tridiag_solve_batched_noalloc(adi_dtype dtype, int n, int batch, const void* a,
+                                         const void* b, const void* c, void* d,
+                                         long long sys_stride, long long elem_stride,
+                                         void* hip_stream);
+
 /* ------------------------------------------------------ introspection/timing -- */
 
 typedef struct {

@@ -510,8 +510,11 @@ def simulate_traces(wave, kappa, u_prev, u_curr, nsteps, src_idx, src_amp, rec_i
                                  checkpoint_every)
 
 
-def tridiag_solve_batched(a, b, c, d, n: int, batch: int, sys_stride: int, elem_stride: int = 1):
-    """Solve batch tridiagonal systems in place in d (see tridiag_solve_batched in adiwave.h)."""
+def tridiag_solve_batched(a, b, c, d, n: int, batch: int, sys_stride: int, elem_stride: int = 1,
+                          noalloc: bool = False):
+    """Solve batch tridiagonal systems in place in d (see tridiag_solve_batched in adiwave.h).
+    noalloc=True calls tridiag_solve_batched_noalloc: no device allocation, the library's
+    fixed 64 MiB scratch instead (larger workspaces raise)."""
     torch = _torch()
     for name, t in (("a", a), ("b", b), ("c", c), ("d", d)):
         if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
@@ -524,9 +527,9 @@ def tridiag_solve_batched(a, b, c, d, n: int, batch: int, sys_stride: int, elem_
             if t.numel() < need:
                 raise ValueError(f"{name} holds {t.numel()} values, the layout needs {need}")
     code = _dtype_code(d.dtype)
-    _lib.check(_lib.load().tridiag_solve_batched(code, int(n), int(batch), a.data_ptr(),
-                                                 b.data_ptr(), c.data_ptr(), d.data_ptr(),
-                                                 int(sys_stride), int(elem_stride), _stream_ptr()))
+    fn = _lib.load().tridiag_solve_batched_noalloc if noalloc else _lib.load().tridiag_solve_batched
+    _lib.check(fn(code, int(n), int(batch), a.data_ptr(), b.data_ptr(), c.data_ptr(), d.data_ptr(),
+                  int(sys_stride), int(elem_stride), _stream_ptr()))
     return d
 
 

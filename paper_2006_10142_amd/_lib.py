@@ -74,6 +74,8 @@ _SIGNATURES = {
     "adi_wave_destroy": [_vp],
     "tridiag_solve_batched": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
                               ctypes.c_longlong, ctypes.c_longlong, _vp],
+    "tridiag_solve_batched_noalloc": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                      ctypes.c_longlong, ctypes.c_longlong, _vp],
     "adi_wave_get_info": [_vp, ctypes.POINTER(AdiWaveInfo)],
     "adi_wave_set_tuning": [_vp, ctypes.POINTER(AdiTuning)],
     "adi_wave_profile": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(AdiSource),

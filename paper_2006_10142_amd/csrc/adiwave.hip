@@ -1043,46 +1043,119 @@ adi_status adi_stream_copy(const void* src, void* dst, size_t bytes, void* hip_s
     return ADI_OK;
 }
 
-// scratch of the per-thread batched path, one per device, grown on demand
-static std::mutex g_scr_mu;
-static std::vector<std::pair<void*, size_t>> g_scr;
+}  // extern "C"
 
-adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* a, const void* b,
-                                 const void* c, void* d, long long sys_stride,
-                                 long long elem_stride, void* hip_stream)
+namespace {
+
+// Argument checks shared by the two batched-solve entry points.  On success *wg
+// tells whether the on-chip one-workgroup-per-system kernels take the layout
+// (with plan *p), else the partition solve does (it needs a workspace).
+adi_status tri_check(adi_dtype dtype, int n, int batch, const void* a, const void* b, const void* c,
+                     const void* d, long long sys_stride, long long elem_stride, bool* wg, TPlan* p)
 {
     if (dtype != ADI_F32 && dtype != ADI_F64) return fail(ADI_EINVAL, "unknown dtype");
     if (n < 0 || batch < 0) return fail(ADI_EINVAL, "n and batch must be >= 0");
+    *wg = false;
     if (n == 0 || batch == 0) return ADI_OK;
     if (!a || !b || !c || !d) return fail(ADI_EINVAL, "null array");
     if (d == a || d == b || d == c) return fail(ADI_EINVAL, "d must not alias a, b or c");
     if (elem_stride < 1) return fail(ADI_EINVAL, "elem_stride must be >= 1");
     if (batch > 1 && sys_stride < 1) return fail(ADI_EINVAL, "sys_stride must be >= 1 when batch > 1");
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    TPlan p{};
-    const bool wg_path = elem_stride == 1 && choose_tri(n, dtype, p);
+    *wg = elem_stride == 1 && choose_tri(n, dtype, *p);
+    return ADI_OK;
+}
+
+adi_status tri_run_wg(adi_dtype dtype, const TPlan& p, int n, int batch, const void* a, const void* b,
+                      const void* c, void* d, long long sys_stride, long long elem_stride, hipStream_t st)
+{
     const size_t es = esize(dtype);
-    if (wg_path) {
-        const bool vec = aligned16(a) && aligned16(b) && aligned16(c) && aligned16(d) &&
-                         ((size_t)sys_stride * es) % 16 == 0 && ((size_t)p.s * es) % 16 == 0;
-        bool ok;
-        if (dtype == ADI_F32) {
-            TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
-                             sys_stride, elem_stride, vec};
-            ok = launch_tri<float>(p, batch, t, st);
-        } else {
-            TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
-                              sys_stride, elem_stride, vec};
-            ok = launch_tri<double>(p, batch, t, st);
-        }
-        if (!ok) return fail(ADI_EUNSUPPORTED, "no batched kernel for this size");
-        ADI_LAUNCHED("tridiag_wg");
-        return ADI_OK;
+    const bool vec = aligned16(a) && aligned16(b) && aligned16(c) && aligned16(d) &&
+                     ((size_t)sys_stride * es) % 16 == 0 && ((size_t)p.s * es) % 16 == 0;
+    bool ok;
+    if (dtype == ADI_F32) {
+        TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
+                         sys_stride, elem_stride, vec};
+        ok = launch_tri<float>(p, batch, t, st);
+    } else {
+        TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
+                          sys_stride, elem_stride, vec};
+        ok = launch_tri<double>(p, batch, t, st);
     }
+    if (!ok) return fail(ADI_EUNSUPPORTED, "no batched kernel for this size");
+    ADI_LAUNCHED("tridiag_wg");
+    return ADI_OK;
+}
+
+size_t tri_part_bytes(adi_dtype dtype, int n, int batch)
+{
+    return (dtype == ADI_F32 ? tri_part_workspace<float>(n, batch) : tri_part_workspace<double>(n, batch)) *
+           esize(dtype);
+}
+
+adi_status tri_run_part(adi_dtype dtype, int n, int batch, const void* a, const void* b, const void* c, void* d,
+                        long long sys_stride, long long elem_stride, void* scr, hipStream_t st)
+{
+    if (dtype == ADI_F32) {
+        TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
+                         sys_stride, elem_stride, 0};
+        launch_tri_part<float>(t, (float*)scr, st);
+    } else {
+        TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
+                          sys_stride, elem_stride, 0};
+        launch_tri_part<double>(t, (double*)scr, st);
+    }
+    ADI_LAUNCHED("tridiag_part");
+    return ADI_OK;
+}
+
+// scratch of the partition solve, one per device, grown on demand
+std::mutex g_scr_mu;
+std::vector<std::pair<void*, size_t>> g_scr;
+
+// The allocation-free variant's scratch: a fixed array in the library's code
+// object, one copy per device.  In host code `scratch` names a host-side
+// stand-in, so the kernels get the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device and kept.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_na_mu;
+std::vector<void*> g_na_ptr;
+
+adi_status noalloc_scratch(void** out)
+{
     int dev = 0;
     ADI_HIP(hipGetDevice(&dev));
-    const size_t need = (dtype == ADI_F32 ? tri_part_workspace<float>(n, batch)
-                                          : tri_part_workspace<double>(n, batch)) * es;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if ((int)g_na_ptr.size() <= dev) g_na_ptr.resize(dev + 1, nullptr);
+    if (!g_na_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ADI_EHIP, std::string("hipGetSymbolAddress of the no-allocation scratch: ") +
+                                      hipGetErrorString(e));
+        g_na_ptr[dev] = ptr;
+    }
+    *out = g_na_ptr[dev];
+    return ADI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* a, const void* b,
+                                 const void* c, void* d, long long sys_stride,
+                                 long long elem_stride, void* hip_stream)
+{
+    bool wg = false;
+    TPlan p{};
+    if (adi_status s = tri_check(dtype, n, batch, a, b, c, d, sys_stride, elem_stride, &wg, &p)) return s;
+    if (n == 0 || batch == 0) return ADI_OK;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (wg) return tri_run_wg(dtype, p, n, batch, a, b, c, d, sys_stride, elem_stride, st);
+    int dev = 0;
+    ADI_HIP(hipGetDevice(&dev));
+    const size_t need = tri_part_bytes(dtype, n, batch);
     void* scr = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_scr_mu);
@@ -1101,17 +1174,27 @@ adi_status tridiag_solve_batched(adi_dtype dtype, int n, int batch, const void* 
         }
         scr = slot.first;
     }
-    if (dtype == ADI_F32) {
-        TriArgs<float> t{(const float*)a, (const float*)b, (const float*)c, (float*)d, n, batch,
-                         sys_stride, elem_stride, 0};
-        launch_tri_part<float>(t, (float*)scr, st);
-    } else {
-        TriArgs<double> t{(const double*)a, (const double*)b, (const double*)c, (double*)d, n, batch,
-                          sys_stride, elem_stride, 0};
-        launch_tri_part<double>(t, (double*)scr, st);
-    }
-    ADI_LAUNCHED("tridiag_part");
-    return ADI_OK;
+    return tri_run_part(dtype, n, batch, a, b, c, d, sys_stride, elem_stride, scr, st);
+}
+
+adi_status tridiag_solve_batched_noalloc(adi_dtype dtype, int n, int batch, const void* a, const void* b,
+                                         const void* c, void* d, long long sys_stride,
+                                         long long elem_stride, void* hip_stream)
+{
+    bool wg = false;
+    TPlan p{};
+    if (adi_status s = tri_check(dtype, n, batch, a, b, c, d, sys_stride, elem_stride, &wg, &p)) return s;
+    if (n == 0 || batch == 0) return ADI_OK;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (wg) return tri_run_wg(dtype, p, n, batch, a, b, c, d, sys_stride, elem_stride, st);
+    const size_t need = tri_part_bytes(dtype, n, batch);
+    if (need > kNoAllocScratchBytes)
+        return fail(ADI_EINVAL, "the layout needs " + std::to_string(need) +
+                                    " bytes of partition workspace, above the no-allocation scratch of " +
+                                    std::to_string(kNoAllocScratchBytes) + " bytes");
+    void* scr = nullptr;
+    if (adi_status s = noalloc_scratch(&scr)) return s;
+    return tri_run_part(dtype, n, batch, a, b, c, d, sys_stride, elem_stride, scr, st);
 }
 
 }  // extern "C"
