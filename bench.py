@@ -397,15 +397,23 @@ def plain_leg(adw, torch, prob, name: str, dtype: str, steps: int, warmup: int, 
         (a, b), kms = wave.profile(a, b, psteps, **srcs(0, psteps))
         dom = max((k for k in kms if k in ALG_BYTES_PER_NODE), key=lambda k: kms[k])
         alg_bytes = ALG_BYTES_PER_NODE[dom] * esz * npts
-        achieved = alg_bytes / (kms[dom] / 1e3) / 1e9
         info = wave.info()
+        # the dominant kernel's mean launch duration: a step of one launch (the one-pass
+        # step) is timed by the events around the timed region (launches back to back);
+        # a step of several launches by events around each launch (profile steps)
+        single = info["kernels_per_step"] == 1 and len(kms) == 1
+        kernel_ms = ms / steps if single else kms[dom]
+        achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
         per_node = FUSED_STEP_BYTES_PER_NODE if info["fused_step"] else STEP_BYTES_PER_NODE
         step_gbps = per_node * esz * npts * steps / (ms / 1e3) / 1e9
         res = {"value": round(npts * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 5),
                "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                             "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                            "traffic": load_traffic(name, dom, alg_bytes)},
+                            "traffic": load_traffic(name, dom, alg_bytes),
+                            "kernel_ms": round(kernel_ms, 5),
+                            "timed_by": "timed region (one launch per step)" if single
+                            else "events around each launch"},
                "step_algorithmic_bytes_per_node": per_node * esz,
                "step_algorithmic_GBps": round(step_gbps, 1),
                "step_frac_of_peak": round(step_gbps / HBM_PEAK_GBPS, 4),
@@ -459,8 +467,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--reps", type=int, default=5,
-                    help="timed repetitions of --steps steps; the median is reported")
+    ap.add_argument("--reps", type=int, default=0,
+                    help="timed repetitions of --steps steps; the median is reported "
+                         "(default: at least 5, and at least 200 timed steps in all)")
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
@@ -482,6 +491,10 @@ def main():
     import torch
     import paper_2006_10142_amd as adw
 
+    if args.reps <= 0:
+        # the GPU's clocks move over the first tens of milliseconds of a run (the per-launch
+        # durations dip and recover); enough repetitions put the median past that
+        args.reps = max(5, -(-200 // max(1, args.steps)))
     name, dtype, n = WORKLOADS[args.workload]
     prob = make_problem(args.workload, args.warmup + args.reps * args.steps)
     dev = torch.device("cuda:0")
@@ -529,6 +542,7 @@ def main():
         "hbm_counted": main.get("hbm_counted"),
         "kernel_ms": main["kernel_ms"],
         "repeats_ms_per_step": main["repeats_ms_per_step"],
+        "reps": args.reps,
         "two_pass": two_pass,
         "copy_GBps": round(copy_gbps, 1),
         "create_ms": round(create_ms, 2),

@@ -532,7 +532,7 @@ void fused_plan(adi_wave_s* w)
         w->f_tx = (w->nx + w->f_wt - 1) / w->f_wt;
         w->f_hs = hs;
         w->f_tiles = w->f_tx * ((w->ny + hs - 1) / hs);
-        w->f_grid = w->f_tiles;
+        w->f_grid = (w->f_tiles + 7) / 8 * 8;   // a multiple of 8 for the XCD-aware block map
     }
 }
 

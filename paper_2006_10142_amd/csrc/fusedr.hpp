@@ -6,10 +6,19 @@
 // output rows, and walks down it in bands of 24 x-rows; band k holds the x-rows
 // [r0 - 8 + 24k, r0 + 16 + 24k).
 //   x-role (12 wavefronts): two x-rows each per band, four nodes per lane, on
-//     the window [c0 - 8, c0 + Wt + 8) exactly as fused4.hpp; w, r and u^n of
-//     the central columns go to rings of 56 rows in LDS.  The inputs of band k + 1
-//     are in registers, and those of band k + 2 are requested as soon as band k
-//     is solved.
+//     the window [c0 - 8, c0 + Wt + 8) as fused4.hpp, except for the entry pivots
+//     (below); w, r and u^n of the central columns go to rings of 56 rows in LDS.
+//     The inputs of band k + 1 are in registers, and those of band k + 2 are
+//     requested as soon as band k is solved.
+//   Entry pivots: each lane rebuilds the elimination pivot entering its four
+//     nodes by running the pivot map q -> r / (1 + r (2 - q)) from q = 0 over the
+//     six nodes before them, instead of reading the full-line value.  The map
+//     contracts by its derivative q^2 <= qs^2 (qs < 0.14 for r <= 0.18), so after
+//     six nodes the start value is forgotten to a factor below 1e-11: the pivot is
+//     the full-line one up to rounding.  The window's first two lanes have fewer
+//     nodes before them inside the window and start from zero at its edge: that is
+//     the window's own system, the same truncation as the y-lines', covered by the
+//     bound of fused.hpp (the cut is 9 columns from the first output column).
 //   y-role (4 wavefronts, one thread per column): in the same pass, band k - 1.
 //     The forward elimination of each y-line continues down the strip from row
 //     r0 - 8 (zero carries: the upper cut, 9 rows above the first output row),
@@ -52,19 +61,20 @@ struct FRShared {
 static_assert(sizeof(FRShared) <= 160 * 1024, "the strip ring exceeds the LDS of a workgroup");
 
 // x-role inputs of one band: u^n rows j-1 .. j+kFrXr and r rows j .. j+kFrXr-1
-// of the wavefront's x-rows, with the window-edge values and entry pivots
+// of the wavefront's x-rows, with the window-edge values
 struct FRIn {
     float u[kFrXr + 2][kF4Seg];
     float e[kFrXr + 2];
     float r[kFrXr][kF4Seg];
-    float q[kFrXr];
 };
 
 __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
 {
     __shared__ FRShared sh;
     rec_tap<float>(A.uc, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
-    const int blk = blockIdx.x;
+    // neighbouring strips of a segment row run on one XCD (their halo columns meet
+    // in that XCD's L2): the grid is a multiple of 8 and blocks past the tiles exit
+    const int blk = A.xcd_map ? xcd_band(blockIdx.x) : (int)blockIdx.x;
     if (blk >= A.tiles) return;
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -77,7 +87,10 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
     const int nl = (wt + 2 * kFuKx) / kF4Seg;            // lanes of the x-window
     const long long npts = (long long)nx * ny;
     const int xr_lo = r0 - kFuKy, xr_hi = xr_lo + kFrB * nb;   // x-rows of the strip
-    auto slot = [&](int j) { return (j - xr_lo) % kFrR; };
+    // ring slot of x-row xr_lo + 24 k + i (0 <= i < 56): the band's first slot
+    // (24 k mod 56) is carried from band to band, so no division is needed
+    auto wrap = [](int s) { return s >= kFrR ? s - kFrR : s; };
+    auto next_base = [&](int sb) { return wrap(sb + kFrB); };
 
     // ---- point sources of the strip's x-rows and x-window, in source order
     if (t < 64) {
@@ -111,29 +124,36 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
     const int xw = wv - kFrY;                               // x-role wavefront index
     const bool inwin = lane < nl;
     const int col0 = c0 - kFuKx + lane * kF4Seg;            // first column of the lane
-    const int voff = inwin ? col0 * 4 : kFuOOB;
-    const int seg = (c0 - kFuKx) / kSeg + (lane >> 1);      // its full-line 8-node segment
-    const bool odd = lane & 1;
-    const int qoff = inwin ? seg * 4 : kFuOOB;              // negative segments wrap past the row
-    const int eoff = (lane == 0) ? (c0 - kFuKx - 1) * 4 : (lane == nl - 1) ? (c0 + wt + kFuKx) * 4 : kFuOOB;
-    auto load4 = [&](rsrc_t rs, float (&v)[kF4Seg]) {
-        const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
+    // One buffer resource per plane: a row is reached through the scalar offset, and
+    // whatever lies outside the grid (the lanes or edge values past a wall, whole rows
+    // above or below it, the bands past the strip's last) through a vector offset past
+    // every range, which the range check turns into zeros without a memory access.
+    const int ecol = (lane == 0) ? c0 - kFuKx - 1 : (lane == nl - 1) ? c0 + wt + kFuKx : -1;
+    const int voff = (inwin && col0 >= 0 && col0 < nx) ? col0 * 4 : kFuOOB;
+    const int eoff = (ecol >= 0 && ecol < nx) ? ecol * 4 : kFuOOB;
+    const int plane = (int)(npts * 4);
+    const rsrc_t ru_all = buf(A.uc, plane);
+    const rsrc_t rr_all = buf(A.r, plane);
+    auto load4 = [&](rsrc_t rs, int vo, int so, float (&v)[kF4Seg]) {
+        const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0));
         v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    };
+    auto load1 = [&](rsrc_t rs, int vo, int so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
     };
     // pieces of band k's inputs: u^n row j-1+i (with its window-edge values), and
     // r row j+i with its entry pivots, j = the wavefront's first x-row of band k
     auto load_u = [&](int k, int i, FRIn& P) {
         const int jj = xr_lo + kFrB * k + kFrXr * xw - 1 + i;
-        const bool ok = row_ok(jj);
-        const rsrc_t rs = buf(A.uc + (size_t)(ok ? jj : 0) * nx, ok ? row_bytes : 0);
-        load4(rs, P.u[i]);
-        P.e[i] = bload1<float>(rs, eoff);
+        const bool ok = row_ok(jj) && k < nb;
+        const int so = ok ? jj * row_bytes : 0;
+        load4(ru_all, ok ? voff : kFuOOB, so, P.u[i]);
+        P.e[i] = load1(ru_all, ok ? eoff : kFuOOB, so);
     };
     auto load_r = [&](int k, int i, FRIn& P) {
         const int jj = xr_lo + kFrB * k + kFrXr * xw + i;
-        const bool ok = row_ok(jj);
-        load4(buf(A.r + (size_t)(ok ? jj : 0) * nx, ok ? row_bytes : 0), P.r[i]);
-        P.q[i] = bload1<float>(buf(A.qin + (size_t)(ok ? jj : 0) * A.nseg, ok ? A.nseg * 4 : 0), qoff);
+        const bool ok = row_ok(jj) && k < nb;
+        load4(rr_all, ok ? voff : kFuOOB, ok ? jj * row_bytes : 0, P.r[i]);
     };
     auto load_band = [&](int k, FRIn& P) {
 #pragma unroll
@@ -141,8 +161,9 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
 #pragma unroll
         for (int i = 0; i < kFrXr; ++i) load_r(k, i, P);
     };
-    // the x-rows of band k from P; w and r of the central columns to the ring
-    auto x_band = [&](int k, const FRIn& P) {
+    // the x-rows of band k from P (sb: the band's first ring slot); w and r of the
+    // central columns to the ring
+    auto x_band = [&](int k, int sb, const FRIn& P) {
 #pragma unroll
         for (int it = 0; it < kFrXr; ++it) {
             const int j = xr_lo + kFrB * k + kFrXr * xw + it;
@@ -186,14 +207,20 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
                     }
                 }
             }
-            // entry pivot: the segment's full-line pivot, carried by odd lanes over
-            // the four nodes of the even lane before them
-            float q = P.q[it];
+            // entry pivot of the lane, rebuilt from zero over the six nodes before it
+            // (see the header: within rounding of the full-line pivot; at the window's
+            // first lanes, the window's own system)
+            float q = 0.f;
             {
-                float qo = q;
+                float r1[kF4Seg];
 #pragma unroll
-                for (int e = 0; e < kF4Seg; ++e) (void)pivot_step<float>(dpp<kRowShr + 1>(0.f, rc[e]), qo);
-                q = odd ? qo : q;
+                for (int e = 0; e < kF4Seg; ++e) r1[e] = dpp<kWaveShr1>(0.f, rc[e]);
+                const float r2a = dpp<kWaveShr1>(0.f, r1[2]);
+                const float r2b = dpp<kWaveShr1>(0.f, r1[3]);
+                (void)pivot_step<float>(r2a, q);
+                (void)pivot_step<float>(r2b, q);
+#pragma unroll
+                for (int e = 0; e < kF4Seg; ++e) (void)pivot_step<float>(r1[e], q);
             }
             float Ge[kF4Seg], qe[kF4Seg], Qe[kF4Seg];
             float fG, fQ, H, Ev;
@@ -231,7 +258,7 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
             if (lane >= kFuKx / kF4Seg && lane < nl - kFuKx / kF4Seg) {
                 // indexed in float4 units, so that each lane's four values are one 16-byte
                 // LDS write (contiguous across the wavefront, free of bank conflicts)
-                const int o4 = slot(j) * (kFrS / 4) + (lane - kFuKx / kF4Seg);
+                const int o4 = wrap(sb + kFrXr * xw + it) * (kFrS / 4) + (lane - kFuKx / kF4Seg);
                 reinterpret_cast<float4*>(sh.w)[o4] = make_float4(wout[0], wout[1], wout[2], wout[3]);
                 reinterpret_cast<float4*>(sh.r)[o4] = make_float4(rc[0], rc[1], rc[2], rc[3]);
                 reinterpret_cast<float4*>(sh.u)[o4] = make_float4(uc[0], uc[1], uc[2], uc[3]);
@@ -281,13 +308,12 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
     // b+1's is requested at once, so that it has a whole pass to arrive;
     // then the forward elimination over the band's rows (g and the pivots replace
     // w and r in the ring), and the back substitution with the update
-    auto y_band = [&](int b) {
+    auto y_band = [&](int b, int s0) {
         const int xb = xr_lo + kFrB * b;
         float base[kFrB];                                    // -u^{n-1} of the output rows
 #pragma unroll
         for (int o = 0; o < kFrB; ++o) base[o] = -pu[o];
         load_upd(b + 1);                                     // past the last band: out of range
-        const int s0 = slot(xb);
         // ring slot s (< 2 kFrR) of this column; threads past the strip read a valid
         // column and write nothing, so every thread issues the same memory operations
         const int ty = t < wt ? t : wt - 1;
@@ -314,7 +340,7 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
         // back substitution from the band's last row, up through the look-ahead rows
         // of the band before (rows xb - 8 .. xb - 1; band 0 has none: zeros, and its
         // rows there are above the strip, so nothing is stored for them)
-        const int sl = slot(xb + kFrR - kFuKy);                // = slot(xb - 8)
+        const int sl = wrap(s0 + kFrR - kFuKy);                // the slot of row xb - 8
         const int so0 = (xb - kFuKy) * rowb;
         auto back = [&](auto full_c) {
             constexpr bool kFull = decltype(full_c)::value;
@@ -359,8 +385,10 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
         // b + 1, and a last barrier when the x-role's loop makes an odd count
         load_upd(0);
         __syncthreads();
+        int sb = 0;
         for (int b = 0; b < nb; ++b) {
-            y_band(b);
+            y_band(b, sb);
+            sb = next_base(sb);
             __syncthreads();
         }
         if ((nb & 1) == 0) __syncthreads();
@@ -371,11 +399,14 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
         FRIn PA, PB;
         load_band(0, PA);
         load_band(1, PB);
+        int sb = 0;
         for (int k = 0; k <= nb; k += 2) {
-            if (k < nb) x_band(k, PA);
+            if (k < nb) x_band(k, sb, PA);
+            sb = next_base(sb);
             load_band(k + 2, PA);
             __syncthreads();
-            if (k + 1 < nb) x_band(k + 1, PB);
+            if (k + 1 < nb) x_band(k + 1, sb, PB);
+            sb = next_base(sb);
             load_band(k + 3, PB);
             __syncthreads();
         }

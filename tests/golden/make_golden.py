@@ -27,11 +27,22 @@ HEAD = {
     "c3_recipe_96_f32_inputs":
         "As c3_recipe_96_f64, with the speed field and source values rounded to FP32\n"
         "once; the oracle runs in FP64 on those values (the FP32 parity inputs).",
+    "c3p_pulse_8192_500_f32_inputs":
+        "C3p in full: the C3 speed field on 8192^2 nodes, Gaussian u0 (sigma 0.02), ghost\n"
+        "start, 500 steps, inputs rounded to FP32 once and run in FP64.  Follows eq. (CN1)\n"
+        "as the factored delta form with a per-node coefficient kappa = c^2.  Nodes: rows\n"
+        "and columns where the solver's line partitions meet, the centre row, random nodes\n"
+        "near the pulse and a far-field sample.",
+    "c3_ricker_8192_500_f32_inputs":
+        "C3 in full: 8192^2 speed field in [1, 3], zero initial levels, Ricker point\n"
+        "source (f0 = 10) at the centre node, 500 steps, inputs rounded to FP32 once and\n"
+        "run in FP64.  Follows eq. (CN1) as the factored delta form with point sources f^n.\n"
+        "Nodes: the source row and columns, random nodes near the source, a far-field sample.",
 }
 
 
 def write_run(name: str):
-    p, nodes = cases.CASES[name]()
+    p, nodes = {**cases.CASES, **cases.FULL}[name]()
     _, uc, tr = oracle.run_problem(p)
     lines = [f"# {l}" for l in HEAD[name].splitlines()]
     lines += ["# Written by tests/golden/make_golden.py from the oracle; do not edit by hand.",
@@ -66,8 +77,16 @@ def write_tridiag():
 
 
 if __name__ == "__main__":
+    import sys
     oracle.build()
-    for name in cases.CASES:
-        write_run(name)
-    write_tridiag()
+    # optional names select cases (the full-size ones take minutes each)
+    names = sys.argv[1:] or list(cases.CASES) + list(cases.FULL)
+    for name in names:
+        if name == "tridiag":
+            write_tridiag()
+        else:
+            print("writing", name, flush=True)
+            write_run(name)
+    if not sys.argv[1:]:
+        write_tridiag()
     print("written:", sorted(f for f in os.listdir(HERE) if f.endswith(".txt")))
