@@ -90,7 +90,10 @@ typedef struct {
 
 /* ---------------------------------------------------------------- handle ---- */
 
-/* Create a solver for an nx x ny interior grid with spacing h and time step dt.
+/* Create a solver for an nx x ny interior grid with spacing h and time step dt:
+ * the uniform grid of Sec. 2, eq. (f6) (nodes (i+1) h, (j+1) h; h = 1/(N+1) for
+ * N interior nodes on the unit square), and the coefficient of the line systems
+ * of eq. (CN1) in the split of eqs. (fr1)-(fr2), r = beta kappa / h^2.
  * speed: device field (nx*ny, handle type) of wave speeds (kappa = speed^2),
  *        or NULL to use the constant speed_scalar.  Speeds must be > 0.
  * The per-node coefficient r = dt^2 speed^2 / (2 h^2) is computed on the
@@ -210,8 +213,10 @@ adi_status adi_wave_step_split(adi_wave_t w, int mode, void* u_half, void* u_cur
 /* ------------------------------------------------------ batched simulations -- */
 
 /* Many independent simulations of uneven grid sizes advanced together: each
- * step of the batch advances every simulation by one ADI step (the scheme
- * above on its own grid, spacing, time step and coefficient), with one
+ * step of the batch advances every simulation by one ADI step (the scheme of
+ * Sec. 2, eq. (CN1) split as eqs. (fr1)-(fr2), on its own grid of eq. (f6),
+ * spacing, time step and coefficient; the batching itself is not in the
+ * paper), with one
  * launch per kernel for the whole batch over a work list of (simulation,
  * tile) items.  No sources or receivers. */
 typedef struct adi_batch_s* adi_batch_t;
@@ -277,7 +282,10 @@ adi_status adi_batch_destroy(adi_batch_t b);
 
 /* ------------------------------------------------------- batched line solve -- */
 
-/* Solve `batch` independent tridiagonal systems of size n:
+/* Solve `batch` independent tridiagonal systems of size n: the batched line
+ * solve of Sec. 3.1 (Algorithm 1 solves one such system per grid line, by cyclic
+ * reduction; here any strictly diagonally dominant systems, in any of the
+ * layouts below):
  *   a[k] x[k-1] + b[k] x[k] + c[k] x[k+1] = d[k],  k = 0..n-1
  * (a[0] and c[n-1] are ignored).  Element k of system s is at offset
  * s*sys_stride + k*elem_stride (in elements) in each of a, b, c, d (device,
@@ -287,7 +295,9 @@ adi_status adi_batch_destroy(adi_batch_t b);
  * Contiguous systems (elem_stride == 1, n <= 16384 / 8192 for f64) are solved
  * one per workgroup on chip.  Other layouts take a partition solve in three
  * launches (chunks of 32 rows for f32, 16 for f64, eliminated onto their last
- * row, the chunk-boundary system solved per system, then the chunks again),
+ * row; the chunk-boundary system, solved by a second partition level with up to
+ * 64 threads per system, or by one thread per system when it has more than 1024
+ * rows; then the chunks again),
  * with a library workspace of 6*ceil(n/chunk)*batch values allocated on first
  * use (or growth) and kept; a call that needs more synchronises the stream
  * before it replaces the workspace, and ADI_ENOMEM if that allocation fails.

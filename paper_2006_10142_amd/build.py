@@ -18,8 +18,6 @@ LIB = os.path.join(PKG, "libadiwave.so")
 ARCH = os.environ.get("ADIWAVE_ARCH", "gfx950")
 
 SOURCES = [os.path.join(CSRC, "adiwave.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "line_solver.hpp", "xsweep.hpp", "batch.hpp", "adjoint.hpp")] + \
-    [os.path.join(INCLUDE, "adiwave.h")]
 
 
 def hipcc() -> str:

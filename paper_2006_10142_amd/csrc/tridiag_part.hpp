@@ -20,8 +20,10 @@
 //   k_tri_part_reduce   one thread per (system, chunk): interior elimination,
 //                       then the interface equations' coefficients from the
 //                       (y, v, w) at the first and last interior rows;
-//   k_tri_part_iface    one thread per system: forms and solves the interface
-//                       system, writes X_p into d and into the workspace;
+//   k_tri_part_iface2   the interface system, several threads per system (a
+//                       second partition level in registers and LDS), writes X_p
+//                       into d and into the workspace (k_tri_part_iface, one
+//                       thread per system, for interface systems too long for it);
 //   k_tri_part_expand   one thread per (system, chunk): the interior again with
 //                       X_{p-1}, X_p known, writes the interior of d.
 // An empty interior (a chunk of one row) is the limit case: its first-row
@@ -223,6 +225,165 @@ __global__ void __launch_bounds__(kTpIfaceThreads) k_tri_part_iface(TriArgs<T> A
     }
 }
 
+// The interface system in parallel: TPS threads per system (a power of two, 256 /
+// TPS systems per workgroup), each owning a group of L <= kTpL consecutive interface
+// rows.  The same partition once more, in registers and LDS: every group's last row
+// carries a second-level unknown Z_i; the group's other rows are eliminated onto
+// Z_{i-1} and Z_i, which leaves one equation per group (its Schur complement row),
+// and these G <= TPS equations per system are solved by Thomas in LDS by one thread
+// of the system.  Each thread then recovers its group's rows from Z_{i-1} and Z_i
+// and writes them into slot 2 of the records and into d.  Lanes take neighbouring
+// systems first, so the record rows load in runs of 256 / TPS values.
+constexpr int kTpL = 16;            // interface rows per thread at most
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tri_part_iface2(TriArgs<T> A, int P, int M, int TPS, T* __restrict__ red)
+{
+    __shared__ T s_c[256];                         // C of each group's last row
+    __shared__ T s_a[256], s_b[256], s_cc[256], s_d[256], s_z[256];   // second-level rows, Z
+    const int spw = 256 / TPS;                     // systems per workgroup
+    const int t = threadIdx.x;
+    const int sl = t % spw, gi = t / spw;          // system in the workgroup, group
+    const long long nb = A.batch;
+    const long long s = (long long)blockIdx.x * spw + sl;
+    const long long q = (long long)P * nb;
+    const int L = (P + TPS - 1) / TPS;
+    const int G = (P + L - 1) / L;                 // groups holding rows
+    const int p0 = gi * L;
+    const int np = (s < nb && gi < G) ? min(P, p0 + L) - p0 : 0;   // rows of the group
+    const int li = np - 1;                         // interior rows (np - 1), -1 if none
+    const int slot = sl * TPS + gi;                // this group's second-level row
+    T ra[kTpL], rb[kTpL], rc[kTpL], rd[kTpL];
+#pragma unroll
+    for (int k = 0; k < kTpL; ++k) {
+        if (k < np) {
+            const T* g = red + (long long)(p0 + k) * nb + s;
+            ra[k] = g[0];
+            rb[k] = g[q] - g[3 * q];
+            rc[k] = g[4 * q];
+            rd[k] = g[2 * q] - g[5 * q];
+        }
+    }
+    if (p0 == 0) ra[0] = T(0);
+    // the group's last row (selected with static indices, so the arrays stay in registers)
+    T ar = T(0), br = T(0), cr = T(0), dr = T(0);
+#pragma unroll
+    for (int k = 0; k < kTpL; ++k)
+        if (k == li) { ar = ra[k]; br = rb[k]; cr = rc[k]; dr = rd[k]; }
+    s_c[t] = cr;
+    __syncthreads();
+    const T cprv = (gi > 0 && np > 0) ? s_c[t - spw] : T(0);   // C of the previous group's last row
+    // interior elimination: y, v, w (against D, A e_first, C e_last) at the first and
+    // last interior rows; an empty interior gives the limit triples
+    T yf = T(0), vf = T(0), wf = T(-1), yl = T(0), vl = T(-1), wl = T(0);
+    if (li > 0) {
+        T cprev = T(0), dprev = T(0), vprev = T(0);
+        T ce[kTpL], de[kTpL], ve[kTpL];
+#pragma unroll
+        for (int k = 0; k < kTpL - 1; ++k) {
+            if (k < li) {
+                const T ak = ra[k];
+                const T m = T(1) / (rb[k] - ak * cprev);
+                const bool last = k == li - 1;
+                if (last) wl = rc[k] * m;
+                cprev = last ? T(0) : rc[k] * m;
+                dprev = (rd[k] - ak * dprev) * m;
+                vprev = (k == 0 ? ak : -ak * vprev) * m;
+                ce[k] = cprev;
+                de[k] = dprev;
+                ve[k] = vprev;
+            }
+        }
+        yl = dprev;
+        vl = vprev;
+        T y = yl, v = vl, w = wl;
+#pragma unroll
+        for (int k = kTpL - 3; k >= 0; --k) {
+            if (k < li - 1) {
+                y = de[k] - ce[k] * y;
+                v = ve[k] - ce[k] * v;
+                w = -ce[k] * w;
+            }
+        }
+        yf = y;
+        vf = v;
+        wf = w;
+    }
+    // this group's Schur row, and the part of the previous group's row that comes
+    // from this group's first interior row
+    if (np > 0) {
+        s_a[slot] = -ar * vl;
+        s_b[slot] = br - ar * wl;
+        s_d[slot] = dr - ar * yl;
+        s_cc[slot] = T(0);
+    }
+    __syncthreads();
+    if (np > 0 && gi > 0) {
+        s_b[slot - 1] -= cprv * vf;
+        s_cc[slot - 1] = -cprv * wf;
+        s_d[slot - 1] -= cprv * yf;
+    }
+    __syncthreads();
+    // second-level Thomas, one thread per system
+    if (gi == 0 && s < nb) {
+        const int base = sl * TPS;
+        T cp = T(0), dp = T(0);
+        for (int g = 0; g < G; ++g) {
+            const T m = T(1) / (s_b[base + g] - s_a[base + g] * cp);
+            cp = s_cc[base + g] * m;
+            dp = (s_d[base + g] - s_a[base + g] * dp) * m;
+            s_cc[base + g] = cp;
+            s_z[base + g] = dp;
+        }
+        T z = dp;
+        for (int g = G - 2; g >= 0; --g) {
+            z = s_z[base + g] - s_cc[base + g] * z;
+            s_z[base + g] = z;
+        }
+    }
+    __syncthreads();
+    if (np <= 0) return;
+    const T zl = gi > 0 ? s_z[slot - 1] : T(0);
+    const T zh = s_z[slot];
+    // the group's rows: its last row is Z_i; the interior from Z_{i-1}, Z_i
+    T x[kTpL];
+    if (li > 0) {
+        T cprev = T(0), dprev = zl;
+        T ce[kTpL], de[kTpL];
+#pragma unroll
+        for (int k = 0; k < kTpL - 1; ++k) {
+            if (k < li) {
+                const T ak = ra[k];
+                const T m = T(1) / (rb[k] - ak * cprev);
+                const bool last = k == li - 1;
+                const T dk = last ? rd[k] - rc[k] * zh : rd[k];
+                cprev = last ? T(0) : rc[k] * m;
+                dprev = (dk - ak * dprev) * m;
+                ce[k] = cprev;
+                de[k] = dprev;
+            }
+        }
+        T xv = T(0);
+#pragma unroll
+        for (int k = kTpL - 2; k >= 0; --k) {
+            if (k < li) {
+                xv = de[k] - ce[k] * xv;
+                x[k] = xv;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kTpL; ++k) {
+        if (k < np) {
+            const int p = p0 + k;
+            const T xk = k == li ? zh : x[k];
+            red[2 * q + (long long)p * nb + s] = xk;
+            const int r = min(A.n, (p + 1) * M) - 1;
+            A.d[s * A.sys_stride + (long long)r * A.elem_stride] = xk;
+        }
+    }
+}
+
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_tri_part_expand(TriArgs<T> A, int P, const T* __restrict__ red)
 {
@@ -279,9 +440,20 @@ void launch_tri_part(const TriArgs<T>& t, T* red, hipStream_t st)
     const int P = (t.n + M - 1) / M;
     const long long work = (long long)P * t.batch;
     const unsigned g1 = (unsigned)((work + 255) / 256);
-    const unsigned g2 = (unsigned)((t.batch + kTpIfaceThreads - 1) / kTpIfaceThreads);
     hipLaunchKernelGGL((k_tri_part_reduce<T, M>), dim3(g1), dim3(256), 0, st, t, P, red);
-    hipLaunchKernelGGL((k_tri_part_iface<T>), dim3(g2), dim3(kTpIfaceThreads), 0, st, t, P, M, red);
+    // threads per system for the parallel interface solve: the least power of two
+    // whose groups of at most kTpL rows cover P (at most 64); longer interface
+    // systems take the serial solve, one thread per system
+    int tps = 1;
+    while (tps < 64 && (long long)tps * kTpL < P) tps *= 2;
+    if ((long long)tps * kTpL >= P) {
+        const long long spw = 256 / tps;
+        const unsigned g2 = (unsigned)((t.batch + spw - 1) / spw);
+        hipLaunchKernelGGL((k_tri_part_iface2<T>), dim3(g2), dim3(256), 0, st, t, P, M, tps, red);
+    } else {
+        const unsigned g2 = (unsigned)((t.batch + kTpIfaceThreads - 1) / kTpIfaceThreads);
+        hipLaunchKernelGGL((k_tri_part_iface<T>), dim3(g2), dim3(kTpIfaceThreads), 0, st, t, P, M, red);
+    }
     hipLaunchKernelGGL((k_tri_part_expand<T, M>), dim3(g1), dim3(256), 0, st, t, P, (const T*)red);
 }
 

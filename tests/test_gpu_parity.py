@@ -84,6 +84,12 @@ STRIDED = {  # layout: (n, batch, sys_stride, elem_stride)
     "n1": (1, 9, 2, 1),
     "n2": (2, 9, 1, 9),
     "long_strided": (9001, 2, 1, 2),
+    # interface systems of 256 (FP32) / 512 (FP64) rows: the parallel interface solve with
+    # 16 / 32 threads per system
+    "interleaved_8192": (8192, 64, 1, 64),
+    # interface systems longer than the parallel solve takes (1250 / 2500 rows): the
+    # serial interface solve
+    "very_long_strided": (40000, 2, 1, 2),
 }
 
 
