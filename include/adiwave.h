@@ -161,8 +161,11 @@ adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_c
  * grad_traces: device, nsteps x rec->count values of dJ/d(trace).
  * grad_kappa: device nx*ny, overwritten with dJ/dkappa.
  * grad_amp: device nsteps x f->count, overwritten with dJ/d(source value),
- * or NULL.  Each segment between checkpoints is recomputed once (allocates
- * 2 * checkpoint_every fields on first use or growth). */
+ * or NULL.  Each segment between checkpoints is recomputed once, on a second
+ * stream the library creates for the handle, overlapping the reverse pass of the
+ * segment after it (allocates 4 * checkpoint_every fields and a copy of the
+ * y-chunk planes on first use or growth); the call returns with all its work
+ * ordered on the handle's stream. */
 adi_status adi_adjoint_backward(adi_wave_t w, unsigned long long record, const adi_source* f,
                                 const adi_receivers* rec, const void* grad_traces,
                                 void* grad_kappa, void* grad_amp);

@@ -16,7 +16,9 @@
 // and dt^2 Lap(kappa mu) = 2 (5-point sum of t - 4 t).  d^k is recovered from
 // the stored levels as u^{k+1} - 2u^k + u^{k-1}; w^k is stored by the
 // recomputation.  Levels are checkpointed every K steps by the forward run;
-// each segment is recomputed once, in reverse segment order.
+// each segment is recomputed once, in reverse segment order, on a second stream
+// into one of two halves of the segment storage, so that the recomputation of
+// segment c - 1 runs while the reverse pass of segment c does (events order them).
 
 namespace adw {
 
@@ -154,10 +156,16 @@ struct adi_adjoint_s {
     unsigned long long record = 0;   // id of the stored forward run (0: none, or invalidated)
     size_t field = 0;            // bytes of one field
     void* ck = nullptr;          // 2 * ncheck fields: (u^{k0-1}, u^{k0}) of every segment
-    void* seg = nullptr;         // 2 * K fields: levels u^{k0+1..k0+K}, then w^{k0..k0+K-1}
+    void* seg = nullptr;         // 2 x 2K fields, one half per segment parity: levels
+                                 // u^{k0+1..k0+K}, then w^{k0..k0+K-1}
     void* work = nullptr;        // 6 fields: forward levels (2), lambda (2), t, z
     void* rmap = nullptr;        // nx*ny ints + receiver count ints: receiver map of the reverse pass
-    size_t ck_cap = 0, seg_cap = 0, work_cap = 0, rmap_cap = 0;
+    void* ysum = nullptr;        // y-chunk planes and interface values of the recomputation stream
+    size_t ck_cap = 0, seg_cap = 0, work_cap = 0, rmap_cap = 0, ysum_cap = 0;
+    // the recomputation of segment c - 1 runs on its own stream while the reverse
+    // pass of segment c runs on the handle's stream
+    hipStream_t rs = nullptr;
+    hipEvent_t ev_start = nullptr, ev_rc[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -175,11 +183,26 @@ void adjoint_invalidate(adi_wave_s* w)
 void adjoint_free(adi_adjoint_s* a)
 {
     if (!a) return;
+    if (a->rs) (void)hipStreamSynchronize(a->rs);
     if (a->ck) (void)hipFree(a->ck);
     if (a->seg) (void)hipFree(a->seg);
     if (a->work) (void)hipFree(a->work);
     if (a->rmap) (void)hipFree(a->rmap);
+    if (a->ysum) (void)hipFree(a->ysum);
+    for (hipEvent_t e : {a->ev_start, a->ev_rc[0], a->ev_rc[1], a->ev_rev[0], a->ev_rev[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (a->rs) (void)hipStreamDestroy(a->rs);
     delete a;
+}
+
+// the recomputation stream and its events, created on first use (default priority)
+adi_status adjoint_streams(adi_adjoint_s* a)
+{
+    if (a->rs) return ADI_OK;
+    ADI_HIP(hipStreamCreateWithFlags(&a->rs, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&a->ev_start, &a->ev_rc[0], &a->ev_rc[1], &a->ev_rev[0], &a->ev_rev[1]})
+        ADI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return ADI_OK;
 }
 
 adi_status grow(void** p, size_t* cap, size_t need)
@@ -295,7 +318,16 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     const size_t F = a->field;
     const int S = a->nsteps, K = a->K;
     const long long npts = (long long)w->nx * w->ny;
-    if (adi_status s = grow(&a->seg, &a->seg_cap, 2 * (size_t)K * F)) return s;
+    if (adi_status s = grow(&a->seg, &a->seg_cap, 4 * (size_t)K * F)) return s;
+    if (adi_status s = adjoint_streams(a)) return s;
+    // the recomputation's y-chunk workspace: the handle's planes (the static interface
+    // coefficients among them) copied, so the two streams never share scratch
+    const size_t es = sizeof(T);
+    const size_t nsum = (size_t)kSummaryPlanes * w->K * w->nxp, nX = (size_t)w->K * w->nx;
+    if (adi_status s = grow(&a->ysum, &a->ysum_cap, (nsum + nX) * es)) return s;
+    void* sum2 = a->ysum;
+    void* X2 = static_cast<char*>(a->ysum) + nsum * es;
+    ADI_HIP(hipMemcpyAsync(sum2, w->sum, nsum * es, hipMemcpyDeviceToDevice, w->stream));
     char* work = static_cast<char*>(a->work);
     T* lam1 = reinterpret_cast<T*>(work + 2 * F);
     T* lam2 = reinterpret_cast<T*>(work + 3 * F);
@@ -341,39 +373,69 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     ua.c1 = (T)(w->dt * w->dt / (w->h * w->h));
     ua.c2 = (T)(beta / (w->h * w->h));
     const dim3 ug((w->nx + 63) / 64, (w->ny + 3) / 4);
-    void* wkeep = w->w;
-    for (int c = a->ncheck - 1; c >= 0; --c) {
+    // segment c: levels L[0..n+1] = u^{k0-1} .. u^{k0+n} (L[0], L[1] the checkpoint,
+    // the others in half c % 2 of the segment storage) and w^{k0..k0+n-1}
+    auto lev = [&](int c, int m) -> void* {
+        if (m < 2) return static_cast<char*>(a->ck) + (2 * (size_t)c + m) * F;
+        return seg + (2 * (size_t)K * (c & 1) + (m - 2)) * F;
+    };
+    auto wst = [&](int c, int m) -> void* { return seg + (2 * (size_t)K * (c & 1) + K + m) * F; };
+    // recompute segment c on the recomputation stream (the same kernels, in the same
+    // order, as the forward run: the levels come out bit for bit)
+    auto recompute = [&](int c) -> adi_status {
         const int k0 = 1 + c * K;
         const int n = std::min(K, S - c * K);
-        // levels L[0..n+1] = u^{k0-1} .. u^{k0+n}; L[0], L[1] are the checkpoint
-        auto lev = [&](int m) -> void* {
-            if (m < 2) return static_cast<char*>(a->ck) + (2 * (size_t)c + m) * F;
-            return seg + (size_t)(m - 2) * F;
-        };
-        auto wst = [&](int m) -> void* { return seg + ((size_t)K + m) * F; };
-        for (int m = 0; m < n; ++m) {
+        hipStream_t s1 = w->stream;
+        void *wkeep = w->w, *skeep = w->sum, *xkeep = w->X;
+        w->stream = a->rs;
+        w->sum = sum2;
+        w->X = X2;
+        adi_status s = ADI_OK;
+        for (int m = 0; m < n && s == ADI_OK; ++m) {
             adi_source sc = src_at(f, k0 - 1 + m, sizeof(T));
-            w->w = wst(m);                       // keep w^k of this step
-            adi_status s = queue_solve<T>(w, lev(m + 1), lev(m), lev(m + 2), T(2), T(-1), f ? &sc : nullptr, 0,
-                                          T(1), nullptr);
-            w->w = wkeep;
-            if (s != ADI_OK) return s;
+            w->w = wst(c, m);                    // keep w^k of this step
+            s = queue_solve<T>(w, lev(c, m + 1), lev(c, m), lev(c, m + 2), T(2), T(-1), f ? &sc : nullptr, 0,
+                               T(1), nullptr);
         }
+        w->stream = s1;
+        w->w = wkeep;
+        w->sum = skeep;
+        w->X = xkeep;
+        return s;
+    };
+    // the recomputation stream starts after everything queued so far (the checkpoints,
+    // the copy of the planes); segment c - 1 is recomputed into the half that segment
+    // c + 1 used, once the reverse pass of c + 1 is done with it
+    ADI_HIP(hipEventRecord(a->ev_start, w->stream));
+    ADI_HIP(hipStreamWaitEvent(a->rs, a->ev_start, 0));
+    const int last = a->ncheck - 1;
+    if (adi_status s = recompute(last)) return s;
+    ADI_HIP(hipEventRecord(a->ev_rc[last & 1], a->rs));
+    for (int c = last; c >= 0; --c) {
+        if (c >= 1) {
+            if (c + 1 <= last) ADI_HIP(hipStreamWaitEvent(a->rs, a->ev_rev[(c + 1) & 1], 0));
+            if (adi_status s = recompute(c - 1)) return s;
+            ADI_HIP(hipEventRecord(a->ev_rc[(c - 1) & 1], a->rs));
+        }
+        ADI_HIP(hipStreamWaitEvent(w->stream, a->ev_rc[c & 1], 0));
+        const int k0 = 1 + c * K;
+        const int n = std::min(K, S - c * K);
         for (int m = n - 1; m >= 0; --m) {
             const int k = k0 + m;
             if (adi_status s = queue_ysolve_scaled<T>(w, lam1, zz)) return s;
             if (adi_status s = queue_xsolve<T>(w, zz, tt)) return s;
             ua.t = tt; ua.z = zz; ua.lam1 = lam1; ua.lam2 = lam2;
-            ua.um = static_cast<const T*>(lev(m));
-            ua.uk = static_cast<const T*>(lev(m + 1));
-            ua.up = static_cast<const T*>(lev(m + 2));
-            ua.wk = static_cast<const T*>(wst(m));
+            ua.um = static_cast<const T*>(lev(c, m));
+            ua.uk = static_cast<const T*>(lev(c, m + 1));
+            ua.up = static_cast<const T*>(lev(c, m + 2));
+            ua.wk = static_cast<const T*>(wst(c, m));
             ua.rvals = (k >= 2 && nrec > 0) ? gt + (size_t)(k - 2) * nrec : nullptr;
             ua.gout = nsrc > 0 ? static_cast<T*>(grad_amp) + (size_t)(k - 1) * nsrc : nullptr;
             hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
             ADI_LAUNCHED("adjoint_update");
             std::swap(lam1, lam2);
         }
+        ADI_HIP(hipEventRecord(a->ev_rev[c & 1], w->stream));
     }
     return ADI_OK;
 }
