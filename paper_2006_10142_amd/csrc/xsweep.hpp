@@ -380,8 +380,18 @@ __device__ __forceinline__ T bload1(rsrc_t rs, int voff)
 // LDS of one line group
 constexpr int kStripSrc = 32;   // point sources staged per strip (more: read per row)
 
+// FP64 line groups of 1024 threads keep the row above the one being solved (u^n,
+// row j-1) in LDS instead of registers, and request the next row of r only after
+// the scans: with both in registers the group needs more than the 128 VGPRs a
+// 1024-thread workgroup allows, and the spills went to scratch memory (twice the
+// kernel's algorithmic traffic).  Each thread writes and reads only its own LDS
+// slots, so no barrier is involved.
+template <typename T, int TR>
+constexpr bool kUmLds = sizeof(T) == 8 && TR >= 1024;
+
 template <typename T, int TR, bool FUSE>
 struct XShared {
+    T um[kUmLds<T, TR> ? kSeg * TR : 1];     // row j-1 of u^n per lane (see kUmLds)
     T halo[2][2][TR];                        // segment edges of two rows: [row parity][first/last][seg]
     T totf[2][TR / 64][2];                   // wavefront totals by row parity: forward (a, b)
     T totb[2][TR / 64][3];                   //   and backward (a0, a1, b)
@@ -499,6 +509,10 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
 
     if constexpr (STENCIL) stage_sources<T, TR, FUSE>(A, j0, RS, t, sh);
     load_u(j0 - 1, ua);
+    if constexpr (kUmLds<T, TR>) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) sh.um[e * TR + t] = ua[e];
+    }
     load_u(j0, ub);
     load_u(j0 + 1, uc0);
     load_rq(j0, ra, qa);
@@ -513,7 +527,9 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
         const bool live = j < ny;
         // prefetch
         load_u(live ? j + 2 : -1, u2);
-        load_rq(live ? j + 1 : -1, rn, qn);
+        // (FP64 line groups of 1024 threads request row j+1 of r after the scans
+        // instead, where fewer registers are live: see kUmLds)
+        if constexpr (!kUmLds<T, TR>) load_rq(live ? j + 1 : -1, rn, qn);
         // edges of row j+1 (resident since the previous row) for the next row's stencil;
         // the other parity buffer is read below, and row j-1's readers passed a barrier
         if (live && j + 1 < ny) put_halo(j + 1, u1);
@@ -527,15 +543,24 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
             // rho_scale * 2 r x == (2 rho_scale) * (r x) exactly: 2 and rho_scale
             // (1 or 1/2) are powers of two
             const T s2 = T(2) * A.rho_scale;
+            T umv[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) umv[e] = kUmLds<T, TR> ? sh.um[e * TR + t] : um[e];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if constexpr (STENCIL) {
                     const T uw = (e == 0) ? west0 : uc[e - 1];
                     const T ue = (e == E - 1) ? eastL : uc[e + 1];
-                    rho[e] = s2 * (rc[e] * (((uw + ue) + (um[e] + u1[e])) - T(4) * uc[e]));
+                    rho[e] = s2 * (rc[e] * (((uw + ue) + (umv[e] + u1[e])) - T(4) * uc[e]));
                 } else {
                     rho[e] = A.rho_scale * uc[e];
                 }
+            }
+            // row j is the next row's row j-1: to LDS now, so it is not live in registers
+            // across this row's scans
+            if constexpr (kUmLds<T, TR>) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) sh.um[e * TR + t] = uc[e];
             }
         }
         if constexpr (STENCIL) {
@@ -569,10 +594,14 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
         // end of the line (e >= L) have r = 0 and rho = 0 (zero-filled loads): they
         // get m = 1, q = 0, G = 0 and add nothing to the segment's maps, so no
         // branch is needed.  A lane without nodes keeps the identity map (0, 1).
-        T Ge[E], qe[E], Qe[E];
+        // (the running products of q are not kept per node: the back substitution forms
+        // them again, with the same multiplications in the same order, which keeps the
+        // FP64 line group of 1024 threads within its 128 registers)
+        T Ge[E], qe[E];
         T fG, fQ, H, Ev;
         {
             T q = qc, Gv = T(0), Qv = T(1), h = T(0), ee = T(0);
+            T QL = T(1);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T m = pivot_step<T>(rc[e], q);
@@ -583,13 +612,14 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
                 ee = fma_rn(P, Qv, ee);
                 Ge[e] = Gv;
                 qe[e] = q;
-                Qe[e] = Qv;
+                if (e == L - 1) QL = Qv;
             }
             fG = Gv; fQ = act ? Qv : T(1); H = h; Ev = ee;
             if (L < E) {                              // partial segment: carry the last node's map
 #pragma unroll
                 for (int e = 0; e < E; ++e)
-                    if (e == L - 1) { fG = Ge[e]; fQ = Qe[e]; }
+                    if (e == L - 1) fG = Ge[e];
+                fQ = QL;
             }
         }
 
@@ -639,13 +669,21 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
             dbelow = fma_rn(yb, D, fma_rn(ya1, C, ya0));
         }
 
+        if constexpr (kUmLds<T, TR>) load_rq(live ? j + 1 : -1, rn, qn);
+
         // back substitution, store (tail nodes give 0 and feed q = 0 into the last node)
         T wout[E];
         {
+            T Qv = T(1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                Qv = qe[e] * Qv;
+                Ge[e] = fma_rn(Qv, gin, Ge[e]);
+            }
             T x = dbelow;
 #pragma unroll
             for (int e = E - 1; e >= 0; --e) {
-                x = fma_rn(qe[e], x, fma_rn(Qe[e], gin, Ge[e]));
+                x = fma_rn(qe[e], x, Ge[e]);
                 wout[e] = x;
             }
             if constexpr (VEC) bstore8<T>(buf(A.w + (size_t)(live ? j : 0) * nx, live ? row_bytes : 0), voff, wout);
@@ -694,7 +732,8 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
         qa = qb;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            ua[e] = ub[e]; ub[e] = uc0[e]; uc0[e] = ud[e]; ra[e] = rb[e];
+            if constexpr (!kUmLds<T, TR>) ua[e] = ub[e];
+            ub[e] = uc0[e]; uc0[e] = ud[e]; ra[e] = rb[e];
         }
     }
 }
