@@ -354,6 +354,7 @@ XArgs<T> make_x(const adi_wave_s* w, const void* u, const adi_source* f, int k, 
     a.ny = w->ny;
     a.nseg = w->nseg;
     a.rows_per_strip = w->xp.fuse ? w->xp.frs : w->xp.rs;
+    a.xcd = a.rows_per_strip <= kXcdStripRows;
     a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && aligned16(u) && aligned16(w->r) &&
             aligned16(w->w);
     a.sum = static_cast<T*>(w->sum);
@@ -397,10 +398,7 @@ YArgs<T> make_y(const adi_wave_s* w, const void* u, const void* v, void* out, T 
 
 int x_grid(const adi_wave_s* w)
 {
-    const int g = x_groups_per_wg(w->xp.tr);
-    const int rs = w->xp.fuse ? w->xp.frs : w->xp.rs;
-    const int strips = (w->ny + rs - 1) / rs;
-    return (strips + g - 1) / g;
+    return xsweep_grid(w->ny, w->xp.fuse ? w->xp.frs : w->xp.rs, x_groups_per_wg(w->xp.tr));
 }
 
 // Queue one solve: x-sweep of `u` (with sources f at step k) then the y-chain

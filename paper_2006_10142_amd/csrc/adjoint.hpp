@@ -39,6 +39,7 @@ struct AdjArgs {
     // point terms of the step (see k_adjoint_points), folded into the same launch:
     const int* rmap;     // per node: first receiver of the node (>= nrec: none)
     const int* rnext;    // per receiver: next receiver of the same node, or -1
+    const int* rrow;     // per row: nonzero when a receiver lies in it (rows without skip rmap)
     const T* rvals;      // this step's receiver values (NULL: none)
     const int* sidx;     // source nodes (NULL: no source gradient)
     T* gout;             // dJ/d(source value) of this step
@@ -87,11 +88,96 @@ __global__ void __launch_bounds__(256) k_adjoint_update(AdjArgs<T> A)
     A.lam2[p] = lam;
 }
 
+// The same update with 16 bytes of every field per thread (4 FP32 / 2 FP64 nodes
+// of one row; nx a multiple of that, 16-byte aligned fields), rows in XCD bands.  Every load is
+// independent of the others; the x-neighbours across a lane's edges come from the
+// neighbouring lanes by a wavefront shift, and from memory only at the
+// wavefront's two ends.  The receiver map is read only by workgroups whose part of
+// the row holds a receiver.  The expressions are those of k_adjoint_update.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adjoint_update_v(AdjArgs<T> A)
+{
+    using V = Vec16<T>;
+    constexpr int N = V::N;
+    using VT = typename V::type;
+    const int lane = threadIdx.x & 63;
+    const int nx = A.nx, ny = A.ny;
+    // work index (row j, column block bx) of this workgroup: the workgroups of one XCD
+    // take a contiguous band of rows, so the rows above and below a row are read
+    // through the same L2 (the grid is a multiple of 8; workgroups past the last row exit)
+    const int gx = (nx / N + 255) / 256;
+    const int wk = xcd_band(blockIdx.x);
+    const int j = wk / gx, bx = wk - j * gx;
+    if (j >= ny) return;
+    const int i0 = (bx * 256 + threadIdx.x) * N;
+    if (A.sidx && blockIdx.x == 0) {
+        for (int s = threadIdx.x; s < A.nsrc; s += 256) {
+            const int id = A.sidx[s];
+            A.gout[s] = (id >= 0 && id < A.npts) ? A.tau2 * A.t[id] / A.r[id] : T(0);
+        }
+    }
+    const bool in = i0 < nx;
+    const bool hn = in && j > 0, hs = in && j + 1 < ny;
+    const size_t snx = (size_t)nx;
+    const size_t p = (size_t)j * snx + (in ? i0 : 0);
+    auto ld = [&](const T* a, size_t q, bool ok, T (&v)[N]) {
+        if (ok) V::unpack(*reinterpret_cast<const VT*>(a + q), v);
+        else {
+#pragma unroll
+            for (int e = 0; e < N; ++e) v[e] = T(0);
+        }
+    };
+    T tc[N], tn[N], ts[N], uc[N], un[N], us[N], pc[N], pn[N], ps[N], mc[N], mn[N], ms[N];
+    T wc[N], zc[N], rc[N], l1[N], l2[N], gc[N];
+    ld(A.t, p, in, tc); ld(A.t, p - snx, hn, tn); ld(A.t, p + snx, hs, ts);
+    ld(A.uk, p, in, uc); ld(A.uk, p - snx, hn, un); ld(A.uk, p + snx, hs, us);
+    ld(A.up, p, in, pc); ld(A.up, p - snx, hn, pn); ld(A.up, p + snx, hs, ps);
+    ld(A.um, p, in, mc); ld(A.um, p - snx, hn, mn); ld(A.um, p + snx, hs, ms);
+    ld(A.wk, p, in, wc); ld(A.z, p, in, zc); ld(A.r, p, in, rc);
+    ld(A.lam1, p, in, l1); ld(A.lam2, p, in, l2); ld(A.grad, p, in, gc);
+    // values beyond the wavefront's first and last lanes
+    const bool le = lane == 0 && in && i0 > 0, re = lane == 63 && in && i0 + N < nx;
+    const T tle = le ? A.t[p - 1] : T(0), tre = re ? A.t[p + N] : T(0);
+    const T ule = le ? A.uk[p - 1] : T(0), ure = re ? A.uk[p + N] : T(0);
+    const T wle = le ? A.wk[p - 1] : T(0), wre = re ? A.wk[p + N] : T(0);
+    const T tl = dpp<kWaveShr1>(tle, tc[N - 1]), tr = dpp<kWaveShl1>(tre, tc[0]);
+    const T ul = dpp<kWaveShr1>(ule, uc[N - 1]), ur = dpp<kWaveShl1>(ure, uc[0]);
+    const T wl = dpp<kWaveShr1>(wle, wc[N - 1]), wr = dpp<kWaveShl1>(wre, wc[0]);
+    const bool row_rec = A.rvals && A.rrow[j] != 0;
+    if (!in) return;
+    T go[N], lo[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const T tw = e == 0 ? tl : tc[e - 1], te = e == N - 1 ? tr : tc[e + 1];
+        const T uw = e == 0 ? ul : uc[e - 1], ue = e == N - 1 ? ur : uc[e + 1];
+        const T ww = e == 0 ? wl : wc[e - 1], we = e == N - 1 ? wr : wc[e + 1];
+        const T s5t = ((tw + te) + (tn[e] + ts[e])) - T(4) * tc[e];
+        const T s5u = ((uw + ue) + (un[e] + us[e])) - T(4) * uc[e];
+        const T sxw = (ww + we) - T(2) * wc[e];
+        const T dn = hn ? (pn[e] - T(2) * un[e]) + mn[e] : T(0);
+        const T dc = (pc[e] - T(2) * uc[e]) + mc[e];
+        const T ds = hs ? (ps[e] - T(2) * us[e]) + ms[e] : T(0);
+        const T syd = (dn + ds) - T(2) * dc;
+        const T mu = tc[e] / rc[e];
+        const T nu = zc[e] / rc[e];
+        go[e] = gc[e] + (mu * (A.c1 * s5u + A.c2 * sxw) + nu * (A.c2 * syd));
+        T lam = (T(2) * l1[e] - l2[e]) + T(2) * s5t;
+        if (row_rec) {
+            const int j0 = A.rmap[p + e];
+            for (int k = j0 < A.nrec ? j0 : -1; k >= 0; k = A.rnext[k]) lam += A.rvals[k];
+        }
+        lo[e] = lam;
+    }
+    *reinterpret_cast<VT*>(A.grad + p) = V::pack(go);
+    *reinterpret_cast<VT*>(A.lam2 + p) = V::pack(lo);
+}
+
 // receiver map of the reverse pass: rmap[node] = smallest receiver index at the
 // node (rmap filled beforehand with a value above every index, so that a node
-// without receivers keeps it), rnext[k] = next receiver at the same node or -1
+// without receivers keeps it), rnext[k] = next receiver at the same node or -1,
+// rrow[row] = 1 for every row that holds a receiver (rrow zeroed beforehand)
 __global__ void __launch_bounds__(256) k_receiver_map(const int* __restrict__ ridx, int nrec, long long npts,
-                                                      int* rmap, int* rnext)
+                                                      int nx, int* rmap, int* rnext, int* rrow)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= nrec) return;
@@ -99,6 +185,7 @@ __global__ void __launch_bounds__(256) k_receiver_map(const int* __restrict__ ri
     int nxt = -1;
     if (id >= 0 && id < npts) {
         atomicMin(&rmap[id], k);
+        rrow[id / nx] = 1;
         for (int j = k + 1; j < nrec; ++j)
             if (ridx[j] == id) { nxt = j; break; }
     }
@@ -159,7 +246,7 @@ struct adi_adjoint_s {
     void* seg = nullptr;         // 2 x 2K fields, one half per segment parity: levels
                                  // u^{k0+1..k0+K}, then w^{k0..k0+K-1}
     void* work = nullptr;        // 6 fields: forward levels (2), lambda (2), t, z
-    void* rmap = nullptr;        // nx*ny ints + receiver count ints: receiver map of the reverse pass
+    void* rmap = nullptr;        // nx*ny + receiver count + ny ints: receiver map of the reverse pass
     void* ysum = nullptr;        // y-chunk planes and interface values of the recomputation stream
     size_t ck_cap = 0, seg_cap = 0, work_cap = 0, rmap_cap = 0, ysum_cap = 0;
     // the recomputation of segment c - 1 runs on its own stream while the reverse
@@ -234,9 +321,10 @@ adi_status queue_xsolve(adi_wave_s* w, const void* rhs, void* out)
     XArgs<T> a = make_x<T>(w, rhs, nullptr, 0, T(1));
     a.w = static_cast<T*>(out);
     a.rows_per_strip = w->xp.rs;
+    a.xcd = a.rows_per_strip <= kXcdStripRows;
     a.vec = a.vec && aligned16(out);
     const int g = x_groups_per_wg(w->xp.tr);
-    const int grid = ((w->ny + w->xp.rs - 1) / w->xp.rs + g - 1) / g;
+    const int grid = xsweep_grid(w->ny, w->xp.rs, g);
     switch (w->xp.tr) {
         case 64: launch_xsolve1<T, 64>(grid, a, w->stream); break;
         case 128: launch_xsolve1<T, 128>(grid, a, w->stream); break;
@@ -349,18 +437,22 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     const double beta = 0.5 * w->dt * w->dt;
     int* rmap = nullptr;
     int* rnext = nullptr;
+    int* rrow = nullptr;
     if (nrec > 0) {
-        if (adi_status s = grow(&a->rmap, &a->rmap_cap, ((size_t)npts + nrec) * sizeof(int))) return s;
+        if (adi_status s = grow(&a->rmap, &a->rmap_cap, ((size_t)npts + nrec + w->ny) * sizeof(int))) return s;
         rmap = static_cast<int*>(a->rmap);
         rnext = rmap + npts;
+        rrow = rnext + nrec;
         ADI_HIP(hipMemsetAsync(rmap, 0x7f, (size_t)npts * sizeof(int), w->stream));   // 0x7f7f7f7f: no receiver
+        ADI_HIP(hipMemsetAsync(rrow, 0, (size_t)w->ny * sizeof(int), w->stream));
         hipLaunchKernelGGL(k_receiver_map, dim3((nrec + 255) / 256), dim3(256), 0, w->stream, rec->idx, nrec, npts,
-                           rmap, rnext);
+                           w->nx, rmap, rnext, rrow);
         ADI_LAUNCHED("receiver_map");
     }
     AdjArgs<T> ua{};
     ua.rmap = rmap;
     ua.rnext = rnext;
+    ua.rrow = rrow;
     ua.sidx = nsrc > 0 ? f->idx : nullptr;
     ua.nsrc = nsrc;
     ua.nrec = nrec;
@@ -373,6 +465,11 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     ua.c1 = (T)(w->dt * w->dt / (w->h * w->h));
     ua.c2 = (T)(beta / (w->h * w->h));
     const dim3 ug((w->nx + 63) / 64, (w->ny + 3) / 4);
+    // 16-byte vectors: whole vectors per row, and every field of the update 16-byte aligned
+    // (the handle's and this adjoint's buffers are; the gradient is the caller's)
+    constexpr int NV = 16 / (int)sizeof(T);
+    const bool vec_upd = w->nx % NV == 0 && aligned16(grad_kappa) && aligned16(w->r) && F % 16 == 0;
+    const dim3 ugv((unsigned)((((long long)(w->nx / NV + 255) / 256) * w->ny + 7) / 8 * 8));
     // segment c: levels L[0..n+1] = u^{k0-1} .. u^{k0+n} (L[0], L[1] the checkpoint,
     // the others in half c % 2 of the segment storage) and w^{k0..k0+n-1}
     auto lev = [&](int c, int m) -> void* {
@@ -431,7 +528,8 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
             ua.wk = static_cast<const T*>(wst(c, m));
             ua.rvals = (k >= 2 && nrec > 0) ? gt + (size_t)(k - 2) * nrec : nullptr;
             ua.gout = nsrc > 0 ? static_cast<T*>(grad_amp) + (size_t)(k - 1) * nsrc : nullptr;
-            hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
+            if (vec_upd) hipLaunchKernelGGL((k_adjoint_update_v<T>), ugv, dim3(256), 0, w->stream, ua);
+            else hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
             ADI_LAUNCHED("adjoint_update");
             std::swap(lam1, lam2);
         }

@@ -240,6 +240,7 @@ struct XArgs {
     T* w;                // out, (ny, nx)
     int nx, ny, nseg;    // nseg = ceil(nx / 8)
     int rows_per_strip;  // consecutive rows handled by one line group
+    int xcd;             // strips in XCD bands (short strips, see k_xsweep)
     int vec;             // rows are 16-byte aligned and nx % 8 == 0
     T rho_scale;         // 1 for a step, 1/2 for the ghost start
     T tau2;              // dt^2
@@ -762,14 +763,33 @@ __device__ __forceinline__ void rec_tap(const T* u, const int* idx, T* out, int 
         }
 }
 
+// With A.xcd set, the workgroups of one XCD (blockIdx mod 8) take a contiguous band
+// of strips, so the rows a strip reads above and below itself, which its
+// neighbouring strips read too, come through the same L2 (it pays for strips of a
+// few rows, where those rows are a large share of the reads); the grid is a
+// multiple of 8 and the workgroups past the last strip exit.
 template <typename T, int TR, bool FUSE, bool STENCIL = true>
 __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsweep(XArgs<T> A)
 {
     rec_tap<T>(A.u, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
     constexpr int G = (TR >= 256 ? TR : 256) / TR;
     __shared__ XShared<T, TR, FUSE> sh[G];
+    const int blk = A.xcd ? (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3)) : (int)blockIdx.x;
+    const int strips = (A.ny + A.rows_per_strip - 1) / A.rows_per_strip;
+    if (blk * G >= strips) return;
     const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / TR);   // one group per wavefront or more
-    xsweep_strip<T, TR, FUSE, STENCIL>(A, blockIdx.x * G + g, threadIdx.x - g * TR, sh[g]);
+    xsweep_strip<T, TR, FUSE, STENCIL>(A, blk * G + g, threadIdx.x - g * TR, sh[g]);
+}
+
+// strips in XCD bands: strips of at most this many rows
+constexpr int kXcdStripRows = 4;
+
+// x-sweep grid: workgroups for the strips (a multiple of 8 for XCD bands)
+inline int xsweep_grid(int ny, int rows_per_strip, int groups_per_wg)
+{
+    const int strips = (ny + rows_per_strip - 1) / rows_per_strip;
+    const int wgs = (strips + groups_per_wg - 1) / groups_per_wg;
+    return rows_per_strip <= kXcdStripRows ? (wgs + 7) / 8 * 8 : wgs;
 }
 
 }  // namespace adw
