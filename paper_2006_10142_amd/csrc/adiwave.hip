@@ -96,12 +96,13 @@ bool choose_tri(int n, adi_dtype dt, TPlan& p)
 
 int x_groups_per_wg(int tr) { return tr >= 256 ? 1 : 256 / tr; }
 
-// rows per strip: enough workgroups to cover 256 CUs twice, 2..32 rows
+// rows per strip: enough workgroups to cover 256 CUs twice, 1..32 rows (the rows
+// of a strip are solved one after another, so short strips suit small grids)
 int choose_rows(int ny, int tr)
 {
     const int g = x_groups_per_wg(tr);
     int rs = ny / (512 * g);
-    return std::max(2, std::min(32, rs));
+    return std::max(1, std::min(32, rs));
 }
 
 struct YScanPlan { int sk, p; };

@@ -172,6 +172,218 @@ __global__ void __launch_bounds__(256) k_adjoint_update_v(AdjArgs<T> A)
     *reinterpret_cast<VT*>(A.lam2 + p) = V::pack(lo);
 }
 
+// ---------------------------------------------- transposed x-lines + update --
+// t = A_x^{-1} z of one reverse step with the step's update (the expressions of
+// k_adjoint_update) folded in, so that t never goes to memory: a line group of TR
+// threads (kSeg nodes each, the layout of xsweep.hpp) owns a strip of RS output
+// rows and solves the x-lines of rows j0 - 1 .. j0 + RS (the neighbouring strips
+// solve the rows above and below again, with the same arithmetic); once the row
+// below a row is solved, that row's update runs from registers: t of rows q - 1,
+// q, q + 1 (its x-neighbours across segment edges through LDS), z and r of row q
+// (the solve's inputs), and u^k, d^k of rows q - 1 .. q + 1 rolled down the strip.
+template <typename T, int TR>
+struct XUShared {
+    T halo[2][2][TR];            // first and last t of every segment, by row parity
+    T totf[2][TR / 64][2];       // wavefront totals of the scans (xline_row)
+    T totb[2][TR / 64][3];
+    int src_pos[kStripSrc];      // sources in the strip's output rows: row offset * 2^16 + column
+    int src_k[kStripSrc];        //   and the source's index
+    int src_n;                   // count, or -1 when the strip holds more than kStripSrc
+};
+
+template <typename T, int TR, bool VEC>
+__device__ __forceinline__ void xsolve_update_strip(const XArgs<T>& X, const AdjArgs<T>& A, const int strip,
+                                                    const int t, XUShared<T, TR>& sh)
+{
+    constexpr int E = kSeg;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int nx = X.nx, ny = X.ny, nseg = X.nseg;
+    const int RS = X.rows_per_strip;
+    const int j0 = strip * RS;
+    const int j1 = min(j0 + RS, ny);              // output rows [j0, j1)
+    const int i0 = E * t;
+    const bool act = t < nseg;
+    const int L = act ? min(E, nx - i0) : 0;
+    const int voff = i0 * (int)sizeof(T);
+    const int row_bytes = nx * (int)sizeof(T);
+    const long long npts = (long long)nx * ny;
+    auto seg = [&](const T* base, int row, T (&v)[E]) {      // this lane's nodes of a row, 0 outside
+        const bool in = row >= 0 && row < ny;
+        if constexpr (VEC) {
+            bload8<T>(buf(base + (size_t)(in ? row : 0) * nx, in ? row_bytes : 0), voff, v);
+        } else if (act && in) {
+            gload8<T>(base + (size_t)row * nx, i0, nx, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = T(0);
+        }
+    };
+    auto put = [&](T* base, int row, const T (&v)[E]) {
+        if constexpr (VEC) bstore8<T>(buf(base + (size_t)row * nx, row_bytes), voff, v);
+        else if (act) gstore8<T>(base + (size_t)row * nx, i0, nx, v);
+    };
+    auto one = [&](const T* base, int row, int col) -> T {   // a single value, 0 outside
+        return (act && row >= 0 && row < ny && col >= 0 && col < nx) ? base[(size_t)row * nx + col] : T(0);
+    };
+
+    // sources in the output rows, in source order (wavefront 0 of the group, ballot-compacted)
+    if (t < 64) {
+        int n = 0;
+        for (int base = 0; base < A.nsrc; base += 64) {
+            const int k = base + t;
+            const int id = (A.sidx && k < A.nsrc) ? A.sidx[k] : -1;
+            const int row = (id >= 0 && id < npts) ? id / nx : -1;
+            const bool hit = row >= j0 && row < j1;
+            const unsigned long long mask = __ballot(hit);
+            const int before = __popcll(mask & ((1ull << t) - 1ull));
+            if (hit && n + before < kStripSrc) {
+                sh.src_pos[n + before] = ((row - j0) << 16) | (id - row * nx);
+                sh.src_k[n + before] = k;
+            }
+            n += __popcll(mask);
+        }
+        if (t == 0) sh.src_n = n <= kStripSrc ? n : -1;
+    }
+
+    // rows q - 1 and q of t, u^k and d^k (rolled down the strip), z and r of row q
+    T tm[E], tq[E], ua[E], ub[E], da[E], db[E], zq[E], rq[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) { tm[e] = tq[e] = ua[e] = ub[e] = da[e] = db[e] = zq[e] = rq[e] = T(0); }
+
+    // inputs of the first row's solve; each pass requests those of the next row
+    // before it solves its own
+    auto pivot_in = [&](int row) -> T { return (act && row >= 0 && row < ny) ? X.qin[(size_t)row * nseg + t] : T(0); };
+    T zc[E], rc[E];
+    seg(X.u, j0 - 1, zc);
+    seg(X.r, j0 - 1, rc);
+    T qc = pivot_in(j0 - 1);
+    for (int j = j0 - 1; j <= j0 + RS; ++j) {
+        const int q = j - 1;                       // the row updated in this pass
+        const bool upd = q >= j0 && q < j1;
+        T zn[E], rn[E];
+        const int jn = j < j0 + RS ? j + 1 : -1;   // no row after the strip's last
+        seg(X.u, jn, zn);
+        seg(X.r, jn, rn);
+        const T qn = pivot_in(jn);
+        // u^k and d^k of row j, and the update's row q
+        T un[E], pn[E], mn[E];
+        seg(A.uk, j, un);
+        seg(A.up, j, pn);
+        seg(A.um, j, mn);
+        T wq[E], l1[E], l2[E], gq[E];
+        T uwe = T(0), uee = T(0), wwe = T(0), wee = T(0);
+        if (upd) {
+            seg(A.wk, q, wq);
+            seg(A.lam1, q, l1);
+            seg(A.lam2, q, l2);
+            seg(A.grad, q, gq);
+            uwe = one(A.uk, q, i0 - 1); uee = one(A.uk, q, i0 + L);
+            wwe = one(A.wk, q, i0 - 1); wee = one(A.wk, q, i0 + L);
+        }
+        // solve row j (rows outside the grid have z = r = 0 and give t = 0)
+        T rho[E], tn[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) rho[e] = X.rho_scale * zc[e];
+        xline_row<T, TR>(rho, rc, qc, L, act, lane, wv, j & 1, sh.totf, sh.totb, []() {}, tn);
+        if (act) {
+            T last = tn[0];
+#pragma unroll
+            for (int e = 1; e < E; ++e)
+                if (e == L - 1) last = tn[e];
+            sh.halo[j & 1][0][t] = tn[0];
+            sh.halo[j & 1][1][t] = last;
+        }
+        T dn[E];
+        const bool jin = j >= 0 && j < ny;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dn[e] = jin ? (pn[e] - T(2) * un[e]) + mn[e] : T(0);
+        if (upd && act) {
+            // t across the segment edges of row q (written in the previous pass, before
+            // this pass's barrier)
+            const T tw0 = t > 0 ? sh.halo[q & 1][1][t - 1] : T(0);
+            const T teL = t + 1 < nseg ? sh.halo[q & 1][0][t + 1] : T(0);
+            const bool row_rec = A.rvals && A.rrow[q] != 0;
+            const size_t p0 = (size_t)q * nx + i0;
+            T go[E], lo[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T tw = e == 0 ? tw0 : tq[e - 1], te = e == L - 1 ? teL : (e + 1 < E ? tq[e + 1] : T(0));
+                const T uw = e == 0 ? uwe : ub[e - 1], ue = e == L - 1 ? uee : (e + 1 < E ? ub[e + 1] : T(0));
+                const T ww = e == 0 ? wwe : wq[e - 1], we = e == L - 1 ? wee : (e + 1 < E ? wq[e + 1] : T(0));
+                const T s5t = ((tw + te) + (tm[e] + tn[e])) - T(4) * tq[e];
+                const T s5u = ((uw + ue) + (ua[e] + un[e])) - T(4) * ub[e];
+                const T sxw = (ww + we) - T(2) * wq[e];
+                const T syd = (da[e] + dn[e]) - T(2) * db[e];
+                T g = gq[e], lam = l2[e];
+                if (e < L) {
+                    const T mu = tq[e] / rq[e];
+                    const T nu = zq[e] / rq[e];
+                    g = gq[e] + (mu * (A.c1 * s5u + A.c2 * sxw) + nu * (A.c2 * syd));
+                    lam = (T(2) * l1[e] - l2[e]) + T(2) * s5t;
+                    if (row_rec) {
+                        const int k0 = A.rmap[p0 + e];
+                        for (int k = k0 < A.nrec ? k0 : -1; k >= 0; k = A.rnext[k]) lam += A.rvals[k];
+                    }
+                }
+                go[e] = g;
+                lo[e] = lam;
+            }
+            put(A.grad, q, go);
+            put(A.lam2, q, lo);
+            // dJ/d(source value) = tau^2 t / r at the source nodes of row q
+            if (A.gout) {
+                const int ns = sh.src_n;
+                for (int k = 0; k < (ns >= 0 ? ns : A.nsrc); ++k) {
+                    int col, kk;
+                    if (ns >= 0) {
+                        const int pos = sh.src_pos[k];
+                        if ((pos >> 16) != q - j0) continue;
+                        col = pos & 0xffff;
+                        kk = sh.src_k[k];
+                    } else {
+                        const int id = A.sidx[k];
+                        if (id < 0 || id >= npts || id / nx != q) continue;
+                        col = id - q * nx;
+                        kk = k;
+                    }
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        if (i0 + e == col && e < L) A.gout[kk] = A.tau2 * tq[e] / rq[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            tm[e] = tq[e]; tq[e] = tn[e];
+            ua[e] = ub[e]; ub[e] = un[e];
+            da[e] = db[e]; db[e] = dn[e];
+            zq[e] = zc[e]; rq[e] = rc[e];
+            zc[e] = zn[e]; rc[e] = rn[e];
+        }
+        qc = qn;
+    }
+}
+
+template <typename T, int TR>
+__global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsolve_update(XArgs<T> X, AdjArgs<T> A)
+{
+    constexpr int G = (TR >= 256 ? TR : 256) / TR;
+    __shared__ XUShared<T, TR> sh[G];
+    // sources outside the grid: zero gradient (the strips see only the others)
+    if (A.gout && blockIdx.x == 0)
+        for (int k = threadIdx.x; k < A.nsrc; k += blockDim.x) {
+            const int id = A.sidx[k];
+            if (id < 0 || id >= A.npts) A.gout[k] = T(0);
+        }
+    const int blk = X.xcd ? (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3)) : (int)blockIdx.x;
+    const int strips = (X.ny + X.rows_per_strip - 1) / X.rows_per_strip;
+    if (blk * G >= strips) return;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / TR);
+    if (X.vec) xsolve_update_strip<T, TR, true>(X, A, blk * G + g, threadIdx.x - g * TR, sh[g]);
+    else xsolve_update_strip<T, TR, false>(X, A, blk * G + g, threadIdx.x - g * TR, sh[g]);
+}
+
 // receiver map of the reverse pass: rmap[node] = smallest receiver index at the
 // node (rmap filled beforehand with a value above every index, so that a node
 // without receivers keeps it), rnext[k] = next receiver at the same node or -1,
@@ -334,6 +546,27 @@ adi_status queue_xsolve(adi_wave_s* w, const void* rhs, void* out)
     }
     ADI_LAUNCHED("x_solve");
     return ADI_OK;
+}
+
+// the transposed x-lines of z with the update folded in (k_xsolve_update); false
+// when the plan's line groups are too wide for it (1024 threads: the registers of
+// the update do not fit next to the solve's)
+template <typename T>
+bool queue_xsolve_update(adi_wave_s* w, const void* z, const AdjArgs<T>& ua)
+{
+    XArgs<T> a = make_x<T>(w, z, nullptr, 0, T(1));
+    a.rows_per_strip = w->xp.rs;
+    a.xcd = a.rows_per_strip <= kXcdStripRows;
+    a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && aligned16(z) && aligned16(w->r) && aligned16(ua.uk) &&
+            aligned16(ua.up) && aligned16(ua.um) && aligned16(ua.wk) && aligned16(ua.lam1) && aligned16(ua.lam2) &&
+            aligned16(ua.grad);
+    const int grid = xsweep_grid(w->ny, w->xp.rs, x_groups_per_wg(w->xp.tr));
+    switch (w->xp.tr) {
+        case 64: hipLaunchKernelGGL((k_xsolve_update<T, 64>), dim3(grid), dim3(256), 0, w->stream, a, ua); return true;
+        case 128: hipLaunchKernelGGL((k_xsolve_update<T, 128>), dim3(grid), dim3(256), 0, w->stream, a, ua); return true;
+        case 256: hipLaunchKernelGGL((k_xsolve_update<T, 256>), dim3(grid), dim3(256), 0, w->stream, a, ua); return true;
+    }
+    return false;
 }
 
 // y-line solves: out = A_y^{-1} (r * rhs)
@@ -520,7 +753,6 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
         for (int m = n - 1; m >= 0; --m) {
             const int k = k0 + m;
             if (adi_status s = queue_ysolve_scaled<T>(w, lam1, zz)) return s;
-            if (adi_status s = queue_xsolve<T>(w, zz, tt)) return s;
             ua.t = tt; ua.z = zz; ua.lam1 = lam1; ua.lam2 = lam2;
             ua.um = static_cast<const T*>(lev(c, m));
             ua.uk = static_cast<const T*>(lev(c, m + 1));
@@ -528,9 +760,14 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
             ua.wk = static_cast<const T*>(wst(c, m));
             ua.rvals = (k >= 2 && nrec > 0) ? gt + (size_t)(k - 2) * nrec : nullptr;
             ua.gout = nsrc > 0 ? static_cast<T*>(grad_amp) + (size_t)(k - 1) * nsrc : nullptr;
-            if (vec_upd) hipLaunchKernelGGL((k_adjoint_update_v<T>), ugv, dim3(256), 0, w->stream, ua);
-            else hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
-            ADI_LAUNCHED("adjoint_update");
+            if (queue_xsolve_update<T>(w, zz, ua)) {
+                ADI_LAUNCHED("x_solve + adjoint_update");
+            } else {
+                if (adi_status s = queue_xsolve<T>(w, zz, tt)) return s;
+                if (vec_upd) hipLaunchKernelGGL((k_adjoint_update_v<T>), ugv, dim3(256), 0, w->stream, ua);
+                else hipLaunchKernelGGL((k_adjoint_update<T>), ug, dim3(256), 0, w->stream, ua);
+                ADI_LAUNCHED("adjoint_update");
+            }
             std::swap(lam1, lam2);
         }
         ADI_HIP(hipEventRecord(a->ev_rev[c & 1], w->stream));

@@ -368,6 +368,118 @@ __device__ __forceinline__ T bload1(rsrc_t rs, int voff)
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, 0));
 }
 
+// One row of x-lines solved on chip by a line group of TR threads (kSeg nodes each,
+// the segment layout above): the local elimination of every segment from its entry
+// pivot qc, both affine scans across the line with one workgroup barrier (totals
+// of the wavefronts in totf / totb, parity par), and the back substitution into
+// wout.  mid() runs after the barrier and before the back substitution (the FP64
+// line groups of 1024 threads request their next row of r there).  Every thread of
+// the workgroup must call this the same number of times.
+template <typename T, int TR, class Mid>
+__device__ __forceinline__ void xline_row(const T (&rho)[kSeg], const T (&rc)[kSeg], const T qc, const int L,
+                                          const bool act, const int lane, const int wv, const int par,
+                                          T (&totf)[2][TR / 64][2], T (&totb)[2][TR / 64][3], Mid&& mid,
+                                          T (&wout)[kSeg])
+{
+    constexpr int E = kSeg;
+    constexpr int NW = TR / 64;
+    // local elimination of the segment from its entry pivot.  Nodes past the
+    // end of the line (e >= L) have r = 0 and rho = 0 (zero-filled loads): they
+    // get m = 1, q = 0, G = 0 and add nothing to the segment's maps, so no
+    // branch is needed.  A lane without nodes keeps the identity map (0, 1).
+    // (the running products of q are not kept per node: the back substitution forms
+    // them again, with the same multiplications in the same order, which keeps the
+    // FP64 line group of 1024 threads within its 128 registers)
+    T Ge[E], qe[E];
+    T fG, fQ, H, Ev;
+    {
+        T q = qc, Gv = T(0), Qv = T(1), h = T(0), ee = T(0);
+        T QL = T(1);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const T m = pivot_step<T>(rc[e], q);
+            const T P = Qv;                       // prod of q before node e
+            Gv = fma_rn(m, rho[e], q * Gv);
+            Qv = q * Qv;
+            h = fma_rn(P, Gv, h);
+            ee = fma_rn(P, Qv, ee);
+            Ge[e] = Gv;
+            qe[e] = q;
+            if (e == L - 1) QL = Qv;
+        }
+        fG = Gv; fQ = act ? Qv : T(1); H = h; Ev = ee;
+        if (L < E) {                              // partial segment: carry the last node's map
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (e == L - 1) fG = Ge[e];
+            fQ = QL;
+        }
+    }
+
+    // Both scans across the line with one workgroup barrier.  The forward maps
+    // (g_out = fG + fQ g_in) are scanned inside the wavefront; the value C
+    // entering the wavefront is not known yet, so each lane's backward map
+    // a = H + Ev g_in = (H + Ev xa) + (Ev xb) C is scanned with C symbolic
+    // (components a0, a1).  After the barrier every wavefront combines the
+    // totals of all wavefronts: the carries C_k of every wavefront, and from
+    // them the backward totals (a0 + a1 C_k, b) and the value D below its last
+    // lane.
+    T gin, dbelow;
+    {
+        T a = fG, b = fQ;
+        wave_scan_fwd(a, b);
+        const T xa = dpp<kWaveShr1>(T(0), a);
+        const T xb = dpp<kWaveShr1>(T(1), b);
+        T a0 = fma_rn(Ev, xa, H), a1 = Ev * xb, bb = fQ;
+        if (!act) { a0 = T(0); a1 = T(0); bb = T(1); }
+        wave_scan_bwd3(a0, a1, bb, lane);
+        const T ya0 = dpp<kWaveShl1>(T(0), a0);
+        const T ya1 = dpp<kWaveShl1>(T(0), a1);
+        const T yb = dpp<kWaveShl1>(T(1), bb);
+        if constexpr (NW > 1) {
+            if (lane == 63) { totf[par][wv][0] = a; totf[par][wv][1] = b; }
+            if (lane == 0) { totb[par][wv][0] = a0; totb[par][wv][1] = a1; totb[par][wv][2] = bb; }
+        }
+        __syncthreads();
+        T C = T(0), D = T(0);
+        if constexpr (NW > 1) {
+            const int k = lane < NW ? lane : 0;
+            T fa = (lane < NW) ? totf[par][k][0] : T(0);
+            T fb = (lane < NW) ? totf[par][k][1] : T(1);
+            row_scan_fwd(fa, fb);                        // lane k: waves 0..k
+            const T Ck = dpp<kRowShr + 1, 0xf>(T(0), fa);  // lane k: value entering wave k
+            T ta = T(0), tb = T(1);
+            if (lane < NW) {
+                ta = fma_rn(totb[par][k][1], Ck, totb[par][k][0]);
+                tb = totb[par][k][2];
+            }
+            row_scan_bwd(ta, tb);                        // lane k: waves k..NW-1
+            C = readlane(Ck, __builtin_amdgcn_readfirstlane(wv));
+            D = (wv + 1 < NW) ? readlane(ta, __builtin_amdgcn_readfirstlane(wv + 1)) : T(0);
+        }
+        gin = fma_rn(xb, C, xa);
+        dbelow = fma_rn(yb, D, fma_rn(ya1, C, ya0));
+    }
+
+    mid();
+
+    // back substitution (tail nodes give 0 and feed q = 0 into the last node)
+    {
+        T Qv = T(1);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            Qv = qe[e] * Qv;
+            Ge[e] = fma_rn(Qv, gin, Ge[e]);
+        }
+        T x = dbelow;
+#pragma unroll
+        for (int e = E - 1; e >= 0; --e) {
+            x = fma_rn(qe[e], x, Ge[e]);
+            wout[e] = x;
+        }
+    }
+}
+
 // Workgroup: max(TR, 256) threads = G line groups of TR threads.  A group owns
 // rows_per_strip consecutive rows and solves them in turn; rows j+2 (u) and
 // j+1 (r, entry pivots) are loaded while row j is being solved.
@@ -591,105 +703,12 @@ __device__ __forceinline__ void xsweep_strip_impl(const XArgs<T>& A, const int s
             }
         }
 
-        // local elimination of the segment from its entry pivot.  Nodes past the
-        // end of the line (e >= L) have r = 0 and rho = 0 (zero-filled loads): they
-        // get m = 1, q = 0, G = 0 and add nothing to the segment's maps, so no
-        // branch is needed.  A lane without nodes keeps the identity map (0, 1).
-        // (the running products of q are not kept per node: the back substitution forms
-        // them again, with the same multiplications in the same order, which keeps the
-        // FP64 line group of 1024 threads within its 128 registers)
-        T Ge[E], qe[E];
-        T fG, fQ, H, Ev;
-        {
-            T q = qc, Gv = T(0), Qv = T(1), h = T(0), ee = T(0);
-            T QL = T(1);
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const T m = pivot_step<T>(rc[e], q);
-                const T P = Qv;                       // prod of q before node e
-                Gv = fma_rn(m, rho[e], q * Gv);
-                Qv = q * Qv;
-                h = fma_rn(P, Gv, h);
-                ee = fma_rn(P, Qv, ee);
-                Ge[e] = Gv;
-                qe[e] = q;
-                if (e == L - 1) QL = Qv;
-            }
-            fG = Gv; fQ = act ? Qv : T(1); H = h; Ev = ee;
-            if (L < E) {                              // partial segment: carry the last node's map
-#pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if (e == L - 1) fG = Ge[e];
-                fQ = QL;
-            }
-        }
-
-        // Both scans across the line with one workgroup barrier.  The forward maps
-        // (g_out = fG + fQ g_in) are scanned inside the wavefront; the value C
-        // entering the wavefront is not known yet, so each lane's backward map
-        // a = H + Ev g_in = (H + Ev xa) + (Ev xb) C is scanned with C symbolic
-        // (components a0, a1).  After the barrier every wavefront combines the
-        // totals of all wavefronts: the carries C_k of every wavefront, and from
-        // them the backward totals (a0 + a1 C_k, b) and the value D below its last
-        // lane.
-        T gin, dbelow;
-        {
-            const int par = j & 1;
-            T a = fG, b = fQ;
-            wave_scan_fwd(a, b);
-            const T xa = dpp<kWaveShr1>(T(0), a);
-            const T xb = dpp<kWaveShr1>(T(1), b);
-            T a0 = fma_rn(Ev, xa, H), a1 = Ev * xb, bb = fQ;
-            if (!act) { a0 = T(0); a1 = T(0); bb = T(1); }
-            wave_scan_bwd3(a0, a1, bb, lane);
-            const T ya0 = dpp<kWaveShl1>(T(0), a0);
-            const T ya1 = dpp<kWaveShl1>(T(0), a1);
-            const T yb = dpp<kWaveShl1>(T(1), bb);
-            if constexpr (NW > 1) {
-                if (lane == 63) { sh.totf[par][wv][0] = a; sh.totf[par][wv][1] = b; }
-                if (lane == 0) { sh.totb[par][wv][0] = a0; sh.totb[par][wv][1] = a1; sh.totb[par][wv][2] = bb; }
-            }
-            __syncthreads();
-            T C = T(0), D = T(0);
-            if constexpr (NW > 1) {
-                const int k = lane < NW ? lane : 0;
-                T fa = (lane < NW) ? sh.totf[par][k][0] : T(0);
-                T fb = (lane < NW) ? sh.totf[par][k][1] : T(1);
-                row_scan_fwd(fa, fb);                        // lane k: waves 0..k
-                const T Ck = dpp<kRowShr + 1, 0xf>(T(0), fa);  // lane k: value entering wave k
-                T ta = T(0), tb = T(1);
-                if (lane < NW) {
-                    ta = fma_rn(sh.totb[par][k][1], Ck, sh.totb[par][k][0]);
-                    tb = sh.totb[par][k][2];
-                }
-                row_scan_bwd(ta, tb);                        // lane k: waves k..NW-1
-                C = readlane(Ck, __builtin_amdgcn_readfirstlane(wv));
-                D = (wv + 1 < NW) ? readlane(ta, __builtin_amdgcn_readfirstlane(wv + 1)) : T(0);
-            }
-            gin = fma_rn(xb, C, xa);
-            dbelow = fma_rn(yb, D, fma_rn(ya1, C, ya0));
-        }
-
-        if constexpr (kUmLds<T, TR>) load_rq(live ? j + 1 : -1, rn, qn);
-
-        // back substitution, store (tail nodes give 0 and feed q = 0 into the last node)
         T wout[E];
-        {
-            T Qv = T(1);
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                Qv = qe[e] * Qv;
-                Ge[e] = fma_rn(Qv, gin, Ge[e]);
-            }
-            T x = dbelow;
-#pragma unroll
-            for (int e = E - 1; e >= 0; --e) {
-                x = fma_rn(qe[e], x, Ge[e]);
-                wout[e] = x;
-            }
-            if constexpr (VEC) bstore8<T>(buf(A.w + (size_t)(live ? j : 0) * nx, live ? row_bytes : 0), voff, wout);
-            else if (live && act) gstore8<T>(A.w + (size_t)j * nx, i0, nx, wout);
-        }
+        xline_row<T, TR>(rho, rc, qc, L, act, lane, wv, j & 1, sh.totf, sh.totb, [&]() {
+            if constexpr (kUmLds<T, TR>) load_rq(live ? j + 1 : -1, rn, qn);
+        }, wout);
+        if constexpr (VEC) bstore8<T>(buf(A.w + (size_t)(live ? j : 0) * nx, live ? row_bytes : 0), voff, wout);
+        else if (live && act) gstore8<T>(A.w + (size_t)j * nx, i0, nx, wout);
 
         if constexpr (FUSE) {
             const int c = j / A.M;

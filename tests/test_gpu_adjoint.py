@@ -126,16 +126,34 @@ def test_adjoint_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
     check_grads(c, gpu_grad(adw, c, K), oracle_grad(oracle_lib, c), f"K={K} nonzero={nonzero}")
 
 
-@pytest.mark.parametrize("nx,ny", [(30, 50), (7, 90), (130, 9)])
+@pytest.mark.parametrize("nx,ny", [(30, 50), (7, 90), (130, 9), (2100, 12), (2101, 12)])
 def test_adjoint_narrow_grids(adw, oracle_lib, nx, ny):
-    """Grids narrower than one 64-wide block of the reverse kernels (and wide, short
-    ones): gradients of kappa and of the source values against the oracle (FP64)."""
+    """Grids narrower than one 64-wide block of the reverse kernels, and wide, short
+    ones (rows of more than 2048 nodes take the separate transposed x-solve and update
+    kernels, 2101 the update without 16-byte vectors): gradients of kappa and of the
+    source values against the oracle (FP64)."""
     c = case("f64", nx=nx, ny=ny, nsteps=24, seed=nx + ny)
     say(f"adjoint narrow {nx}x{ny}")
     got = gpu_grad(adw, c, 5)
     ref = oracle_grad(oracle_lib, c)
     assert np.abs(ref[1]).max() > 0
     check_grads(c, got, ref, f"narrow {nx}x{ny}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_long_columns(adw, oracle_lib, dtype):
+    """Columns of 1100 rows (69 chunks of 16, so the interface systems of the forward
+    run, the recomputation and the transposed y-lines take 64 threads per column),
+    sources and receivers 10 rows apart in the middle of the grid."""
+    c = case(dtype, nx=24, ny=1100, nsteps=24, seed=17)
+    nx = c["nx"]
+    c["src_idx"] = np.array([550 * nx + 12, 552 * nx + 5], np.int32)
+    c["rec_idx"] = np.array([560 * nx + 2 * k + 3 for k in range(8)], np.int32)
+    say(f"adjoint long columns {dtype}")
+    got = gpu_grad(adw, c, 5)
+    ref = oracle_grad(oracle_lib, c)
+    assert np.abs(ref[1]).max() > 0
+    check_grads(c, got, ref, "long columns")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

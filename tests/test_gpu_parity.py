@@ -422,6 +422,33 @@ def test_launch_plans(adw, oracle_lib, dtype, tr, rs, fused, m):
     assert rel_l2(b.cpu().numpy(), ref) <= TOL_RUN[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("m", [16, 32])
+def test_long_columns(adw, oracle_lib, dtype, m):
+    """Columns of 1100 rows: 69 chunks of 16 rows, or 35 of 32, with the y-chunk
+    elimination in its own launch (unfused plan); the interface systems take the
+    partition solver with 64 threads per column.  Matches the oracle after 10 steps of
+    the exact step."""
+    nx, ny = 72, 1100
+    h = 1.0 / 1101
+    dt = 0.5 * h
+    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=23).astype(npdt(dtype))
+    u0 = wl.gaussian_pulse(nx, ny, sigma=0.1).astype(npdt(dtype))
+    say(f"long columns {dtype} m={m}")
+    wave = adw.Wave(nx, ny, h, dt, c=dev(c), dtype=tdt(dtype))
+    wave.set_tuning(64, 2, False, m, fused_step=False)
+    assert wave.info()["kernels_per_step"] == 4
+    a = dev(u0)
+    b = wave.start(a)
+    a, b = wave.step(a, b, 10)
+    torch.cuda.synchronize()
+    kap = c.astype(np.float64) ** 2
+    u1 = oracle_lib.start(kap, u0, h, dt)
+    _, ref, _ = oracle_lib.run(kap, u0, u1, h, dt, 10)
+    assert rel_l2(b.cpu().numpy(), ref) <= TOL_RUN[dtype]
+    wave.close()
+
+
 def test_invalid_calls_raise(adw):
     wave = adw.Wave(16, 16, 1 / 17, 0.5 / 17, dtype=torch.float32)
     u = torch.zeros((16, 16), device="cuda")
