@@ -353,6 +353,9 @@ typedef struct {
                                  unit gets a segment of >= 256 rows): output rows per strip
                                  segment (fused_tile_cols wide, four nodes per lane);
                                  0 when the step runs on 64-row tiles */
+    int fused_strips_wide;    /* column strips: the first this many are fused_tile_cols wide,
+                                 the others 8 columns narrower (the automatic plan mixes the
+                                 two widths to cover nx evenly) */
 } adi_wave_info;
 
 adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info);

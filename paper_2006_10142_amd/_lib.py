@@ -38,7 +38,7 @@ class AdiWaveInfo(ctypes.Structure):
                 ("fused_allowed", ctypes.c_int), ("r_max", ctypes.c_double),
                 ("line_solver", ctypes.c_int), ("fused_tile_cols", ctypes.c_int),
                 ("fused_tiles", ctypes.c_int), ("fused_lane_nodes", ctypes.c_int),
-                ("fused_segment_rows", ctypes.c_int)]
+                ("fused_segment_rows", ctypes.c_int), ("fused_strips_wide", ctypes.c_int)]
 
 
 class AdiTuning(ctypes.Structure):

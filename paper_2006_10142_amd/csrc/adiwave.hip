@@ -247,6 +247,7 @@ struct adi_wave_s {
     float rmax = 0.f;
     int fused_ok = 0, fused_mode = 0, fstep = 0;
     int f_wt = 0, f_tx = 0, f_tiles = 0, f_grid = 0;
+    int f_wide = 0;      // column strips: the first f_wide are f_wt wide, the others f_wt - 8
     int f_ncu = 0;       // compute units the tiles are balanced over (0: widest tiles)
     int f_wt_user = 0;   // tile width set through adi_wave_set_tuning (0: chosen here)
     int f_lane = 8;      // nodes per lane of the one-pass x-lines (8: fused.hpp, 4: fused4.hpp)
@@ -512,23 +513,45 @@ void fused_plan(adi_wave_s* w)
     }
     w->f_tiles = w->f_tx * ((w->ny + kFuHt - 1) / kFuHt);
     w->f_grid = (w->f_tiles + 7) / 8 * 8;
-    // Column strips (fusedr.hpp): the widest strips of at most 240 columns, one
-    // segment of hs rows per compute unit.  Chosen automatically when that gives
-    // every segment at least kFrHmin rows (measured faster than the tiles from
-    // 4096^2 to 8192^2), or set through adi_wave_set_tuning.
+    w->f_wide = w->f_tx;
+    // Column strips (fusedr.hpp): tx strips of two widths 8 apart (at most 240
+    // columns) that cover nx, and g = ncu / tx segments of hs rows per strip, one per
+    // compute unit.  Among the strip counts from the fewest, the one whose largest
+    // segment has the least x-window work ((widest + 16 halo columns) * hs) is taken,
+    // automatically when every segment then has at least kFrHmin rows (measured faster
+    // than the tiles from 4096^2 to 8192^2); or set through adi_wave_set_tuning (one
+    // width).
     w->f_hs = 0;
     long long c = 0;
     const int wt4 = fused_width(w->nx, w->ny, 0, kF4Wmax, kFuT4a, kFuT4b, &c);
     int hs = w->f_hs_user > 0 ? w->f_hs_user : 0;
+    int swt = w->f_wt_user > 0 ? std::min(w->f_wt_user, kF4Wmax) : wt4;
+    int stx = (w->nx + swt - 1) / swt, swide = stx;
     if (w->f_hs_user == 0 && w->f_ncu > 0 && w->f_wt_user == 0 && w->f_lane_user == 0) {
-        const int g = w->f_ncu / ((w->nx + wt4 - 1) / wt4);
-        const int h = g > 0 ? (w->ny + g - 1) / g : 0;
-        if (g > 0 && h >= kFrHmin) hs = h;
+        long long best = -1;
+        for (int tx = (w->nx + kF4Wmax - 1) / kF4Wmax; tx <= (w->nx + kF4Wmax - 1) / kF4Wmax + 4; ++tx) {
+            const int w0 = w->nx / tx / 8 * 8;
+            const int a = (w->nx - tx * w0 + 7) / 8;           // strips one width step wider
+            const int wmax = a > 0 ? w0 + 8 : w0;
+            const int g = w->f_ncu / tx;
+            if (w0 < 8 || wmax > kF4Wmax || a > tx || g <= 0) continue;
+            const int h = (w->ny + g - 1) / g;
+            if (h < kFrHmin) continue;
+            const long long cost = (long long)(wmax + 2 * kFuKx) * h;
+            if (best < 0 || cost < best) {
+                best = cost;
+                hs = h;
+                swt = wmax;
+                stx = tx;
+                swide = a > 0 ? a : tx;
+            }
+        }
     }
     if (hs > 0) {
         w->f_lane = 4;
-        w->f_wt = w->f_wt_user > 0 ? std::min(w->f_wt_user, kF4Wmax) : wt4;
-        w->f_tx = (w->nx + w->f_wt - 1) / w->f_wt;
+        w->f_wt = swt;
+        w->f_tx = stx;
+        w->f_wide = swide;
         w->f_hs = hs;
         w->f_tiles = w->f_tx * ((w->ny + hs - 1) / hs);
         w->f_grid = (w->f_tiles + 7) / 8 * 8;   // a multiple of 8 for the XCD-aware block map
@@ -588,6 +611,7 @@ adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const ad
     a.nseg = w->nseg;
     a.wt = w->f_wt;
     a.tiles_x = w->f_tx;
+    a.wide = w->f_wide;
     a.tiles = w->f_tiles;
     a.xcd_map = 1;
     a.tau2 = (float)(w->dt * w->dt);
@@ -883,6 +907,7 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->fused_tiles = w->f_tiles;
     info->fused_lane_nodes = w->f_lane;
     info->fused_segment_rows = w->f_hs;
+    info->fused_strips_wide = w->f_wide;
     return ADI_OK;
 }
 

@@ -55,6 +55,7 @@ struct FArgs {
     int nx, ny, nseg;
     int wt;              // output columns per tile (multiple of 8)
     int tiles_x, tiles;  // tiles across, total tiles
+    int wide;            // column strips (fusedr.hpp): strips 0..wide-1 are wt wide, the others wt - 8
     int xcd_map;         // 1: block -> tile map that keeps neighbours on one XCD
     int hs;              // column strips (fusedr.hpp): output rows per strip segment
     float tau2;

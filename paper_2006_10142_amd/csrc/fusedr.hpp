@@ -2,7 +2,8 @@
 // role, so that the y-lines run while the next x-rows are solved and loaded.
 // Included by adiwave.hip after fused4.hpp, whose x-row scheme it uses.
 //
-// A workgroup owns a strip of Wt output columns (a multiple of 8, <= 240) and hs
+// A workgroup owns a strip of Wt output columns (a multiple of 8, <= 240; the plan
+// mixes two widths 8 apart so that the strips cover the grid evenly) and hs
 // output rows, and walks down it in bands of 24 x-rows; band k holds the x-rows
 // [r0 - 8 + 24k, r0 + 16 + 24k).
 //   x-role (12 wavefronts): two x-rows each per band, four nodes per lane, on
@@ -79,8 +80,10 @@ __global__ void __launch_bounds__(kFrThreads) k_fusedr(FArgs A)
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int nx = A.nx, ny = A.ny, wt = A.wt;
-    const int c0 = (blk % A.tiles_x) * wt;
+    const int nx = A.nx, ny = A.ny;
+    const int sx = blk % A.tiles_x;                       // strip index: the first A.wide are
+    const int wt = sx < A.wide ? A.wt : A.wt - 8;         // A.wt wide, the others 8 narrower
+    const int c0 = sx * A.wt - (sx > A.wide ? (sx - A.wide) * 8 : 0);
     const int r0 = (blk / A.tiles_x) * A.hs;
     const int r1 = min(r0 + A.hs, ny);
     const int nb = r1 - r0 <= kFuKy ? 1 : 1 + (r1 - r0 - kFuKy + kFrB - 1) / kFrB;

@@ -136,14 +136,35 @@ def balanced(nx, ny, ncu):
     return (4, w4) if c4 < c8 else (8, w8)
 
 
+def strip_plan(nx, ny, ncu):
+    """Column strips as the plan picks them: for tx strips from the fewest of at most
+    240 columns, widths w0 and w0 + 8 (a strips of w0 + 8) covering nx, g = ncu // tx
+    segments of h rows; the least (widest + 16) * h among those with h >= 256.
+    Returns (widest, tx, a or tx, h) or None."""
+    best = None
+    tx0 = -(-nx // 240)
+    for tx in range(tx0, tx0 + 5):
+        w0 = nx // tx // 8 * 8
+        a = -(-(nx - tx * w0) // 8)
+        wmax = w0 + 8 if a > 0 else w0
+        g = ncu // tx
+        if w0 < 8 or wmax > 240 or a > tx or g <= 0:
+            continue
+        h = -(-ny // g)
+        if h < 256:
+            continue
+        cost = (wmax + 16) * h
+        if best is None or cost < best[0]:
+            best = (cost, (wmax, tx, a if a > 0 else tx, h))
+    return best[1] if best else None
+
+
 def auto_plan(nx, ny, ncu):
     """(nodes per lane, width, strip segment rows or 0) the plan picks: column strips
-    (the widest of at most 240 columns, one segment per compute unit) when every
-    segment gets at least 256 rows, else the tile plan"""
-    w4 = widest(nx, 240)
-    g = ncu // -(-nx // w4)
-    if g > 0 and -(-ny // g) >= 256:
-        return 4, w4, -(-ny // g)
+    (strip_plan) when every segment gets at least 256 rows, else the tile plan"""
+    sp = strip_plan(nx, ny, ncu)
+    if sp:
+        return 4, sp[0], sp[3]
     return balanced(nx, ny, ncu) + (0,)
 
 
@@ -174,6 +195,26 @@ def test_one_pass_matches_oracle(adw, oracle_lib, nx, ny, layout):
     if strips:
         assert info["fused_lane_nodes"] == 4 and info["fused_tile_cols"] == widest(nx, 240)
         assert info["fused_tiles"] == -(-nx // info["fused_tile_cols"]) * -(-ny // k["hs"])
+    ref, rtr = oracle(oracle_lib, k)
+    check(got, ref, what="level")
+    check(tr, rtr, what="traces")
+
+
+def test_one_pass_mixed_strip_widths(adw, oracle_lib):
+    """4096 x 3600: the automatic plan takes 18 column strips, 8 of 232 and 10 of 224
+    columns, 14 segments of 258 rows; 3 steps against the oracle (relative L2 and
+    max-norm), including the traces."""
+    nx, ny = 4096, 3600
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    sp = strip_plan(nx, ny, ncu)
+    if sp is None:
+        pytest.skip(f"no column-strip plan for {ncu} compute units")
+    k = case(nx, ny, seed=31, nsteps=3)
+    k["lane"], k["tile_cols"], k["hs"] = -1, -1, -1
+    say(f"one-pass mixed strip widths {nx}x{ny}")
+    got, tr, info = gpu(adw, k, True)
+    assert (info["fused_tile_cols"], info["fused_segment_rows"], info["fused_strips_wide"]) == (sp[0], sp[3], sp[2])
+    assert info["fused_tiles"] == sp[1] * -(-ny // sp[3])
     ref, rtr = oracle(oracle_lib, k)
     check(got, ref, what="level")
     check(tr, rtr, what="traces")
@@ -229,7 +270,11 @@ def test_tile_width_plan(adw):
         i = w.info()
         lane, wt, hs = auto_plan(n, n, ncu)
         assert (i["fused_lane_nodes"], i["fused_tile_cols"], i["fused_segment_rows"]) == (lane, wt, hs), (n, i)
-        assert i["fused_tiles"] == -(-n // wt) * -(-n // (hs if hs else 64))
+        sp = strip_plan(n, n, ncu)
+        tx = sp[1] if sp else -(-n // wt)
+        assert i["fused_tiles"] == tx * -(-n // (hs if hs else 64))
+        if sp:
+            assert i["fused_strips_wide"] == sp[2]
         w.set_tuning(fused_lane_nodes=8, fused_tile_cols=488)
         j = w.info()
         assert j["fused_tile_cols"] == 488 and j["fused_lane_nodes"] == 8 and j["fused_segment_rows"] == 0
