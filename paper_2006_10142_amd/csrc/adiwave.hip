@@ -231,6 +231,7 @@ struct adi_wave_s {
     void* sum = nullptr;   // 8 * K * nx
     void* X = nullptr;     // K * nx
     void* qin = nullptr;   // ny * nseg entry pivots of the x-line segments
+    void* qin2 = nullptr;  // FP64: ny * ceil(nx / 2) entry pivots of every 2-node lane (one-pass strips)
     int nseg = 0;
     int nxp = 0;           // nx rounded up to the summary-plane column block
     size_t w_cap = 0;      // elements of w (also create-time scratch of 5*K*nx)
@@ -244,7 +245,7 @@ struct adi_wave_s {
     unsigned long long gen = 0;
     // one-pass step (FP32): allowed when the truncation bound holds for the
     // largest r; mode 0 = automatic, 1 = on when allowed, 2 = off
-    float rmax = 0.f;
+    double rmax = 0.0;   // largest r, measured on the device when the coefficient is set
     int fused_ok = 0, fused_mode = 0, fstep = 0;
     int f_wt = 0, f_tx = 0, f_tiles = 0, f_grid = 0;
     int f_wide = 0;      // column strips: the first f_wide are f_wt wide, the others f_wt - 8
@@ -279,10 +280,11 @@ void free_ws(adi_wave_s* w)
     if (w->sum) (void)hipFree(w->sum);
     if (w->X) (void)hipFree(w->X);
     if (w->qin) (void)hipFree(w->qin);
+    if (w->qin2) (void)hipFree(w->qin2);
     if (w->cr_abc) (void)hipFree(w->cr_abc);
     if (w->r_prev) (void)hipFree(w->r_prev);
     if (w->rho_buf) (void)hipFree(w->rho_buf);
-    w->r = w->w = w->sum = w->X = w->qin = w->cr_abc = w->r_prev = w->rho_buf = nullptr;
+    w->r = w->w = w->sum = w->X = w->qin = w->qin2 = w->cr_abc = w->r_prev = w->rho_buf = nullptr;
 }
 
 adi_status alloc_chunks(adi_wave_s* w)
@@ -313,7 +315,8 @@ adi_status alloc_chunks(adi_wave_s* w)
         (void)hipGetLastError();
         return fail(ADI_ENOMEM, "hipMalloc of y-chunk workspace failed");
     }
-    w->bytes = ((size_t)w->nx * w->ny + w->w_cap + (size_t)w->ny * w->nseg + nsum + nX) * es;
+    w->bytes = ((size_t)w->nx * w->ny + w->w_cap + (size_t)w->ny * w->nseg + nsum + nX +
+                (w->qin2 ? (size_t)w->ny * ((w->nx + 1) / 2) : 0)) * es;
     return ADI_OK;
 }
 
@@ -449,22 +452,17 @@ adi_status static_planes(adi_wave_s* w)
     return ADI_OK;
 }
 
-// One-pass step: the truncation error of a step is at most 4 qs^(Ky+1) max|w|
-// (see fused.hpp); it is enabled only when that is below 2^-24.
-bool fused_bound_holds(double rm)
+// One-pass step: the truncation error of a step is at most 4 qs^(K+1) max|w| (see
+// fused.hpp); it is enabled only when that is below half an ulp of the arithmetic:
+// 2^-24 for FP32 (K = 8), 2^-53 for FP64 (K = 16, the FP64 column strips).
+bool fused_bound_holds(double rm, adi_dtype dt)
 {
     if (!(rm >= 0.0) || !std::isfinite(rm)) return false;
     const double qs = rm > 0.0 ? (1.0 + 2.0 * rm - std::sqrt(1.0 + 4.0 * rm)) / (2.0 * rm) : 0.0;
-    return 4.0 * std::pow(qs, kFuKy + 1) <= std::ldexp(1.0, -24);
+    return dt == ADI_F64 ? 4.0 * std::pow(qs, FrCfg<double>::KY + 1) <= std::ldexp(1.0, -53)
+                         : 4.0 * std::pow(qs, kFuKy + 1) <= std::ldexp(1.0, -24);
 }
 
-// Tile width and lane variant of the one-pass step.  A step is ceil(tiles / CUs)
-// rounds of tiles, and a tile under full load takes a fixed time (the x-rows'
-// instruction stream, one wavefront per row, and the phase barriers) plus a
-// part that grows with its width (traffic, y-lines, update).  The two parts,
-// in ns, were fitted to both kernels on MI355X from 1024^2 to 8192^2; the plan
-// takes the width, and with ncu > 0 the variant, of least rounds * tile time.
-// With ncu = 0 (many simulations share the rounds) the tiles are the widest.
 constexpr int kFuT8a = 16000, kFuT8b = 30;   // eight nodes per lane (fused.hpp)
 constexpr int kFuT4a = 12000, kFuT4b = 15;   // four nodes per lane (fused4.hpp)
 constexpr int kFuWmin = 64;
@@ -493,11 +491,65 @@ int fused_width(int nx, int ny, int ncu, int wmax, int ta, int tb, long long* co
     return best;
 }
 
+// FP64 one-pass plan: column strips only (k_fusedr<double>), at most kFrS64 columns
+// wide.  Set through adi_wave_set_tuning: one width (the given one, or the widest
+// that covers nx evenly) and the given segment rows (else one segment per compute
+// unit).  Otherwise the strip count from the fewest to twice as many whose largest
+// segment has the least x-window work ((widest + 2 * 16 halo columns) * hs), with
+// two widths 8 apart as for FP32.
+void fused_plan_f64(adi_wave_s* w)
+{
+    constexpr int S = kFrS64, KX = FrCfg<double>::KX;
+    const int ncu = w->f_ncu > 0 ? w->f_ncu : 1;
+    const int nx = w->nx, ny = w->ny;
+    int swt = w->f_wt_user > 0 ? std::min(w->f_wt_user, S) : 0, stx = 0, swide = 0, hs = w->f_hs_user > 0 ? w->f_hs_user : 0;
+    if (swt > 0 || hs > 0) {
+        if (swt == 0) {
+            const int tx = (nx + S - 1) / S;
+            swt = ((nx + tx - 1) / tx + 7) / 8 * 8;
+        }
+        stx = (nx + swt - 1) / swt;
+        swide = stx;
+        if (hs == 0) hs = (ny + std::max(1, ncu / stx) - 1) / std::max(1, ncu / stx);
+    } else {
+        long long best = -1;
+        const int tx0 = (nx + S - 1) / S;
+        for (int tx = tx0; tx <= 2 * tx0; ++tx) {
+            const int w0 = nx / tx / 8 * 8;
+            const int a = (nx - tx * w0 + 7) / 8;
+            const int wmax = a > 0 ? w0 + 8 : w0;
+            if (w0 < 8 || wmax > S || a > tx) continue;
+            const int g = std::max(1, ncu / tx);
+            const int h = (ny + g - 1) / g;
+            const long long cost = (long long)(wmax + 2 * KX) * h;
+            if (best < 0 || cost < best) {
+                best = cost;
+                swt = wmax; stx = tx; swide = a > 0 ? a : tx; hs = h;
+            }
+        }
+        if (best < 0) {                      // narrower than 8 columns: one strip
+            swt = (nx + 7) / 8 * 8; stx = 1; swide = 1; hs = ny;
+        }
+    }
+    w->f_lane = FrCfg<double>::NPL;
+    w->f_wt = swt;
+    w->f_tx = stx;
+    w->f_wide = swide;
+    w->f_hs = hs;
+    w->f_tiles = stx * ((ny + hs - 1) / hs);
+    w->f_grid = (w->f_tiles + 7) / 8 * 8;
+}
+
 void fused_plan(adi_wave_s* w)
 {
-    w->fused_ok = (w->dtype == ADI_F32 && w->nx % 4 == 0 && fused_bound_holds(w->rmax)) ? 1 : 0;
+    const bool f64 = w->dtype == ADI_F64;
+    w->fused_ok = ((f64 ? w->nx % 2 == 0 : w->nx % 4 == 0) && fused_bound_holds(w->rmax, w->dtype)) ? 1 : 0;
     const bool autoon = (long long)w->nx * w->ny >= (1LL << 16);
     w->fstep = w->fused_ok && (w->fused_mode == 1 || (w->fused_mode == 0 && autoon)) ? 1 : 0;
+    if (f64) {
+        fused_plan_f64(w);
+        return;
+    }
     long long c8 = 0, c4 = 0;
     const int w8 = fused_width(w->nx, w->ny, w->f_ncu, kFuWmax, kFuT8a, kFuT8b, &c8);
     const int w4 = fused_width(w->nx, w->ny, w->f_ncu, kF4Wmax, kFuT4a, kFuT4b, &c4);
@@ -559,18 +611,24 @@ void fused_plan(adi_wave_s* w)
 }
 
 // largest r of an FP32 handle (synchronises the stream); X is free scratch here
+template <typename T>
 adi_status measure_rmax(adi_wave_s* w)
 {
     const long long n = (long long)w->nx * w->ny;
-    ADI_HIP(hipMemsetAsync(w->X, 0, sizeof(unsigned int), w->stream));
+    ADI_HIP(hipMemsetAsync(w->X, 0, sizeof(T), w->stream));   // X holds at least one value
     const int grid = (int)std::min<long long>((n + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_rmax, dim3(grid), dim3(256), 0, w->stream, static_cast<const float*>(w->r), n,
-                       static_cast<unsigned int*>(w->X));
+    if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL(k_rmax, dim3(grid), dim3(256), 0, w->stream, static_cast<const float*>(w->r), n,
+                           static_cast<unsigned int*>(w->X));
+    } else {
+        hipLaunchKernelGGL(k_rmax64, dim3(grid), dim3(256), 0, w->stream, static_cast<const double*>(w->r), n,
+                           static_cast<unsigned long long*>(w->X));
+    }
     ADI_LAUNCHED("rmax");
-    unsigned int bits = 0;
-    ADI_HIP(hipMemcpyAsync(&bits, w->X, sizeof(bits), hipMemcpyDeviceToHost, w->stream));
+    T v = T(0);
+    ADI_HIP(hipMemcpyAsync(&v, w->X, sizeof(T), hipMemcpyDeviceToHost, w->stream));
     ADI_HIP(hipStreamSynchronize(w->stream));
-    std::memcpy(&w->rmax, &bits, sizeof(bits));
+    w->rmax = (double)v;
     fused_plan(w);
     return ADI_OK;
 }
@@ -592,20 +650,24 @@ adi_status set_coef(adi_wave_s* w, const void* field, double scalar, int squared
     hipLaunchKernelGGL((k_xpivots<T>), dim3((w->ny + 255) / 256), dim3(256), 0, w->stream,
                        static_cast<const T*>(w->r), static_cast<T*>(w->qin), w->nx, w->ny, w->nseg);
     ADI_LAUNCHED("x_pivots");
-    if constexpr (sizeof(T) == 4) {
-        if (measure)
-            if (adi_status s = measure_rmax(w)) return s;
+    if (w->qin2) {
+        hipLaunchKernelGGL((k_xpivots<T, 2>), dim3((w->ny + 255) / 256), dim3(256), 0, w->stream,
+                           static_cast<const T*>(w->r), static_cast<T*>(w->qin2), w->nx, w->ny, (w->nx + 1) / 2);
+        ADI_LAUNCHED("x_pivots (2-node lanes)");
     }
+    if (measure)
+        if (adi_status s = measure_rmax<T>(w)) return s;
     return static_planes<T>(w);
 }
 
-adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const adi_source* f, int k)
+template <typename T>
+FArgsT<T> make_fargs(const adi_wave_s* w, const void* u_curr, void* u_prev, const adi_source* f, int k)
 {
-    FArgs a{};
-    a.uc = static_cast<const float*>(u_curr);
-    a.up = static_cast<float*>(u_prev);
-    a.r = static_cast<const float*>(w->r);
-    a.qin = static_cast<const float*>(w->qin);
+    FArgsT<T> a{};
+    a.uc = static_cast<const T*>(u_curr);
+    a.up = static_cast<T*>(u_prev);
+    a.r = static_cast<const T*>(w->r);
+    a.qin = static_cast<const T*>(w->qin);
     a.nx = w->nx;
     a.ny = w->ny;
     a.nseg = w->nseg;
@@ -614,18 +676,31 @@ adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const ad
     a.wide = w->f_wide;
     a.tiles = w->f_tiles;
     a.xcd_map = 1;
-    a.tau2 = (float)(w->dt * w->dt);
+    a.tau2 = (T)(w->dt * w->dt);
     if (f && f->count > 0) {
         a.nsrc = f->count;
         a.src_idx = f->idx;
-        a.src_amp = static_cast<const float*>(f->amp) + (size_t)k * f->count;
+        a.src_amp = static_cast<const T*>(f->amp) + (size_t)k * f->count;
     }
     a.nrec = w->tap_n;
     a.rec_idx = w->tap_idx;
-    a.rec_out = static_cast<float*>(w->tap_out);
+    a.rec_out = static_cast<T*>(w->tap_out);
     a.hs = w->f_hs;
+    return a;
+}
+
+adi_status queue_fused(adi_wave_s* w, const void* u_curr, void* u_prev, const adi_source* f, int k)
+{
+    if (w->dtype == ADI_F64) {
+        FArgsT<double> a = make_fargs<double>(w, u_curr, u_prev, f, k);
+        a.qin = static_cast<const double*>(w->qin2);   // entry pivot of every 2-node lane
+        hipLaunchKernelGGL(k_fusedr<double>, dim3(w->f_grid), dim3(kFrThreads64), 0, w->stream, a);
+        ADI_LAUNCHED("fused_step");
+        return ADI_OK;
+    }
+    const FArgs a = make_fargs<float>(w, u_curr, u_prev, f, k);
     if (w->f_hs > 0)
-        hipLaunchKernelGGL(k_fusedr, dim3(w->f_grid), dim3(kFrThreads), 0, w->stream, a);
+        hipLaunchKernelGGL(k_fusedr<float>, dim3(w->f_grid), dim3(kFrThreads), 0, w->stream, a);
     else if (w->f_lane == 4)
         hipLaunchKernelGGL(k_fused4, dim3(w->f_grid), dim3(1024), 0, w->stream, a);
     else
@@ -707,7 +782,7 @@ adi_status do_step(adi_wave_s* w, void** u_prev, void** u_curr, const adi_source
                    const adi_receivers* rec, int nsteps, bool allow_fused = true)
 {
     const bool cr = allow_fused && w->cr;
-    const bool fused = !cr && sizeof(T) == 4 && allow_fused && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
+    const bool fused = !cr && allow_fused && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
     const bool recs = rec && rec->count > 0;
     auto record = [&](int k, const void* level) -> adi_status {
         hipLaunchKernelGGL((k_record<T>), dim3((rec->count + 255) / 256), dim3(256), 0, w->stream,
@@ -812,7 +887,8 @@ adi_status adi_wave_create(adi_wave_t* out, int nx, int ny, double h, double dt,
     const size_t npts = (size_t)nx * ny;
     w->nseg = (nx + kSeg - 1) / kSeg;
     if (hipMalloc(&w->r, npts * es) != hipSuccess ||
-        hipMalloc(&w->qin, (size_t)ny * w->nseg * es) != hipSuccess) {
+        hipMalloc(&w->qin, (size_t)ny * w->nseg * es) != hipSuccess ||
+        (dtype == ADI_F64 && hipMalloc(&w->qin2, (size_t)ny * ((nx + 1) / 2) * es) != hipSuccess)) {
         (void)hipGetLastError();
         free_ws(w);
         delete w;
@@ -901,7 +977,7 @@ adi_status adi_wave_get_info(adi_wave_t w, adi_wave_info* info)
     info->workspace_bytes = w->bytes;
     info->fused_step = w->fstep;
     info->fused_allowed = w->fused_ok;
-    info->r_max = w->dtype == ADI_F32 ? (double)w->rmax : 0.0;
+    info->r_max = w->rmax;
     info->line_solver = w->cr ? 2 : 1;
     info->fused_tile_cols = w->f_wt;
     info->fused_tiles = w->f_tiles;
@@ -929,7 +1005,16 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
     if (M != 16 && M != 32) return fail(ADI_EINVAL, "y_chunk_rows must be 16 or 32");
     if (t->fused_step < 0 || t->fused_step > 2) return fail(ADI_EINVAL, "fused_step must be 0, 1 or 2");
     if (t->fused_step == 1 && !w->fused_ok)
-        return fail(ADI_EUNSUPPORTED, "the one-pass step needs FP32, nx % 4 == 0 and r <= 0.18 everywhere");
+        return fail(ADI_EUNSUPPORTED, w->dtype == ADI_F64
+                                          ? "the FP64 one-pass step needs nx % 2 == 0 and r <= 0.13 everywhere"
+                                          : "the one-pass step needs nx % 4 == 0 and r <= 0.18 everywhere");
+    if (w->dtype == ADI_F64) {
+        // FP64 runs on column strips only, at most kFrS64 columns wide
+        if (t->fused_lane_nodes > 0 || t->fused_segment_rows == -2)
+            return fail(ADI_EINVAL, "the FP64 one-pass step runs on column strips (no tiles, no lane setting)");
+        if (t->fused_tile_cols > 0 && (t->fused_tile_cols % 8 != 0 || t->fused_tile_cols > kFrS64))
+            return fail(ADI_EINVAL, "FP64 column strips: fused_tile_cols must be a multiple of 8 and at most 96");
+    }
     if (t->fused_lane_nodes != 0 && t->fused_lane_nodes != -1 && t->fused_lane_nodes != 4 &&
         t->fused_lane_nodes != 8)
         return fail(ADI_EINVAL, "fused_lane_nodes must be -1, 0, 4 or 8");
@@ -990,7 +1075,7 @@ adi_status adi_wave_profile(adi_wave_t w, void** u_prev, void** u_curr, const ad
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) { st = fail(ADI_EHIP, "hipEventCreate failed"); break; }
     const bool cr = w->cr != 0;
-    const bool fused = cr || (w->dtype == ADI_F32 && w->fstep && aligned16(*u_prev) && aligned16(*u_curr));
+    const bool fused = cr || (w->fstep && aligned16(*u_prev) && aligned16(*u_curr));
     for (int k = 0; k < nsteps && st == ADI_OK; ++k) {
         hipEvent_t* e = &ev[(size_t)k * 5];
         if (fused) {   // one timed range per step (one-pass step, or the whole cyclic-reduction step)

@@ -47,25 +47,27 @@ constexpr int kFuNT = 2;            // buffer cache policy: non-temporal (a last
 constexpr int kFuOOB = 0x40000000;  // byte offset beyond every buffer range used here
                                     // (grids hold at most 2^27 values, 2^29 bytes)
 
-struct FArgs {
-    const float* uc;     // u^n
-    float* up;           // u^{n-1} in, u^{n+1} out
-    const float* r;
-    const float* qin;    // full-line entry pivot of every 8-node x-segment
+template <typename T>
+struct FArgsT {
+    const T* uc;         // u^n
+    T* up;               // u^{n-1} in, u^{n+1} out
+    const T* r;
+    const T* qin;        // full-line entry pivot of every 8-node x-segment
     int nx, ny, nseg;
     int wt;              // output columns per tile (multiple of 8)
     int tiles_x, tiles;  // tiles across, total tiles
     int wide;            // column strips (fusedr.hpp): strips 0..wide-1 are wt wide, the others wt - 8
     int xcd_map;         // 1: block -> tile map that keeps neighbours on one XCD
     int hs;              // column strips (fusedr.hpp): output rows per strip segment
-    float tau2;
+    T tau2;
     int nsrc;
     const int* src_idx;
-    const float* src_amp;
+    const T* src_amp;
     int nrec;            // receivers of the previous step, sampled from uc (see rec_tap)
     const int* rec_idx;
-    float* rec_out;
+    T* rec_out;
 };
+using FArgs = FArgsT<float>;   // the tile kernels are FP32; the column strips take both
 
 struct FShared {
     float w[kFuRows * kFuWmax];
@@ -377,6 +379,22 @@ __global__ void __launch_bounds__(256) k_rmax(const float* __restrict__ r, long 
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+// the same for FP64 r (the double bits order like the values)
+__global__ void __launch_bounds__(256) k_rmax64(const double* __restrict__ r, long long n, unsigned long long* out)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        m = fmax(m, r[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
 }
 
 }  // namespace adw

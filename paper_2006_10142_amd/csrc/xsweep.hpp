@@ -259,8 +259,9 @@ struct XArgs {
 constexpr int kSeg = 8;   // nodes per x-line segment (one segment per thread)
 constexpr int kPB = 16;   // column block width of the y-chunk summary planes
 
-// pivot entering every segment of every row: one thread per row, sequential
-template <typename T>
+// pivot entering every segment of SEG nodes of every row (SEG = kSeg: the x-sweep's
+// segments; 2: the lanes of the FP64 one-pass strips): one thread per row, sequential
+template <typename T, int SEG = kSeg>
 __global__ void __launch_bounds__(256) k_xpivots(const T* __restrict__ r, T* __restrict__ qin,
                                                  int nx, int ny, int nseg)
 {
@@ -271,8 +272,8 @@ __global__ void __launch_bounds__(256) k_xpivots(const T* __restrict__ r, T* __r
     T q = T(0);
     for (int s = 0; s < nseg; ++s) {
         qo[s] = q;
-        for (int e = 0; e < kSeg; ++e) {
-            const int i = kSeg * s + e;
+        for (int e = 0; e < SEG; ++e) {
+            const int i = SEG * s + e;
             if (i < nx) (void)pivot_step<T>(rr[i], q);
         }
     }

@@ -46,30 +46,31 @@ def say(msg):
     print(msg, flush=True)
 
 
-def case(nx, ny, cfl=0.4, seed=3, nsteps=30, nsrc=2, nrec=6):
+def case(nx, ny, cfl=0.4, seed=3, nsteps=30, nsrc=2, nrec=6, f64=False):
+    npd = np.float64 if f64 else np.float32
     h = 1.0 / (max(nx, ny) + 1)
-    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=seed).astype(np.float32)
+    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=seed).astype(npd)
     dt = cfl * h / 3.0
-    u0 = wl.gaussian_pulse(nx, ny, sigma=0.08).astype(np.float32)
+    u0 = wl.gaussian_pulse(nx, ny, sigma=0.08).astype(npd)
     rng = np.random.default_rng(seed)
     si = np.stack([rng.integers(0, ny, nsrc), rng.integers(0, nx, nsrc)], 1)
     src_idx = (si[:, 0] * nx + si[:, 1]).astype(np.int32)
-    amp = (rng.standard_normal((nsteps, nsrc)) * 50.0).astype(np.float32)
+    amp = (rng.standard_normal((nsteps, nsrc)) * 50.0).astype(npd)
     ri = np.stack([rng.integers(0, ny, nrec), rng.integers(0, nx, nrec)], 1)
     rec_idx = (ri[:, 0] * nx + ri[:, 1]).astype(np.int32)
     return dict(nx=nx, ny=ny, h=h, dt=dt, c=c, u0=u0, src_idx=src_idx, amp=amp, rec_idx=rec_idx,
-                nsteps=nsteps)
+                nsteps=nsteps, dtype=torch.float64 if f64 else torch.float32)
 
 
 def gpu(adw, k, one_pass):
-    wave = adw.Wave(k["nx"], k["ny"], k["h"], k["dt"], c=dev(k["c"]), dtype=torch.float32)
+    wave = adw.Wave(k["nx"], k["ny"], k["h"], k["dt"], c=dev(k["c"]), dtype=k["dtype"])
     wave.set_tuning(fused_step=one_pass, fused_lane_nodes=k.get("lane", 0), fused_tile_cols=k.get("tile_cols", 0),
                     fused_segment_rows=k.get("hs", 0))
     info = wave.info()
     assert info["fused_step"] == int(one_pass)
     a = dev(k["u0"])
     b = wave.start(a)
-    tr = torch.zeros((k["nsteps"], k["rec_idx"].size), dtype=torch.float32, device="cuda")
+    tr = torch.zeros((k["nsteps"], k["rec_idx"].size), dtype=k["dtype"], device="cuda")
     a, b = wave.step(a, b, k["nsteps"], src_idx=dev(k["src_idx"]), src_amp=dev(k["amp"]),
                      rec_idx=dev(k["rec_idx"]), traces=tr)
     torch.cuda.synchronize()
@@ -95,7 +96,14 @@ def test_plan_selection_and_bound(adw):
     i = info(2048, 2048, 0.5)                       # C2: r = 1/8
     assert abs(i["r_max"] - 0.125) < 1e-6
     assert i["fused_allowed"] == 1 and i["fused_step"] == 1 and i["kernels_per_step"] == 1
-    assert info(2048, 2048, 0.5, dtype=torch.float64)["fused_allowed"] == 0
+    # FP64: the bound 4 qs^17 <= 2^-53 of the FP64 column strips (K = 16)
+    i = info(2048, 2048, 0.5, dtype=torch.float64)                # r = 0.125, qs = 0.101
+    assert abs(i["r_max"] - 0.125) < 1e-12
+    assert i["fused_allowed"] == 1 and i["fused_step"] == 1 and i["fused_segment_rows"] > 0
+    assert info(1024, 1024, 0.51, dtype=torch.float64)["fused_allowed"] == 1   # r = 0.130
+    assert info(1024, 1024, 0.52, dtype=torch.float64)["fused_allowed"] == 0   # r = 0.135: bound fails
+    assert info(1023, 1024, 0.5, dtype=torch.float64)["fused_allowed"] == 0    # rows not 16-byte multiples
+    assert info(128, 128, 0.5, dtype=torch.float64)["fused_step"] == 0         # small grids keep two passes
     assert info(1022, 1024, 0.5)["fused_allowed"] == 0            # rows not 16-byte multiples
     assert info(1024, 1024, 0.58)["fused_allowed"] == 1           # r = 0.168
     assert info(1024, 1024, 0.62)["fused_allowed"] == 0           # r = 0.192: bound fails
@@ -198,6 +206,45 @@ def test_one_pass_matches_oracle(adw, oracle_lib, nx, ny, layout):
     ref, rtr = oracle(oracle_lib, k)
     check(got, ref, what="level")
     check(tr, rtr, what="traces")
+
+
+TOL64, TOL64_MAX = 1e-12, 1e-11
+F64_STRIP_LAYOUTS = {"auto": -1, "strips_h8": 8, "strips_h30": 30, "strips_h1000": 1000}
+
+
+@pytest.mark.parametrize("nx,ny", [(480, 64), (488, 65), (1000, 700), (960, 130), (64, 64), (2048, 300),
+                                   (4, 200), (1504, 33), (64, 1), (40, 3), (194, 90)])
+@pytest.mark.parametrize("layout", sorted(F64_STRIP_LAYOUTS))
+def test_one_pass_f64_matches_oracle(adw, oracle_lib, nx, ny, layout):
+    """The FP64 one-pass step (column strips of at most 96 columns, 16 halo columns and
+    rows, truncation bound 4 qs^17 below 2^-53) against the FP64 oracle after 30 steps
+    with two point sources and six receivers: relative L2 <= 1e-12 and max-norm
+    <= 1e-11 (level and traces); the plan's automatic strips and 8-, 30- and 1000-row
+    segments (bands cut anywhere, segments shorter than a band, longer than the grid)."""
+    k = case(nx, ny, seed=nx + 7 * ny, f64=True)
+    k["lane"], k["tile_cols"], k["hs"] = 0, -1, F64_STRIP_LAYOUTS[layout]
+    say(f"one-pass f64 {nx}x{ny} {layout}")
+    got, tr, info = gpu(adw, k, True)
+    assert info["fused_step"] == 1 and info["fused_segment_rows"] > 0 and info["fused_tile_cols"] <= 96
+    if layout != "auto":
+        assert info["fused_segment_rows"] == k["hs"]
+    ref, rtr = oracle(oracle_lib, k)
+    check(got, ref, TOL64, TOL64_MAX, "level")
+    check(tr, rtr, TOL64, TOL64_MAX, "traces")
+
+
+def test_one_pass_f64_forced_widths_agree(adw, oracle_lib):
+    """FP64 strips forced to 32, 64 and 96 columns (one width each) and the automatic
+    mix reach the oracle's level to the FP64 bars on a 1000 x 700 grid."""
+    k = case(1000, 700, seed=12, f64=True, nsteps=20)
+    ref, _ = oracle(oracle_lib, k)
+    for wt in (32, 64, 96, -1):
+        k["lane"], k["tile_cols"], k["hs"] = 0, wt, -1 if wt == -1 else 200
+        say(f"one-pass f64 width {wt}")
+        got, _, info = gpu(adw, k, True)
+        if wt > 0:
+            assert info["fused_tile_cols"] == wt and info["fused_strips_wide"] == -(-1000 // wt)
+        check(got, ref, TOL64, TOL64_MAX, f"width {wt}")
 
 
 def test_one_pass_mixed_strip_widths(adw, oracle_lib):

@@ -335,7 +335,7 @@ def test_step_rotation_and_determinism(adw):
     assert g2 is g and h2 is h_ and torch.equal(h2, u1)
 
 
-@pytest.mark.parametrize("path", ["one_pass", "two_pass", "two_pass_f64", "cyclic_reduction"])
+@pytest.mark.parametrize("path", ["one_pass", "two_pass", "one_pass_f64", "two_pass_f64", "cyclic_reduction"])
 def test_receiver_traces_every_path(adw, path):
     """Traces of a multi-step call equal those of one-step calls bit for bit, and equal
     each level sampled on the host.  Within a call, a step's receivers are recorded by
@@ -343,7 +343,7 @@ def test_receiver_traces_every_path(adw, path):
     uses 1500 receivers (more than one workgroup's threads), with repeated nodes and
     offsets outside the grid, which record NaN."""
     nx, ny, nsteps = 512, 300, 6
-    f64 = path == "two_pass_f64"
+    f64 = path.endswith("_f64")
     dt_ = torch.float64 if f64 else torch.float32
     h = 1.0 / (max(nx, ny) + 1)
     c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=8).astype(np.float64 if f64 else np.float32)
@@ -357,9 +357,9 @@ def test_receiver_traces_every_path(adw, path):
     amp = (rng.standard_normal((nsteps, 1)) * 30.0).astype(c.dtype)
     say(f"receiver traces {path}")
     wave = adw.Wave(nx, ny, h, 0.4 * h / 3.0, c=dev(c), dtype=dt_)
-    wave.set_tuning(fused_step={"one_pass": True, "two_pass_f64": None}.get(path, False),
+    wave.set_tuning(fused_step=path.startswith("one_pass"),
                     cyclic_reduction=True if path == "cyclic_reduction" else None)
-    assert wave.info()["fused_step"] == int(path == "one_pass")
+    assert wave.info()["fused_step"] == int(path.startswith("one_pass"))
     assert wave.info()["line_solver"] == (2 if path == "cyclic_reduction" else 1)
     a0 = dev(u0)
     b0 = wave.start(a0)
