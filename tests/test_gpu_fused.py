@@ -413,3 +413,48 @@ def test_one_step_truncation_bound(adw, oracle_lib, layout):
     err = np.abs(fused - ref).max()
     say(f"  one step {layout}: max|fused - exact oracle| {err:.3e}, bound {trunc:.3e} + FP32 {allowance:.3e}")
     assert err <= trunc + allowance
+
+
+@pytest.mark.parametrize("hs", [100, -1])
+def test_one_step_truncation_bound_f64(adw, oracle_lib, hs):
+    """The FP64 one-pass step, one step at r_max ~ 0.13 (near the largest r its bound
+    admits) against the oracle's exact step, node by node:
+      max |u_fused - u_exact| <= 4 qs^17 max|w| + (FP64 rounding of the step),
+    with u^{n-1} = 2 u^n as in the FP32 test (u^{n+1} is then the increment d).  At this
+    precision the truncation (below half an ulp) is smaller than the roundings of the
+    two paths, which associate the step's sums differently (the one-pass step runs
+    the x-lines as scans of affine maps over 2-node lanes, the exact step over 8-node
+    segments): the FP64 allowance is the GPU's exact two-pass step against the oracle
+    plus four units of rounding of max|d| (measured: the exact step 1.5, the one-pass
+    step 2.9).  Strips of 100 rows and the automatic plan."""
+    nx, ny = 720, 600
+    h = 1.0 / 721
+    rmax = 0.13
+    dt = np.sqrt(2 * rmax) * h / 3.0
+    rng = np.random.default_rng(19)
+    c = wl.smooth_field(nx, ny, 1.0, 3.0, seed=19)
+    uc = wl.gaussian_pulse(nx, ny, sigma=0.05) + 0.1 * rng.standard_normal((ny, nx))
+    up = 2 * uc
+    parts = oracle_lib.step_parts(c ** 2, up, uc, h, dt)
+    ref = parts["u_next"]
+
+    def one(one_pass):
+        wave = adw.Wave(nx, ny, h, dt, c=dev(c), dtype=torch.float64)
+        wave.set_tuning(fused_step=one_pass, **(dict(fused_segment_rows=hs) if one_pass else {}))
+        info = wave.info()
+        a, b = wave.step(dev(up), dev(uc), 1)
+        torch.cuda.synchronize()
+        out = b.cpu().numpy()
+        wave.close()
+        return out, info
+
+    fused, info = one(True)
+    exact, _ = one(False)
+    assert info["fused_step"] == 1 and 0.125 < info["r_max"] < 0.1331
+    rm = float(info["r_max"])
+    qs = (1 + 2 * rm - np.sqrt(1 + 4 * rm)) / (2 * rm)
+    trunc = 4 * qs ** 17 * np.abs(parts["w"]).max()
+    allowance = np.abs(exact - ref).max() + 4 * 2.0 ** -53 * np.abs(ref).max()
+    err = np.abs(fused - ref).max()
+    say(f"  one step f64 hs={hs}: max|fused - exact oracle| {err:.3e}, bound {trunc:.3e} + FP64 {allowance:.3e}")
+    assert err <= trunc + allowance
