@@ -115,7 +115,7 @@ def cpu_baseline(prob, steps: int):
     oracle.run(k1, np.ascontiguousarray(up[:n1, :n1]), np.ascontiguousarray(uc[:n1, :n1]), prob.h, prob.dt, 1,
                threads=1)
     t1 = time.perf_counter() - t1
-    return {"value": prob.nx * prob.ny * steps / t / 1e6, "unit": "Mpts/s",
+    return {"value": round(prob.nx * prob.ny * steps / t / 1e6, 2), "unit": "Mpts/s",
             "cores": cores, "kind": "oracle",
             "build": "gcc -O2 -fopenmp -ffp-contract=off, no -march; OpenMP over lines; x-lines "
                      "row by row, y-lines one column at a time (stride nx); untuned",
