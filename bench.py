@@ -170,7 +170,7 @@ def bench_batched(adw, torch, steps: int, warmup: int, plain_value: float):
             "unit": "Mpts/s", "ms_per_step": round(ms / steps, 5), "sims": len(probs),
             "nodes_per_step": nodes, "steps": steps, "graph": True,
             "plan": {k: plan[k] for k in ("x_threads_per_line", "x_grid", "yscan_grid",
-                                          "ysolve_grid", "fused_lane_nodes")},
+                                          "ysolve_grid", "fused_lane_nodes", "fused_strips")},
             "autotune_ms_per_step": round(tuned_ms, 5),
             "step": "one-pass" if plan["fused_step"] else "two-pass",
             "step_algorithmic_bytes_per_node": 4 * (FUSED_STEP_BYTES_PER_NODE if plan["fused_step"]

@@ -267,10 +267,15 @@ typedef struct {
                                  simulation's truncation bound holds; the default then),
                                  2 (set only): exact two-pass step, 0 (set): keep */
     int fused_allowed;        /* read-only: the one-pass step is allowed for the batch */
-    int fused_items;          /* read-only: one-pass tiles over all simulations */
-    int fused_lane_nodes;     /* one-pass x-line nodes per lane: 8 (default) or 4 (narrower
-                                 tiles with r kept in LDS), 0 (set) = keep; the autotuner
-                                 times both */
+    int fused_items;          /* read-only: one-pass work items (tiles or strip segments)
+                                 over all simulations */
+    int fused_lane_nodes;     /* one-pass tiles: x-line nodes per lane, 8 (default) or 4
+                                 (narrower tiles with r kept in LDS), 0 (set) = keep */
+    int fused_strips;         /* 1: the one-pass step on column strips instead of tiles
+                                 (each simulation's fewest strips of at most 240 columns, of
+                                 one width, in segments of at most 1024 rows), 0 (get): on
+                                 tiles; set: 1 = strips, 2 = tiles, 0 = keep.  The
+                                 autotuner times both tile kinds and the strips */
 } adi_batch_plan;
 adi_status adi_batch_get_plan(adi_batch_t b, adi_batch_plan* p);
 adi_status adi_batch_set_plan(adi_batch_t b, const adi_batch_plan* p);

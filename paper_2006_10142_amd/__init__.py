@@ -398,10 +398,12 @@ class Batch:
         return {f: getattr(p, f) for f, _ in _lib.AdiBatchPlan._fields_}
 
     def set_plan(self, x_threads_per_line=0, x_grid=0, yscan_grid=0, ysolve_grid=0, fused_step=None,
-                 fused_lane_nodes=0):
+                 fused_lane_nodes=0, fused_strips=None):
         """Launch plan of the two-pass step; fused_step: True = one-pass step for every
         simulation (FP32, when allowed), False = exact two-pass step, None = keep;
-        fused_lane_nodes: 8 or 4 nodes per lane of the one-pass tiles (0 = keep)."""
+        fused_lane_nodes: 8 or 4 nodes per lane of the one-pass tiles (0 = keep);
+        fused_strips: True = the one-pass step on column strips, False = on tiles,
+        None = keep."""
         p = _lib.AdiBatchPlan()
         _lib.check(_lib.load().adi_batch_get_plan(self._h, ctypes.byref(p)))
         if x_threads_per_line:
@@ -409,6 +411,7 @@ class Batch:
         p.x_grid, p.yscan_grid, p.ysolve_grid = x_grid, yscan_grid, ysolve_grid
         p.fused_step = 0 if fused_step is None else (1 if fused_step else 2)
         p.fused_lane_nodes = fused_lane_nodes
+        p.fused_strips = 0 if fused_strips is None else (1 if fused_strips else 2)
         _lib.check(_lib.load().adi_batch_set_plan(self._h, ctypes.byref(p)))
 
     def autotune(self, trial_steps: int = 10, cache: Optional[str] = None) -> float:
@@ -425,8 +428,10 @@ class Batch:
                 except Exception:
                     ent = None
                 if ent:
+                    strips = ent.get("fused_strips")
                     self.set_plan(ent["x_threads_per_line"], ent["x_grid"], ent["yscan_grid"],
-                                  ent["ysolve_grid"], fused_lane_nodes=ent.get("fused_lane_nodes", 0))
+                                  ent["ysolve_grid"], fused_lane_nodes=ent.get("fused_lane_nodes", 0),
+                                  fused_strips=None if strips is None else bool(strips))
                     return float(ent["ms_per_step"])
         best = ctypes.c_double(0.0)
         _lib.check(_lib.load().adi_batch_autotune(self._h, int(trial_steps), ctypes.byref(best)))
@@ -439,7 +444,7 @@ class Batch:
                 except Exception:
                     data = {}
             data[key] = {k: p[k] for k in ("x_threads_per_line", "x_grid", "yscan_grid",
-                                           "ysolve_grid", "fused_lane_nodes")}
+                                           "ysolve_grid", "fused_lane_nodes", "fused_strips")}
             data[key]["ms_per_step"] = best.value
             os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
             json.dump(data, open(cache, "w"), indent=1)

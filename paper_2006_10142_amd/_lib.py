@@ -56,7 +56,8 @@ class AdiBatchPlan(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("x_items", ctypes.c_int),
                 ("yscan_items", ctypes.c_int), ("ysolve_items", ctypes.c_int),
                 ("fused_step", ctypes.c_int), ("fused_allowed", ctypes.c_int),
-                ("fused_items", ctypes.c_int), ("fused_lane_nodes", ctypes.c_int)]
+                ("fused_items", ctypes.c_int), ("fused_lane_nodes", ctypes.c_int),
+                ("fused_strips", ctypes.c_int)]
 
 
 _SIGNATURES = {

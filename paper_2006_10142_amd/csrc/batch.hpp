@@ -13,11 +13,14 @@
 
 namespace adw {
 
+constexpr int kBatchStripRows = 1024;   // longest strip segment of a batched simulation
+
 template <typename T>
 struct SimDesc {
     int nx, ny, nseg, K, nxp, vec;
     int f_wt, f_tx, f_tiles;   // one-pass tiles (see fused.hpp)
     int f4_wt, f4_tx, f4_tiles;   // one-pass tiles with four nodes per lane (fused4.hpp)
+    int s_wt, s_tx, s_hs, s_tiles;   // one-pass column strips (fusedr.hpp): width, strips, segment rows
     T* r;
     T* w;
     T* qin;
@@ -88,6 +91,36 @@ __global__ void __launch_bounds__(1024) k_fused4_batch(FBatchArgs B)
     A.tiles_x = __builtin_amdgcn_readfirstlane(S.f4_tx);
     A.tiles = __builtin_amdgcn_readfirstlane(S.f4_tiles);
     fused4_tile(A, __builtin_amdgcn_readfirstlane(wi.y), sh);
+}
+
+// the one-pass step on column strips (fusedr.hpp): work list of (simulation,
+// strip segment), one per workgroup, in the order the host dealt it (block k
+// takes item k: the XCD queues interleaved, padding items (-1, -1)); each
+// simulation's strips are of one width (the last one cut by the grid's edge),
+// so a plain handle tuned to the same width and segment rows runs the same
+// arithmetic
+__global__ void __launch_bounds__(Fr<float>::THREADS) k_fusedr_batch(FBatchArgs B)
+{
+    __shared__ FRShared<float> sh;
+    const int it = blockIdx.x;
+    if (it >= B.nitems) return;
+    const int2 wi = B.items[it];
+    if (wi.x < 0) return;
+    const SimDesc<float>& S = B.sims[wi.x];
+    FArgsT<float> A{};
+    A.uc = S.lev[B.u_slot];
+    A.up = S.lev[B.out_slot];
+    A.r = S.r;
+    A.qin = S.qin;
+    A.nx = __builtin_amdgcn_readfirstlane(S.nx);
+    A.ny = __builtin_amdgcn_readfirstlane(S.ny);
+    A.nseg = __builtin_amdgcn_readfirstlane(S.nseg);
+    A.wt = __builtin_amdgcn_readfirstlane(S.s_wt);
+    A.tiles_x = __builtin_amdgcn_readfirstlane(S.s_tx);
+    A.wide = A.tiles_x;
+    A.hs = __builtin_amdgcn_readfirstlane(S.s_hs);
+    A.tiles = __builtin_amdgcn_readfirstlane(S.s_tiles);
+    fusedr_strip<float>(A, __builtin_amdgcn_readfirstlane(wi.y), sh);
 }
 
 template <typename T, int TR>
@@ -207,8 +240,12 @@ struct adi_batch_s {
     // one-pass step: allowed when every simulation allows it (FP32, bound holds)
     int fused_ok = 0, fused = 0;
     int flane = 8;                  // nodes per lane of the one-pass tiles (8 or 4)
-    int2* fitems = nullptr;         // (simulation, tile) of the eight-node tiles, then the four-node ones
-    int nf_items = 0, nf4_items = 0;
+    int fstrips = 0;                // 1: the one-pass step on column strips instead of tiles
+    int2* fitems = nullptr;         // (simulation, tile) of the eight-node tiles, then the four-node
+                                    // ones, then (simulation, strip segment) of the column strips
+    int nf_items = 0, nf4_items = 0, nfs_items = 0;   // list lengths (the strips' with padding)
+    int nfs_segments = 0;           // strip segments over all simulations
+    std::vector<int> s_wt, s_tx, s_hs, s_tiles;   // column-strip plan of every simulation
 };
 
 namespace {
@@ -229,6 +266,22 @@ void batch_free(adi_batch_s* b)
 
 bool batch_fits(int tr, adi_dtype dt) { return fuse_fits(tr, dt); }
 
+
+// One-pass column strips of one simulation of a batch: the fewest strips of at
+// most 240 columns, all of one width (a multiple of 8; the last strip is cut by
+// the grid's edge), and segments of at most kBatchStripRows rows of even length.
+// The many simulations fill the device, so no segment count per compute unit is
+// sought (the plain plan's rule).
+void batch_strip_plan(int nx, int ny, int& wt, int& tx, int& hs, int& tiles)
+{
+    tx = (nx + kFrS - 1) / kFrS;
+    wt = std::min(kFrS, ((nx + tx - 1) / tx + 7) / 8 * 8);
+    tx = (nx + wt - 1) / wt;
+    const int seg = (ny + kBatchStripRows - 1) / kBatchStripRows;
+    hs = (ny + seg - 1) / seg;
+    tiles = tx * ((ny + hs - 1) / hs);
+}
+
 template <typename T>
 void fill_desc(adi_batch_s* b)
 {
@@ -239,6 +292,9 @@ void fill_desc(adi_batch_s* b)
         d[s].nx = w.nx; d[s].ny = w.ny; d[s].nseg = w.nseg; d[s].K = w.K; d[s].nxp = w.nxp;
         d[s].f_wt = w.f_wt; d[s].f_tx = w.f_tx; d[s].f_tiles = w.f_tiles;
         d[s].f4_wt = w.f4_wt; d[s].f4_tx = w.f4_tx; d[s].f4_tiles = w.f4_tiles;
+        if (!b->s_wt.empty()) {
+            d[s].s_wt = b->s_wt[s]; d[s].s_tx = b->s_tx[s]; d[s].s_hs = b->s_hs[s]; d[s].s_tiles = b->s_tiles[s];
+        }
         d[s].vec = ((size_t)w.nx * sizeof(T)) % 16 == 0;
         d[s].r = (T*)w.r; d[s].w = (T*)w.w; d[s].qin = (T*)w.qin; d[s].sum = (T*)w.sum; d[s].X = (T*)w.X;
         d[s].lev[0] = b->bound ? (T*)b->lev0[s] : nullptr;
@@ -328,6 +384,13 @@ adi_status queue_batch_solve(adi_batch_s* b, int u_slot, int v_slot, int out_slo
 adi_status batch_step_once(adi_batch_s* b, hipStream_t st, int parity)
 {
     const int p = parity;
+    if (b->fused && b->fstrips) {
+        FBatchArgs a{static_cast<const SimDesc<float>*>(b->desc), b->fitems + b->nf_items + b->nf4_items,
+                     b->nfs_items, p ^ 1, p};
+        hipLaunchKernelGGL(k_fusedr_batch, dim3((b->nfs_items + 7) / 8 * 8), dim3(Fr<float>::THREADS), 0, st, a);
+        ADI_LAUNCHED("fused_batch");
+        return ADI_OK;
+    }
     if (b->fused && b->flane == 4) {
         FBatchArgs a{static_cast<const SimDesc<float>*>(b->desc), b->fitems + b->nf_items, b->nf4_items, p ^ 1, p};
         hipLaunchKernelGGL(k_fused4_batch, dim3((b->nf4_items + 7) / 8 * 8), dim3(1024), 0, st, a);
@@ -514,6 +577,53 @@ adi_status adi_batch_create(adi_batch_t* out, int count, const int* nx, const in
         for (int s = 0; s < count && b->fused_ok; ++s)
             for (int tl = 0; tl < b->sims[s].f4_tiles; ++tl) fi.push_back(make_int2(s, tl));
         b->nf4_items = (int)fi.size() - b->nf_items;
+        b->s_wt.assign(count, 0); b->s_tx.assign(count, 0); b->s_hs.assign(count, 0); b->s_tiles.assign(count, 0);
+        for (int s = 0; s < count && b->fused_ok; ++s) {
+            batch_strip_plan(nx[s], ny[s], b->s_wt[s], b->s_tx[s], b->s_hs[s], b->s_tiles[s]);
+            for (int tl = 0; tl < b->s_tiles[s]; ++tl) fi.push_back(make_int2(s, tl));
+        }
+        b->nfs_items = (int)fi.size() - b->nf_items - b->nf4_items;
+        {
+            // Load balance: whole simulations are dealt to 8 queues, one per XCD, the
+            // largest first to the least loaded queue (so a simulation's neighbouring
+            // strips share one L2), and each queue runs its longest segments first, so
+            // that the short ones fill in at the end.  Block k of the launch takes
+            // entry k / 8 of queue k mod 8 (the hardware hands blocks to the XCDs in
+            // turn); entries past a queue's end are (-1, -1).  Cost of a segment: its
+            // x-window columns times its x-rows.
+            auto cost = [&](int2 q) {
+                const int s = q.x, r0 = (q.y / b->s_tx[s]) * b->s_hs[s];
+                return (long long)(b->s_wt[s] + 2 * kFuKx) * (std::min(b->s_hs[s], ny[s] - r0) + 2 * kFuKy);
+            };
+            b->nfs_segments = b->nfs_items;
+            std::vector<int2> strip(fi.end() - b->nfs_items, fi.end());
+            fi.resize(fi.size() - b->nfs_items);
+            std::vector<long long> scost(count, 0);
+            std::vector<std::vector<int2>> per(count);
+            for (const int2& q : strip) {
+                scost[q.x] += cost(q);
+                per[q.x].push_back(q);
+            }
+            std::vector<int> ord;
+            for (int s = 0; s < count; ++s)
+                if (scost[s] > 0) ord.push_back(s);
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return scost[x] > scost[y]; });
+            std::vector<std::vector<int2>> qs(8);
+            std::vector<long long> load(8, 0);
+            for (int s : ord) {
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (const int2& q : per[s]) qs[x].push_back(q);
+                load[x] += scost[s];
+            }
+            size_t len = 0;
+            for (auto& q : qs) {
+                std::stable_sort(q.begin(), q.end(), [&](int2 x, int2 y) { return cost(x) > cost(y); });
+                len = std::max(len, q.size());
+            }
+            for (size_t k = 0; k < len; ++k)
+                for (int x = 0; x < 8; ++x) fi.push_back(k < qs[x].size() ? qs[x][k] : make_int2(-1, -1));
+            b->nfs_items = (int)(8 * len);
+        }
         if (b->fused_ok) {
             if (hipMalloc(&b->fitems, fi.size() * sizeof(int2)) != hipSuccess) {
                 (void)hipGetLastError();
@@ -629,8 +739,9 @@ adi_status adi_batch_get_plan(adi_batch_t b, adi_batch_plan* p)
     p->ysolve_items = b->nyv_items;
     p->fused_step = b->fused;
     p->fused_allowed = b->fused_ok;
-    p->fused_items = b->flane == 4 ? b->nf4_items : b->nf_items;
+    p->fused_items = b->fstrips ? b->nfs_segments : b->flane == 4 ? b->nf4_items : b->nf_items;
     p->fused_lane_nodes = b->flane;
+    p->fused_strips = b->fstrips;
     return ADI_OK;
 }
 
@@ -649,7 +760,9 @@ adi_status adi_batch_set_plan(adi_batch_t b, const adi_batch_plan* p)
         return fail(ADI_EUNSUPPORTED, "the one-pass step is not allowed for every simulation of the batch");
     if (p->fused_lane_nodes != 0 && p->fused_lane_nodes != 4 && p->fused_lane_nodes != 8)
         return fail(ADI_EINVAL, "fused_lane_nodes must be 0, 4 or 8");
+    if (p->fused_strips < 0 || p->fused_strips > 2) return fail(ADI_EINVAL, "fused_strips must be 0, 1 or 2");
     if (p->fused_step > 0) b->fused = p->fused_step == 1 ? 1 : 0;
+    if (p->fused_strips) b->fstrips = p->fused_strips == 1 ? 1 : 0;
     if (p->fused_lane_nodes) b->flane = p->fused_lane_nodes;
     b->x_tr = tr;
     b->x_grid = p->x_grid;
@@ -708,15 +821,17 @@ adi_status adi_batch_autotune(adi_batch_t b, int trial_steps, double* best_ms)
     int btr = b->x_tr, bxg = b->x_grid, bsg = b->ys_grid, bvg = b->yv_grid;
     static const int grids[] = {0, 256, 512, 1024, 2048, 4096};
     if (st == ADI_OK && b->fused) {
-        // the one-pass step: the faster of its two tile kinds
-        int blane = b->flane;
-        for (int lane : {8, 4}) {
-            b->flane = lane;
+        // the one-pass step: the fastest of its two tile kinds and the column strips
+        int blane = b->flane, bstrips = b->fstrips;
+        for (int kind : {8, 4, 0}) {
+            b->fstrips = kind == 0 ? 1 : 0;
+            if (kind) b->flane = kind;
             double ms = 0;
             if ((st = trial(ms)) != ADI_OK) break;
-            if (ms < best) { best = ms; blane = lane; }
+            if (ms < best) { best = ms; blane = b->flane; bstrips = b->fstrips; }
         }
         b->flane = blane;
+        b->fstrips = bstrips;
     } else if (st == ADI_OK) {
         for (int tr : {128, 256, 1024}) {
             if (8LL * tr < b->max_nx || !batch_fits(tr, b->dtype)) continue;

@@ -174,19 +174,15 @@ __device__ __forceinline__ void fr_scan_bwd2(T& a, T& b, int lane)
     }
 }
 
+// One strip segment (blk = segment row * tiles_x + strip) of the grid A
+// describes, by the whole workgroup.
 template <typename T>
-__global__ void __launch_bounds__(Fr<T>::THREADS) k_fusedr(FArgsT<T> A)
+__device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShared<T>& sh)
 {
     using C = FrCfg<T>;
     constexpr int NPL = C::NPL, KX = C::KX, KY = C::KY, KG = C::KG;
     constexpr int R = Fr<T>::R, S = Fr<T>::S, XR = Fr<T>::XR;
     constexpr int ES = (int)sizeof(T);
-    __shared__ FRShared<T> sh;
-    rec_tap<T>(A.uc, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
-    // neighbouring strips of a segment row run on one XCD (their halo columns meet
-    // in that XCD's L2): the grid is a multiple of 8 and blocks past the tiles exit
-    const int blk = A.xcd_map ? xcd_band(blockIdx.x) : (int)blockIdx.x;
-    if (blk >= A.tiles) return;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -553,6 +549,18 @@ __global__ void __launch_bounds__(Fr<T>::THREADS) k_fusedr(FArgsT<T> A)
             __syncthreads();
         }
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(Fr<T>::THREADS) k_fusedr(FArgsT<T> A)
+{
+    __shared__ FRShared<T> sh;
+    rec_tap<T>(A.uc, A.rec_idx, A.rec_out, A.nrec, (long long)A.nx * A.ny);
+    // neighbouring strips of a segment row run on one XCD (their halo columns meet
+    // in that XCD's L2): the grid is a multiple of 8 and blocks past the tiles exit
+    const int blk = A.xcd_map ? xcd_band(blockIdx.x) : (int)blockIdx.x;
+    if (blk >= A.tiles) return;
+    fusedr_strip<T>(A, blk, sh);
 }
 
 }  // namespace adw

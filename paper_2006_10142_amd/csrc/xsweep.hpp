@@ -80,12 +80,23 @@ __device__ __forceinline__ float dpp(float old, float src)
                                                                 __builtin_bit_cast(int, src),
                                                                 CTRL, ROWMASK, 0xf, false));
 }
+// A 32-bit half whose `old` is a known 0 under full row and bank masks is moved
+// with the bound control set instead: lanes without a source then read 0 from the
+// hardware, and no register has to be filled with the old value first (the 0
+// identity, and the low word of 1.0, cost no instruction).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_half(int old, int src)
+{
+    if (ROWMASK == 0xf && __builtin_constant_p(old) && old == 0)
+        return __builtin_amdgcn_update_dpp(0, src, CTRL, 0xf, 0xf, true);
+    return __builtin_amdgcn_update_dpp(old, src, CTRL, ROWMASK, 0xf, false);
+}
 template <int CTRL, int ROWMASK = 0xf>
 __device__ __forceinline__ double dpp(double old, double src)
 {
     const long long o = __builtin_bit_cast(long long, old), s = __builtin_bit_cast(long long, src);
-    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, CTRL, ROWMASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), CTRL, ROWMASK, 0xf, false);
+    const int lo = dpp_half<CTRL, ROWMASK>((int)o, (int)s);
+    const int hi = dpp_half<CTRL, ROWMASK>((int)(o >> 32), (int)(s >> 32));
     return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 __device__ __forceinline__ float readlane(float v, int l)

@@ -104,18 +104,100 @@ def test_batch_one_pass_matches_oracle(adw, oracle_lib, lane):
         assert rel_l2(g, oracle_run(oracle_lib, s, 25)) <= TOL["f32"], (s["nx"], s["ny"])
 
 
-@pytest.mark.parametrize("lane", [8, 4])
+@pytest.mark.parametrize("lane", [8, 4, "strips"])
 def test_batch_one_pass_graph_and_exact_step(adw, lane):
     sims = make_batch("f32", sizes=SIZES4, seed=6)
-    say(f"batch one-pass graph / exact, {lane} nodes per lane")
-    eager, _ = run_batch(adw, sims, "f32", 11, plan=dict(fused_lane_nodes=lane))
-    graph, info = run_batch(adw, sims, "f32", 11, graph=True, plan=dict(fused_lane_nodes=lane))
-    assert info["graph"] == 1
+    say(f"batch one-pass graph / exact, {lane} (nodes per lane)")
+    plan = dict(fused_strips=True) if lane == "strips" else dict(fused_lane_nodes=lane)
+    eager, _ = run_batch(adw, sims, "f32", 11, plan=plan)
+    graph, info = run_batch(adw, sims, "f32", 11, graph=True, plan=plan)
+    assert info["graph"] == 1 and info["fused_strips"] == (lane == "strips")
     exact, info2 = run_batch(adw, sims, "f32", 11, plan=dict(fused_step=False))
     assert info2["fused_step"] == 0
     for a, b, c in zip(eager, graph, exact):
         assert np.array_equal(a, b)
         assert rel_l2(a, c) <= 3e-6
+
+
+def strip_plan(nx, ny):
+    """a batched simulation's one-pass column strips: the fewest of at most 240
+    columns, of one width (a multiple of 8), in segments of at most 1024 rows"""
+    tx = -(-nx // 240)
+    wt = min(240, (-(-nx // tx) + 7) // 8 * 8)
+    seg = -(-ny // 1024)
+    hs = -(-ny // seg)
+    return wt, hs, -(-nx // wt) * -(-ny // hs)
+
+
+def plain_strips(adw, p, u0, u1, nsteps, wt, hs):
+    """the plain solver on the given column strips"""
+    w = adw.Wave(p["nx"], p["ny"], p["h"], p["dt"], c=torch.from_numpy(p["c"]).cuda(), dtype=torch.float32)
+    w.set_tuning(fused_step=True, fused_lane_nodes=4, fused_tile_cols=wt, fused_segment_rows=max(hs, 8))
+    i = w.info()
+    assert (i["fused_step"], i["fused_tile_cols"], i["fused_segment_rows"]) == (1, wt, max(hs, 8))
+    _, c = w.step(u0.clone(), u1.clone(), nsteps)
+    torch.cuda.synchronize()
+    w.close()
+    return c.cpu().numpy()
+
+
+# row lengths a multiple of 4, one to four strips, one or two segments (1100 rows)
+SIZES_STRIPS = [(64, 64), (100, 37), (4, 9), (8, 1), (256, 256), (300, 211), (488, 96),
+                (1000, 50), (36, 517), (1024, 1100)]
+
+
+def test_batch_one_pass_strips_match_plain_and_oracle(adw, oracle_lib):
+    """The batch's column strips run each simulation exactly as the plain solver on
+    the same strips (bitwise), and match the oracle to the FP32 bars."""
+    nsteps = 21
+    sims = make_batch("f32", sizes=SIZES_STRIPS, seed=8)
+    say(f"batch one-pass strips, {len(sims)} sims, {nsteps} steps")
+    u0s, u1s = [], []
+    for p in sims:
+        w = adw.Wave(p["nx"], p["ny"], p["h"], p["dt"], c=torch.from_numpy(p["c"]).cuda(), dtype=torch.float32)
+        u0 = torch.from_numpy(p["u0"]).cuda()
+        u1s.append(w.start(u0, mode="ghost"))
+        u0s.append(u0)
+        w.close()
+    b = adw.Batch([(p["nx"], p["ny"]) for p in sims], [p["h"] for p in sims], [p["dt"] for p in sims],
+                  [torch.from_numpy(p["c"]).cuda() for p in sims], dtype=torch.float32)
+    b.set_plan(fused_strips=True)
+    b.bind([x.clone() for x in u0s], [x.clone() for x in u1s])
+    b.step(nsteps)
+    _, curr = b.levels()
+    torch.cuda.synchronize()
+    info = b.plan()
+    got = [x.cpu().numpy() for x in curr]
+    b.close()
+    assert info["fused_step"] == 1 and info["fused_strips"] == 1
+    assert info["fused_items"] == sum(strip_plan(p["nx"], p["ny"])[2] for p in sims)
+    for k, p in enumerate(sims):
+        wt, hs, _ = strip_plan(p["nx"], p["ny"])
+        ref = plain_strips(adw, p, u0s[k], u1s[k], nsteps, wt, hs)
+        assert np.array_equal(ref, got[k]), (p["nx"], p["ny"], wt, hs)
+        e2, em = rel_l2(got[k], oracle_run(oracle_lib, p, nsteps)), max_rel(got[k], oracle_run(oracle_lib, p, nsteps))
+        say(f"  {p['nx']}x{p['ny']} strips {wt} x {hs}: rel L2 {e2:.3e}, max-norm {em:.3e}")
+        assert e2 <= TOL["f32"] and em <= TOL["f32"], (p["nx"], p["ny"], e2, em)
+
+
+def test_batch_plan_strips_round_trip(adw):
+    sims = make_batch("f32", sizes=SIZES4[:3])
+    b = adw.Batch([(s["nx"], s["ny"]) for s in sims], [s["h"] for s in sims],
+                  [s["dt"] for s in sims], [torch.from_numpy(s["c"]).cuda() for s in sims], dtype=torch.float32)
+    assert b.plan()["fused_strips"] == 0
+    b.set_plan(fused_strips=True, fused_lane_nodes=8)
+    p = b.plan()
+    assert (p["fused_strips"], p["fused_lane_nodes"]) == (1, 8)
+    assert p["fused_items"] == sum(strip_plan(s["nx"], s["ny"])[2] for s in sims)
+    b.set_plan(fused_lane_nodes=4)                  # the tile kind only: strips kept
+    assert (b.plan()["fused_strips"], b.plan()["fused_lane_nodes"]) == (1, 4)
+    b.set_plan(fused_strips=False)
+    assert b.plan()["fused_strips"] == 0 and b.plan()["fused_lane_nodes"] == 4
+    p = adw._lib.AdiBatchPlan()
+    adw._lib.check(adw._lib.load().adi_batch_get_plan(b._h, adw._lib.ctypes.byref(p)))
+    p.fused_strips = 3
+    assert adw._lib.load().adi_batch_set_plan(b._h, adw._lib.ctypes.byref(p)) != 0
+    b.close()
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -185,12 +267,18 @@ def test_batch_c4_full(adw, oracle_lib):
     torch.cuda.synchronize()
     info = b.plan()
     assert info["count"] == 256 and info["graph"] == 1 and info["fused_step"] == 1
-    lane = info["fused_lane_nodes"]
-    say(f"  autotuned plan: {lane} nodes per lane, x threads {info['x_threads_per_line']}")
+    lane, strips = info["fused_lane_nodes"], info["fused_strips"]
+    say(f"  autotuned plan: {'column strips' if strips else f'tiles of {lane} nodes per lane'}, "
+        f"x threads {info['x_threads_per_line']}")
     got = [x.cpu().numpy() for x in curr]
     b.close()
-    say("batch C4 full: plain runs on the same tiles")
+    say("batch C4 full: plain runs on the same tiles or strips")
     for s, p in enumerate(probs):
+        if strips:
+            wt, hs, _ = strip_plan(p.nx, p.ny)
+            ref = plain_strips(adw, dict(nx=p.nx, ny=p.ny, h=p.h, dt=p.dt, c=p.c), u0s[s], u1s[s], nsteps, wt, hs)
+            assert np.array_equal(ref, got[s]), (s, p.nx)
+            continue
         w = adw.Wave(p.nx, p.ny, p.h, p.dt, c=torch.from_numpy(p.c).cuda(), dtype=torch.float32)
         w.set_tuning(fused_step=True, fused_lane_nodes=lane, fused_segment_rows=-2,
                      fused_tile_cols=widest(p.nx, 240 if lane == 4 else 496))
