@@ -255,13 +255,14 @@ def bench_adjoint(adw, torch):
     steps, 64 receivers; target traces from the run on the second kappa field.
 
     Algorithmic bytes per node (E = 4 B), each launch's own inputs and outputs once:
-      forward step   8E   the exact two-pass step (x-sweep 3E, y-solve and update 5E),
-                          plus 4E / K for the checkpoint copy every K steps;
-      backward step 22E   the recomputed forward step (8E, its w kept), the transposed
+      forward step   4E   the handle's step, the one-pass step here (8E where it takes the
+                          exact two-pass step), plus 4E / K for the checkpoint copy every K
+                          steps;
+      backward step 21E   the recomputed step (the exact two-pass step, 8E), the transposed
                           y-lines (reads lambda, r, writes z: 3E) and the transposed x-lines
                           with the update folded in (reads z, r, two lambda levels, three u
-                          levels, w, dJ/dkappa; writes dJ/dkappa and lambda: 11E; t stays on
-                          chip).
+                          levels, dJ/dkappa; writes dJ/dkappa and lambda: 10E; t stays on
+                          chip, and w^k = A_y d^k is formed from the u levels).
     vs_plain divides by the plain solver's rate on the same 1024^2 grid (same kappa,
     source and step count; the handle's default step)."""
     import numpy as np
@@ -316,8 +317,9 @@ def bench_adjoint(adw, torch):
     value = nodes * p.nsteps / ((fwd + bwd) / 1e3) / 1e6
     plain_value = nodes * p.nsteps / (plain_ms / 1e3) / 1e6
     E = 4
-    fb = (8 + 4.0 / K) * E * nodes
-    bb = 22 * E * nodes
+    fwd_e = 4 if wave.info()["fused_step"] else 8
+    fb = (fwd_e + 4.0 / K) * E * nodes
+    bb = 21 * E * nodes
     f_gbps = fb * p.nsteps / (fwd / 1e3) / 1e9
     b_gbps = bb * p.nsteps / (bwd / 1e3) / 1e9
     wave.close()
@@ -326,7 +328,8 @@ def bench_adjoint(adw, torch):
             "forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
             "ms_per_step_forward": round(fwd / p.nsteps, 5),
             "ms_per_step_backward": round(bwd / p.nsteps, 5), "checkpoint_every": K,
-            "algorithmic_bytes_per_node": {"forward_step": round((8 + 4.0 / K) * E, 2), "backward_step": 22 * E},
+            "forward_step": "one-pass" if fwd_e == 4 else "two-pass", "recompute_step": "two-pass",
+            "algorithmic_bytes_per_node": {"forward_step": round((fwd_e + 4.0 / K) * E, 2), "backward_step": 21 * E},
             "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS,
                          "forward": {"achieved": round(f_gbps, 1), "frac": round(f_gbps / HBM_PEAK_GBPS, 4)},
                          "backward": {"achieved": round(b_gbps, 1), "frac": round(b_gbps / HBM_PEAK_GBPS, 4)}},

@@ -139,13 +139,20 @@ adi_status adi_wave_destroy(adi_wave_t w);
  *   nu = A_y^{-T} lambda^{k+1}, mu = A_x^{-T} nu,
  *   dJ/dkappa += dt^2 mu Lap(u^k) + beta (mu Lxx w^k + nu Lyy d^k),
  *   dJ/df^k = dt^2 mu at the source nodes,
- *   lambda^k = g^k + 2 lambda^{k+1} - lambda^{k+2} + dt^2 Lap(kappa mu).
- * The initial levels are treated as independent of kappa. */
+ *   lambda^k = g^k + 2 lambda^{k+1} - lambda^{k+2} + dt^2 Lap(kappa mu),
+ * with d^k = u^{k+1} - 2u^k + u^{k-1} and w^k = A_y d^k formed from the levels.
+ * The initial levels are treated as independent of kappa.  Where the forward
+ * run takes the one-pass step, the reverse pass works on the exact step's levels
+ * recomputed from its checkpoints (the two steps differ by at most the one-pass
+ * bound, half an ulp per step), so the gradient then depends on
+ * checkpoint_every only at that level; after exact steps it does not at all. */
 
 /* Forward run of nsteps steps from (u_prev, u_curr) (not modified) with
- * sources and receivers exactly as adi_wave_step, keeping the level pair every
- * checkpoint_every steps in handle-owned device memory (allocated here on
- * first use or growth: 2 * ceil(nsteps / checkpoint_every) + 6 fields).
+ * sources and receivers exactly as adi_wave_step (the handle's step: the
+ * one-pass step where it is allowed, else the exact two-pass step; never cyclic
+ * reduction), keeping the level pair every checkpoint_every steps in
+ * handle-owned device memory (allocated here on first use or growth:
+ * 2 * ceil(nsteps / checkpoint_every) + 6 fields).
  * The handle keeps ONE forward record: this call replaces the previous one,
  * and a coefficient change (adi_wave_set_kappa, adi_wave_step_tdc) discards it.
  * record (may be NULL) receives the id of the new record (never 0). */
@@ -161,11 +168,11 @@ adi_status adi_adjoint_forward(adi_wave_t w, const void* u_prev, const void* u_c
  * grad_traces: device, nsteps x rec->count values of dJ/d(trace).
  * grad_kappa: device nx*ny, overwritten with dJ/dkappa.
  * grad_amp: device nsteps x f->count, overwritten with dJ/d(source value),
- * or NULL.  Each segment between checkpoints is recomputed once, on a second
- * stream the library creates for the handle, overlapping the reverse pass of the
- * segment after it (allocates 4 * checkpoint_every fields and a copy of the
- * y-chunk planes on first use or growth); the call returns with all its work
- * ordered on the handle's stream. */
+ * or NULL.  Each segment between checkpoints is recomputed once, with the
+ * exact two-pass step, on a second stream the library creates for the handle,
+ * overlapping the reverse pass of the segment after it (allocates
+ * 2 * checkpoint_every fields and a copy of the y-chunk planes on first use or
+ * growth); the call returns with all its work ordered on the handle's stream. */
 adi_status adi_adjoint_backward(adi_wave_t w, unsigned long long record, const adi_source* f,
                                 const adi_receivers* rec, const void* grad_traces,
                                 void* grad_kappa, void* grad_amp);

@@ -775,14 +775,17 @@ adi_status queue_cr_step(adi_wave_s* w, const void* u, const void* v, void* out,
     return ADI_OK;
 }
 
-// allow_fused = false keeps the exact two-pass step (the adjoint recomputes
-// its forward run with that path and needs the same trajectory)
+// kind: kStepDefault = the handle's step (cyclic reduction when asked for, else the
+// one-pass step when allowed, else the exact two-pass step); kStepNoCr = the same
+// without cyclic reduction; kStepExact = the exact two-pass step
+enum { kStepDefault = 0, kStepNoCr = 1, kStepExact = 2 };
+
 template <typename T>
 adi_status do_step(adi_wave_s* w, void** u_prev, void** u_curr, const adi_source* f,
-                   const adi_receivers* rec, int nsteps, bool allow_fused = true)
+                   const adi_receivers* rec, int nsteps, int kind = kStepDefault)
 {
-    const bool cr = allow_fused && w->cr;
-    const bool fused = !cr && allow_fused && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
+    const bool cr = kind == kStepDefault && w->cr;
+    const bool fused = !cr && kind != kStepExact && w->fstep && aligned16(*u_prev) && aligned16(*u_curr);
     const bool recs = rec && rec->count > 0;
     auto record = [&](int k, const void* level) -> adi_status {
         hipLaunchKernelGGL((k_record<T>), dim3((rec->count + 255) / 256), dim3(256), 0, w->stream,

@@ -14,11 +14,15 @@
 // the other order (y first, then x) on R lambda, divided by r afterwards:
 //   z = A_y^{-1} (R lambda^{k+1}),  t = A_x^{-1} z,  nu = z / r,  mu = t / r,
 // and dt^2 Lap(kappa mu) = 2 (5-point sum of t - 4 t).  d^k is recovered from
-// the stored levels as u^{k+1} - 2u^k + u^{k-1}; w^k is stored by the
-// recomputation.  Levels are checkpointed every K steps by the forward run;
-// each segment is recomputed once, in reverse segment order, on a second stream
-// into one of two halves of the segment storage, so that the recomputation of
-// segment c - 1 runs while the reverse pass of segment c does (events order them).
+// the stored levels as u^{k+1} - 2u^k + u^{k-1}, and w^k as A_y d^k =
+// d^k - r (d^k above + d^k below - 2 d^k) (zero beyond the walls), so that only
+// levels are kept.  Levels are checkpointed every K steps by the forward run,
+// which takes the handle's step (the one-pass step where it is allowed); each
+// segment is recomputed once with the exact two-pass step (its kernels share the
+// device with the reverse pass far better than the one-pass step's, which fill
+// whole compute units), in reverse segment order, on a second stream into one of
+// two halves of the segment storage, so that the recomputation of segment c - 1
+// runs while the reverse pass of segment c does (events order them).
 
 namespace adw {
 
@@ -32,7 +36,6 @@ struct AdjArgs {
     const T* um;     // u^{k-1}
     const T* uk;     // u^k
     const T* up;     // u^{k+1}
-    const T* wk;     // w^k
     T* grad;         // dJ/dkappa, accumulated
     int nx, ny;
     T c1, c2;        // dt^2 / h^2, beta / h^2
@@ -66,15 +69,20 @@ __global__ void __launch_bounds__(256) k_adjoint_update(AdjArgs<T> A)
     auto at = [&](const T* a, int ii, int jj) -> T {
         return (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? a[(size_t)jj * nx + ii] : T(0);
     };
-    auto dlt = [&](int jj) -> T {   // d^k at (i, jj)
-        return (jj >= 0 && jj < ny) ? (at(A.up, i, jj) - T(2) * at(A.uk, i, jj)) + at(A.um, i, jj) : T(0);
+    auto dlt = [&](int ii, int jj) -> T {   // d^k at (ii, jj), 0 outside the grid
+        return (ii >= 0 && ii < nx && jj >= 0 && jj < ny)
+                   ? (at(A.up, ii, jj) - T(2) * at(A.uk, ii, jj)) + at(A.um, ii, jj) : T(0);
+    };
+    auto sydat = [&](int ii) -> T { return (dlt(ii, j - 1) + dlt(ii, j + 1)) - T(2) * dlt(ii, j); };
+    auto wat = [&](int ii) -> T {           // w^k = A_y d^k at (ii, j), 0 outside the grid
+        return (ii >= 0 && ii < nx) ? dlt(ii, j) - at(A.r, ii, j) * sydat(ii) : T(0);
     };
     const T tc = A.t[p];
     const T s5t = ((at(A.t, i - 1, j) + at(A.t, i + 1, j)) + (at(A.t, i, j - 1) + at(A.t, i, j + 1))) - T(4) * tc;
     const T uc = A.uk[p];
     const T s5u = ((at(A.uk, i - 1, j) + at(A.uk, i + 1, j)) + (at(A.uk, i, j - 1) + at(A.uk, i, j + 1))) - T(4) * uc;
-    const T sxw = (at(A.wk, i - 1, j) + at(A.wk, i + 1, j)) - T(2) * A.wk[p];
-    const T syd = (dlt(j - 1) + dlt(j + 1)) - T(2) * dlt(j);
+    const T sxw = (wat(i - 1) + wat(i + 1)) - T(2) * wat(i);
+    const T syd = sydat(i);
     const T rp = A.r[p];
     const T mu = tc / rp;
     const T nu = A.z[p] / rp;
@@ -128,18 +136,33 @@ __global__ void __launch_bounds__(256) k_adjoint_update_v(AdjArgs<T> A)
         }
     };
     T tc[N], tn[N], ts[N], uc[N], un[N], us[N], pc[N], pn[N], ps[N], mc[N], mn[N], ms[N];
-    T wc[N], zc[N], rc[N], l1[N], l2[N], gc[N];
+    T zc[N], rc[N], l1[N], l2[N], gc[N];
     ld(A.t, p, in, tc); ld(A.t, p - snx, hn, tn); ld(A.t, p + snx, hs, ts);
     ld(A.uk, p, in, uc); ld(A.uk, p - snx, hn, un); ld(A.uk, p + snx, hs, us);
     ld(A.up, p, in, pc); ld(A.up, p - snx, hn, pn); ld(A.up, p + snx, hs, ps);
     ld(A.um, p, in, mc); ld(A.um, p - snx, hn, mn); ld(A.um, p + snx, hs, ms);
-    ld(A.wk, p, in, wc); ld(A.z, p, in, zc); ld(A.r, p, in, rc);
+    ld(A.z, p, in, zc); ld(A.r, p, in, rc);
     ld(A.lam1, p, in, l1); ld(A.lam2, p, in, l2); ld(A.grad, p, in, gc);
-    // values beyond the wavefront's first and last lanes
+    // d^k of the rows above, at and below, its y second difference, and w^k = A_y d^k
+    T syd[N], wc[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const T dn = hn ? (pn[e] - T(2) * un[e]) + mn[e] : T(0);
+        const T dc = (pc[e] - T(2) * uc[e]) + mc[e];
+        const T ds = hs ? (ps[e] - T(2) * us[e]) + ms[e] : T(0);
+        syd[e] = (dn + ds) - T(2) * dc;
+        wc[e] = dc - rc[e] * syd[e];
+    }
+    // values beyond the wavefront's first and last lanes (w^k from the levels there)
     const bool le = lane == 0 && in && i0 > 0, re = lane == 63 && in && i0 + N < nx;
+    auto wmem = [&](size_t q) -> T {
+        auto d = [&](size_t qq) -> T { return (A.up[qq] - T(2) * A.uk[qq]) + A.um[qq]; };
+        const T dc = d(q), dn = hn ? d(q - snx) : T(0), ds = hs ? d(q + snx) : T(0);
+        return dc - A.r[q] * ((dn + ds) - T(2) * dc);
+    };
     const T tle = le ? A.t[p - 1] : T(0), tre = re ? A.t[p + N] : T(0);
     const T ule = le ? A.uk[p - 1] : T(0), ure = re ? A.uk[p + N] : T(0);
-    const T wle = le ? A.wk[p - 1] : T(0), wre = re ? A.wk[p + N] : T(0);
+    const T wle = le ? wmem(p - 1) : T(0), wre = re ? wmem(p + N) : T(0);
     const T tl = dpp<kWaveShr1>(tle, tc[N - 1]), tr = dpp<kWaveShl1>(tre, tc[0]);
     const T ul = dpp<kWaveShr1>(ule, uc[N - 1]), ur = dpp<kWaveShl1>(ure, uc[0]);
     const T wl = dpp<kWaveShr1>(wle, wc[N - 1]), wr = dpp<kWaveShl1>(wre, wc[0]);
@@ -154,13 +177,9 @@ __global__ void __launch_bounds__(256) k_adjoint_update_v(AdjArgs<T> A)
         const T s5t = ((tw + te) + (tn[e] + ts[e])) - T(4) * tc[e];
         const T s5u = ((uw + ue) + (un[e] + us[e])) - T(4) * uc[e];
         const T sxw = (ww + we) - T(2) * wc[e];
-        const T dn = hn ? (pn[e] - T(2) * un[e]) + mn[e] : T(0);
-        const T dc = (pc[e] - T(2) * uc[e]) + mc[e];
-        const T ds = hs ? (ps[e] - T(2) * us[e]) + ms[e] : T(0);
-        const T syd = (dn + ds) - T(2) * dc;
         const T mu = tc[e] / rc[e];
         const T nu = zc[e] / rc[e];
-        go[e] = gc[e] + (mu * (A.c1 * s5u + A.c2 * sxw) + nu * (A.c2 * syd));
+        go[e] = gc[e] + (mu * (A.c1 * s5u + A.c2 * sxw) + nu * (A.c2 * syd[e]));
         T lam = (T(2) * l1[e] - l2[e]) + T(2) * s5t;
         if (row_rec) {
             const int j0 = A.rmap[p + e];
@@ -180,7 +199,9 @@ __global__ void __launch_bounds__(256) k_adjoint_update_v(AdjArgs<T> A)
 // solve the rows above and below again, with the same arithmetic); once the row
 // below a row is solved, that row's update runs from registers: t of rows q - 1,
 // q, q + 1 (its x-neighbours across segment edges through LDS), z and r of row q
-// (the solve's inputs), and u^k, d^k of rows q - 1 .. q + 1 rolled down the strip.
+// (the solve's inputs), and u^k, d^k of rows q - 1 .. q + 1 rolled down the strip,
+// which give w^k = A_y d^k of row q (its x-neighbours across segment edges from
+// the neighbouring lanes, at a wavefront's ends from the levels in memory).
 template <typename T, int TR>
 struct XUShared {
     T halo[2][2][TR];            // first and last t of every segment, by row parity
@@ -225,6 +246,16 @@ __device__ __forceinline__ void xsolve_update_strip(const XArgs<T>& X, const Adj
     };
     auto one = [&](const T* base, int row, int col) -> T {   // a single value, 0 outside
         return (act && row >= 0 && row < ny && col >= 0 && col < nx) ? base[(size_t)row * nx + col] : T(0);
+    };
+    auto dat = [&](int row, int col) -> T {                   // d^k at a node, 0 outside
+        return (row >= 0 && row < ny && col >= 0 && col < nx)
+                   ? (A.up[(size_t)row * nx + col] - T(2) * A.uk[(size_t)row * nx + col]) + A.um[(size_t)row * nx + col]
+                   : T(0);
+    };
+    auto wmem = [&](int row, int col) -> T {                  // w^k = A_y d^k at a node, 0 outside
+        if (col < 0 || col >= nx) return T(0);
+        const T dc = dat(row, col);
+        return dc - A.r[(size_t)row * nx + col] * ((dat(row - 1, col) + dat(row + 1, col)) - T(2) * dc);
     };
 
     // sources in the output rows, in source order (wavefront 0 of the group, ballot-compacted)
@@ -271,15 +302,16 @@ __device__ __forceinline__ void xsolve_update_strip(const XArgs<T>& X, const Adj
         seg(A.uk, j, un);
         seg(A.up, j, pn);
         seg(A.um, j, mn);
-        T wq[E], l1[E], l2[E], gq[E];
-        T uwe = T(0), uee = T(0), wwe = T(0), wee = T(0);
+        T l1[E], l2[E], gq[E];
+        T uwe = T(0), uee = T(0), wwm = T(0), wem = T(0);
         if (upd) {
-            seg(A.wk, q, wq);
             seg(A.lam1, q, l1);
             seg(A.lam2, q, l2);
             seg(A.grad, q, gq);
             uwe = one(A.uk, q, i0 - 1); uee = one(A.uk, q, i0 + L);
-            wwe = one(A.wk, q, i0 - 1); wee = one(A.wk, q, i0 + L);
+            // w^k of row q just beyond the wavefront's first and last lanes
+            if (lane == 0) wwm = wmem(q, i0 - 1);
+            if (lane == 63) wem = wmem(q, i0 + L);
         }
         // solve row j (rows outside the grid have z = r = 0 and give t = 0)
         T rho[E], tn[E];
@@ -298,6 +330,19 @@ __device__ __forceinline__ void xsolve_update_strip(const XArgs<T>& X, const Adj
         const bool jin = j >= 0 && j < ny;
 #pragma unroll
         for (int e = 0; e < E; ++e) dn[e] = jin ? (pn[e] - T(2) * un[e]) + mn[e] : T(0);
+        // w^k = A_y d^k of row q (every lane of the wavefront, so that the lane shifts
+        // below read defined values; lanes past the line hold zeros)
+        T wq[E], syq[E];
+        T wwe = T(0), wee = T(0);
+        if (upd) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                syq[e] = (da[e] + dn[e]) - T(2) * db[e];
+                wq[e] = db[e] - rq[e] * syq[e];
+            }
+            wwe = dpp<kWaveShr1>(wwm, wq[E - 1]);
+            wee = dpp<kWaveShl1>(wem, wq[0]);
+        }
         if (upd && act) {
             // t across the segment edges of row q (written in the previous pass, before
             // this pass's barrier)
@@ -314,7 +359,7 @@ __device__ __forceinline__ void xsolve_update_strip(const XArgs<T>& X, const Adj
                 const T s5t = ((tw + te) + (tm[e] + tn[e])) - T(4) * tq[e];
                 const T s5u = ((uw + ue) + (ua[e] + un[e])) - T(4) * ub[e];
                 const T sxw = (ww + we) - T(2) * wq[e];
-                const T syd = (da[e] + dn[e]) - T(2) * db[e];
+                const T syd = syq[e];
                 T g = gq[e], lam = l2[e];
                 if (e < L) {
                     const T mu = tq[e] / rq[e];
@@ -455,9 +500,10 @@ struct adi_adjoint_s {
     unsigned long long record = 0;   // id of the stored forward run (0: none, or invalidated)
     size_t field = 0;            // bytes of one field
     void* ck = nullptr;          // 2 * ncheck fields: (u^{k0-1}, u^{k0}) of every segment
-    void* seg = nullptr;         // 2 x 2K fields, one half per segment parity: levels
-                                 // u^{k0+1..k0+K}, then w^{k0..k0+K-1}
-    void* work = nullptr;        // 6 fields: forward levels (2), lambda (2), t, z
+    void* seg = nullptr;         // 2 x K fields, one half per segment parity: levels
+                                 // u^{k0+1..k0+K}
+    void* work = nullptr;        // 6 fields: forward levels (2; during the reverse pass the
+                                 // recomputation's x-sweep output), lambda (2), t, z
     void* rmap = nullptr;        // nx*ny + receiver count + ny ints: receiver map of the reverse pass
     void* ysum = nullptr;        // y-chunk planes and interface values of the recomputation stream
     size_t ck_cap = 0, seg_cap = 0, work_cap = 0, rmap_cap = 0, ysum_cap = 0;
@@ -558,7 +604,7 @@ bool queue_xsolve_update(adi_wave_s* w, const void* z, const AdjArgs<T>& ua)
     a.rows_per_strip = w->xp.rs;
     a.xcd = a.rows_per_strip <= kXcdStripRows;
     a.vec = ((size_t)w->nx * sizeof(T)) % 16 == 0 && aligned16(z) && aligned16(w->r) && aligned16(ua.uk) &&
-            aligned16(ua.up) && aligned16(ua.um) && aligned16(ua.wk) && aligned16(ua.lam1) && aligned16(ua.lam2) &&
+            aligned16(ua.up) && aligned16(ua.um) && aligned16(ua.lam1) && aligned16(ua.lam2) &&
             aligned16(ua.grad);
     const int grid = xsweep_grid(w->ny, w->xp.rs, x_groups_per_wg(w->xp.tr));
     switch (w->xp.tr) {
@@ -615,6 +661,8 @@ adi_status adj_forward(adi_wave_s* w, const void* u_prev, const void* u_curr, co
     void* q = lev + F;
     ADI_HIP(hipMemcpyAsync(p, u_prev, F, hipMemcpyDeviceToDevice, w->stream));
     ADI_HIP(hipMemcpyAsync(q, u_curr, F, hipMemcpyDeviceToDevice, w->stream));
+    // the handle's step without cyclic reduction: the one-pass step where it is
+    // allowed, else the exact two-pass step
     for (int c = 0; c < a->ncheck; ++c) {
         char* ck = static_cast<char*>(a->ck) + 2 * (size_t)c * F;
         ADI_HIP(hipMemcpyAsync(ck, p, F, hipMemcpyDeviceToDevice, w->stream));
@@ -626,7 +674,8 @@ adi_status adj_forward(adi_wave_s* w, const void* u_prev, const void* u_curr, co
             rc = *rec;
             rc.traces = static_cast<char*>(rec->traces) + (size_t)c * K * rec->count * sizeof(T);
         }
-        if (adi_status s = do_step<T>(w, &p, &q, f ? &sc : nullptr, rec ? &rc : nullptr, n, false)) return s;
+        if (adi_status s = do_step<T>(w, &p, &q, f ? &sc : nullptr, rec ? &rc : nullptr, n, kStepNoCr))
+            return s;
     }
     return ADI_OK;
 }
@@ -639,7 +688,7 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     const size_t F = a->field;
     const int S = a->nsteps, K = a->K;
     const long long npts = (long long)w->nx * w->ny;
-    if (adi_status s = grow(&a->seg, &a->seg_cap, 4 * (size_t)K * F)) return s;
+    if (adi_status s = grow(&a->seg, &a->seg_cap, 2 * (size_t)K * F)) return s;
     if (adi_status s = adjoint_streams(a)) return s;
     // the recomputation's y-chunk workspace: the handle's planes (the static interface
     // coefficients among them) copied, so the two streams never share scratch
@@ -704,14 +753,15 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     const bool vec_upd = w->nx % NV == 0 && aligned16(grad_kappa) && aligned16(w->r) && F % 16 == 0;
     const dim3 ugv((unsigned)((((long long)(w->nx / NV + 255) / 256) * w->ny + 7) / 8 * 8));
     // segment c: levels L[0..n+1] = u^{k0-1} .. u^{k0+n} (L[0], L[1] the checkpoint,
-    // the others in half c % 2 of the segment storage) and w^{k0..k0+n-1}
+    // the others in half c % 2 of the segment storage)
     auto lev = [&](int c, int m) -> void* {
         if (m < 2) return static_cast<char*>(a->ck) + (2 * (size_t)c + m) * F;
-        return seg + (2 * (size_t)K * (c & 1) + (m - 2)) * F;
+        return seg + ((size_t)K * (c & 1) + (m - 2)) * F;
     };
-    auto wst = [&](int c, int m) -> void* { return seg + (2 * (size_t)K * (c & 1) + K + m) * F; };
-    // recompute segment c on the recomputation stream (the same kernels, in the same
-    // order, as the forward run: the levels come out bit for bit)
+    // recompute segment c on the recomputation stream with the exact two-pass step
+    // (the levels are those of the forward run bit for bit when it took that step;
+    // after one-pass steps they differ by at most that step's bound, half an ulp per
+    // step)
     auto recompute = [&](int c) -> adi_status {
         const int k0 = 1 + c * K;
         const int n = std::min(K, S - c * K);
@@ -720,10 +770,10 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
         w->stream = a->rs;
         w->sum = sum2;
         w->X = X2;
+        w->w = work;                             // the x-sweep's output (not kept)
         adi_status s = ADI_OK;
         for (int m = 0; m < n && s == ADI_OK; ++m) {
             adi_source sc = src_at(f, k0 - 1 + m, sizeof(T));
-            w->w = wst(c, m);                    // keep w^k of this step
             s = queue_solve<T>(w, lev(c, m + 1), lev(c, m), lev(c, m + 2), T(2), T(-1), f ? &sc : nullptr, 0,
                                T(1), nullptr);
         }
@@ -757,7 +807,6 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
             ua.um = static_cast<const T*>(lev(c, m));
             ua.uk = static_cast<const T*>(lev(c, m + 1));
             ua.up = static_cast<const T*>(lev(c, m + 2));
-            ua.wk = static_cast<const T*>(wst(c, m));
             ua.rvals = (k >= 2 && nrec > 0) ? gt + (size_t)(k - 2) * nrec : nullptr;
             ua.gout = nsrc > 0 ? static_cast<T*>(grad_amp) + (size_t)(k - 1) * nsrc : nullptr;
             if (queue_xsolve_update<T>(w, zz, ua)) {

@@ -65,9 +65,14 @@ def case(dtype, nx=90, ny=70, nsteps=50, seed=1, nonzero=False):
                 rec_idx=rec_idx, target=target, nsteps=nsteps, dtype=dtype)
 
 
-def gpu_grad(adw, c, K, want_amp=True, kappa=None):
+def gpu_grad(adw, c, K, want_amp=True, kappa=None, one_pass=None):
+    """one_pass: True / False forces the forward run's step (one-pass / exact
+    two-pass), None keeps the handle's choice."""
     wave = adw.Wave(c["nx"], c["ny"], c["h"], c["dt"], dtype=tdt(c["dtype"]),
                     kappa=dev(c["kappa"] if kappa is None else kappa))
+    if one_pass is not None:
+        wave.set_tuning(fused_step=one_pass)
+        assert wave.info()["fused_step"] == int(one_pass)
     si, ri = dev(c["src_idx"]), dev(c["rec_idx"])
     amp = dev(c["amp"])
     tr = wave.adjoint_forward(dev(c["up"]), dev(c["uc"]), c["nsteps"], src_idx=si, src_amp=amp,
@@ -124,6 +129,35 @@ def test_adjoint_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
     c = case(dtype, nonzero=nonzero)
     say(f"adjoint {dtype} K={K} nonzero={nonzero}")
     check_grads(c, gpu_grad(adw, c, K), oracle_grad(oracle_lib, c), f"K={K} nonzero={nonzero}")
+
+
+@pytest.mark.parametrize("dtype,K,nonzero", [("f64", 7, True), ("f64", 50, False), ("f32", 16, False),
+                                             ("f32", 50, True)])
+def test_adjoint_one_pass_forward_matches_oracle(adw, oracle_lib, dtype, K, nonzero):
+    """The forward run and the recomputation on the one-pass step (96 x 70, so every
+    row length allows it), against the oracle's exact adjoint: the one-pass step
+    differs from the exact one by at most half an ulp per step, so the same bars hold."""
+    c = case(dtype, nx=96, nonzero=nonzero)
+    say(f"adjoint on the one-pass step {dtype} K={K} nonzero={nonzero}")
+    check_grads(c, gpu_grad(adw, c, K, one_pass=True), oracle_grad(oracle_lib, c), f"one-pass K={K}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_one_pass_checkpoint_interval(adw, dtype):
+    """After a one-pass forward run the reverse pass works on the exact step's
+    levels recomputed from the checkpoints, which differ from the forward run's by at
+    most the one-pass bound (half an ulp per step): the gradient then depends on the
+    checkpoint interval only at that level (FP64 1e-13, FP32 2e-6 relative L2); the
+    traces do not depend on it at all."""
+    c = case(dtype, nx=96, ny=48, nsteps=37, seed=4)
+    say(f"one-pass checkpoint interval {dtype}")
+    g = [gpu_grad(adw, c, K, one_pass=True) for K in (1, 5, 37, 100)]
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    for x in g[1:]:
+        assert np.array_equal(g[0][2], x[2])
+        e = (rel_l2(x[0], g[0][0]), rel_l2(x[1], g[0][1]))
+        say(f"  dJ/dkappa {e[0]:.3e}, dJ/dsource {e[1]:.3e} against K = 1")
+        assert e[0] <= tol and e[1] <= tol, e
 
 
 @pytest.mark.parametrize("nx,ny", [(30, 50), (7, 90), (130, 9), (2100, 12), (2101, 12)])
