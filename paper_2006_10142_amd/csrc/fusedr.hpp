@@ -5,33 +5,37 @@
 //
 // A workgroup owns a strip of Wt output columns (a multiple of 8, at most S; the
 // plan mixes two widths 8 apart so that the strips cover the grid evenly) and hs
-// output rows, and walks down it in bands of B = 24 x-rows; band k holds the
-// x-rows [r0 - KY + 24k, r0 - KY + 24 + 24k).  (FP32: NPL = 4 nodes per lane,
-// KX = KY = 8 halo columns and rows, S = 240; FP64: NPL = 2, KX = KY = 16, S = 96.)
-//   x-role (XW wavefronts, 12 / 8): XR = 24 / XW x-rows each per band, NPL nodes per lane, on the
+// output rows, and walks down it in bands of B x-rows; band k holds the x-rows
+// [r0 - KY + Bk, r0 - KY + B + Bk).  (FP32: B = 24, NPL = 4 nodes per lane,
+// KX = KY = 8 halo columns and rows, S = 240; FP64: B = 20, NPL = 2, KX = KY = 16,
+// S = 96.)
+//   x-role (XW wavefronts, 12 / 10): XR = B / XW = 2 x-rows each per band, NPL nodes per lane, on the
 //     window [c0 - KX, c0 + Wt + KX) as fused4.hpp, except for the entry pivots
 //     (below); w, r and u^n of the central columns go to rings of 2B + KY rows in
 //     LDS.  The inputs of band k + 1 are in registers, and those of band k + 2 are
 //     requested as soon as band k is solved.
-//   Entry pivots: each lane rebuilds the elimination pivot entering its nodes by
-//     running the pivot map q -> r / (1 + r (2 - q)) from q = 0 over the PB nodes
-//     before them (6 for FP32, 8 for FP64), instead of reading the full-line value.
-//     The map contracts by its derivative q^2 <= qs^2, so the start value is
-//     forgotten to qs^(2 PB + 1): below 1e-11 for FP32 (qs < 0.14, r <= 0.18) and
-//     below 2^-54 for FP64 (qs < 0.107): the pivot is the full-line one up to
-//     rounding.  The window's first lanes have fewer nodes before them inside the
-//     window and start from zero at its edge: that is the window's own system, the
-//     same truncation as the y-lines', covered by the bound of fused.hpp (the cut is
-//     KX + 1 columns from the first output column).
+//   Entry pivots (FP32): each lane rebuilds the elimination pivot entering its
+//     nodes by running the pivot map q -> r / (1 + r (2 - q)) from q = 0 over the
+//     PB = 6 nodes before them, instead of reading the full-line value.  The map
+//     contracts by its derivative q^2 <= qs^2, so the start value is forgotten to
+//     qs^(2 PB + 1), below 1e-11 (qs < 0.14, r <= 0.18): the pivot is the full-line
+//     one up to rounding.  The window's first lanes have fewer nodes before them
+//     inside the window and start from zero at its edge: that is the window's own
+//     system, the same truncation as the y-lines', covered by the bound of fused.hpp
+//     (the cut is KX + 1 columns from the first output column).  FP64 would need
+//     about nine nodes, four 2-node lanes back, to forget the start to its rounding:
+//     its lanes read their full-line entry pivots from a plane of one value per
+//     2-node lane (the full-line elimination with the carry entering the window set
+//     to zero, the tiles' truncation, under the same bound).
 //   y-role (YW wavefronts, one thread per column): in the same pass, band k - 1.
 //     The forward elimination of each y-line continues down the strip from row
 //     r0 - KY (zero carries: the upper cut, KY + 1 rows above the first output row),
-//     over the band's 24 rows (g and the pivots replace w and r in the ring).  The
+//     over the band's B rows (g and the pivots replace w and r in the ring).  The
 //     back substitution starts at the band's last row with a zero value (the lower
 //     cut, KY + 1 rows below the band's last output row), runs up through the band
 //     and through the KY look-ahead rows kept in the ring by the band before, and
-//     updates the output rows [r0 - 2 KY + 24k, r0 - 2 KY + 24 + 24k) (band 0:
-//     [r0, r0 + 24 - KY)) as it goes: u^{n+1} = 2 u^n - u^{n-1} + d, with u^n from
+//     updates the output rows [r0 - 2 KY + Bk, r0 - 2 KY + B + Bk) (band 0:
+//     [r0, r0 + B - KY)) as it goes: u^{n+1} = 2 u^n - u^{n-1} + d, with u^n from
 //     its ring (the x-role had it in registers) and u^{n-1} requested a pass ahead.
 //     The band's last KY rows (g, pivots and u^n) stay in the rings.
 // Each output row is the solution of a y-window whose cuts are at least KY + 1 rows
@@ -47,6 +51,7 @@ namespace adw {
 
 template <typename T> struct FrCfg;
 template <> struct FrCfg<float> {
+    static constexpr int B = 24;           // x-rows per band
     static constexpr int NPL = kF4Seg;     // nodes per lane (one 16-byte vector)
     static constexpr int KX = kFuKx;       // x-halo columns on each side
     static constexpr int KY = kFuKy;       // y-halo rows (look-ahead rows of a band)
@@ -56,29 +61,30 @@ template <> struct FrCfg<float> {
     static constexpr int KG = 8;           // y-role rows per group of LDS reads
 };
 template <> struct FrCfg<double> {
+    static constexpr int B = 20;           // 10 x-role wavefronts of two x-rows (24 rows on 8 of
+                                           // three: 5% slower, two fewer wavefronts per CU)
     static constexpr int NPL = 2;
     static constexpr int KX = 16;
     static constexpr int KY = 16;
     static constexpr int YW = 2;
-    static constexpr int XW = 8;           // 640 threads: up to 168 registers a thread
-    static constexpr int PB = 8;
+    static constexpr int XW = 10;          // 768 threads: up to 168 registers a thread
+    static constexpr int PB = 8;           // not used: the lanes read their entry pivots
     static constexpr int KG = 4;
 };
 
-constexpr int kFrB = 24;                   // x-rows per band
 constexpr int kFrHmin = 256;               // shortest strip segment the plan picks by itself
 
 template <typename T>
 struct Fr {
     using C = FrCfg<T>;
-    static constexpr int XR = kFrB / C::XW;                    // x-rows per x-role wavefront per band (2 / 3)
-    static_assert(kFrB % C::XW == 0, "every x-role wavefront takes the same number of x-rows");
-    static constexpr int R = 2 * kFrB + C::KY;                 // ring rows (56 / 64)
+    static constexpr int XR = C::B / C::XW;                    // x-rows per x-role wavefront per band (2)
+    static_assert(C::B % C::XW == 0, "every x-role wavefront takes the same number of x-rows");
+    static constexpr int R = 2 * C::B + C::KY;                 // ring rows (56 / 56)
     static constexpr int S = 64 * C::NPL - 2 * C::KX;          // ring row stride, widest strip (240 / 96)
-    static constexpr int THREADS = 64 * (C::YW + C::XW);       // workgroup size (1024 / 640)
+    static constexpr int THREADS = 64 * (C::YW + C::XW);       // workgroup size (1024 / 768)
     static constexpr int LB = (C::PB + C::NPL - 1) / C::NPL;   // lanes the pivot rebuild reaches back
     static constexpr int FIRST = LB * C::NPL - C::PB;          // nodes of the furthest of them skipped
-    static_assert(kFrB % C::KG == 0 && C::KY % C::KG == 0, "the y-role reads whole groups of rows");
+    static_assert(C::B % C::KG == 0 && C::KY % C::KG == 0, "the y-role reads whole groups of rows");
     static_assert(C::KX % C::NPL == 0, "the x-halo is whole lanes");
 };
 constexpr int kFrThreads = Fr<float>::THREADS;
@@ -180,7 +186,7 @@ template <typename T>
 __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShared<T>& sh)
 {
     using C = FrCfg<T>;
-    constexpr int NPL = C::NPL, KX = C::KX, KY = C::KY, KG = C::KG;
+    constexpr int NPL = C::NPL, KX = C::KX, KY = C::KY, KG = C::KG, kFrB = C::B;
     constexpr int R = Fr<T>::R, S = Fr<T>::S, XR = Fr<T>::XR;
     constexpr int ES = (int)sizeof(T);
     const int t = threadIdx.x;
@@ -192,8 +198,8 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
     const int c0 = sx * A.wt - (sx > A.wide ? (sx - A.wide) * 8 : 0);
     const int r0 = (blk / A.tiles_x) * A.hs;
     const int r1 = min(r0 + A.hs, ny);
-    // bands: band b outputs rows [r0 - 2 KY + 24 b, r0 - 2 KY + 24 + 24 b), so
-    // 24 nb >= hs + 2 KY
+    // bands: band b outputs rows [r0 - 2 KY + B b, r0 - 2 KY + B + B b), so
+    // B nb >= hs + 2 KY
     const int nb = (r1 - r0 + 2 * KY + kFrB - 1) / kFrB;
     const int nl = (wt + 2 * KX) / NPL;                   // lanes of the x-window
     const long long npts = (long long)nx * ny;
