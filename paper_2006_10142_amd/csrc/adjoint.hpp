@@ -429,6 +429,54 @@ __global__ void __launch_bounds__(TR >= 256 ? TR : 256) k_xsolve_update(XArgs<T>
     else xsolve_update_strip<T, TR, false>(X, A, blk * G + g, threadIdx.x - g * TR, sh[g]);
 }
 
+// The transposed y-lines of one reverse step, z = A_y^{-1} (r lambda), on windows
+// (the truncation of the one-pass step, fused.hpp): one thread per (column,
+// segment of H rows), the threads of a wavefront on 64 neighbouring columns.  The
+// window [j0 - KY, j0 + H + KY) is eliminated downwards from zero carries and
+// back-substituted upwards from zero, in registers, and its H central rows are
+// written.  Each written row is KY + 1 rows or more from a cut (rows beyond the
+// grid have r = 0 and decouple, so the walls need none), so the result differs
+// from the full-line solve by at most 2 qs^(KY+1) max|z|, below half an ulp where
+// the one-pass bound holds.
+template <typename T, int KY, int H>
+__global__ void __launch_bounds__(256) k_ysolve_win(const T* __restrict__ lam, const T* __restrict__ r,
+                                                   T* __restrict__ z, int nx, int ny)
+{
+    constexpr int W = H + 2 * KY;
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j0 = (int)(blockIdx.y * 4 + (threadIdx.x >> 6)) * H;
+    if (j0 >= ny) return;                                     // no barrier below
+    const bool col = i < nx;
+    // the whole window is requested before the elimination starts (one memory round
+    // trip; the elimination is a chain through the rows)
+    T g[W], q[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int j = j0 - KY + k;
+        const bool in = col && j >= 0 && j < ny;
+        const size_t p = (size_t)(in ? j : 0) * nx + (col ? i : 0);
+        q[k] = in ? r[p] : T(0);
+        g[k] = in ? lam[p] : T(0);
+    }
+    T qc = T(0), gc = T(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const T rr = q[k];
+        const T m = pivot_step<T>(rr, qc);
+        gc = fma_rn(m, rr * g[k], qc * gc);
+        g[k] = gc;
+        q[k] = qc;
+    }
+    T d = T(0);
+#pragma unroll
+    for (int k = W - 1; k >= KY; --k) {
+        d = fma_rn(q[k], d, g[k]);
+        const int j = j0 - KY + k;
+        if (k < KY + H && col && j < ny) z[(size_t)j * nx + i] = d;
+    }
+}
+constexpr int kYWinRows = 32;   // output rows per thread of k_ysolve_win
+
 // receiver map of the reverse pass: rmap[node] = smallest receiver index at the
 // node (rmap filled beforehand with a value above every index, so that a node
 // without receivers keeps it), rnext[k] = next receiver at the same node or -1,
@@ -747,6 +795,10 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
     ua.c1 = (T)(w->dt * w->dt / (w->h * w->h));
     ua.c2 = (T)(beta / (w->h * w->h));
     const dim3 ug((w->nx + 63) / 64, (w->ny + 3) / 4);
+    // the transposed y-lines: on windows (one launch) when the handle takes the FP32
+    // one-pass step (whose bound covers their truncation), else the exact chunk solve
+    const bool ywin = sizeof(T) == 4 && w->fstep;
+    const dim3 ywg((w->nx + 63) / 64, ((w->ny + kYWinRows - 1) / kYWinRows + 3) / 4);
     // 16-byte vectors: whole vectors per row, and every field of the update 16-byte aligned
     // (the handle's and this adjoint's buffers are; the gradient is the caller's)
     constexpr int NV = 16 / (int)sizeof(T);
@@ -802,7 +854,17 @@ adi_status adj_backward(adi_wave_s* w, const adi_source* f, const adi_receivers*
         const int n = std::min(K, S - c * K);
         for (int m = n - 1; m >= 0; --m) {
             const int k = k0 + m;
-            if (adi_status s = queue_ysolve_scaled<T>(w, lam1, zz)) return s;
+            bool ydone = false;
+            if constexpr (sizeof(T) == 4) {
+                if (ywin) {
+                    hipLaunchKernelGGL((k_ysolve_win<T, kFuKy, kYWinRows>), ywg, dim3(256), 0, w->stream, lam1,
+                                       static_cast<const T*>(w->r), zz, w->nx, w->ny);
+                    ADI_LAUNCHED("y_solve windows (adjoint)");
+                    ydone = true;
+                }
+            }
+            if (!ydone)
+                if (adi_status s = queue_ysolve_scaled<T>(w, lam1, zz)) return s;
             ua.t = tt; ua.z = zz; ua.lam1 = lam1; ua.lam2 = lam2;
             ua.um = static_cast<const T*>(lev(c, m));
             ua.uk = static_cast<const T*>(lev(c, m + 1));

@@ -174,17 +174,18 @@ def test_adjoint_narrow_grids(adw, oracle_lib, nx, ny):
     check_grads(c, got, ref, f"narrow {nx}x{ny}")
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_adjoint_long_columns(adw, oracle_lib, dtype):
+@pytest.mark.parametrize("dtype,one_pass", [("f64", None), ("f32", None), ("f32", True)])
+def test_adjoint_long_columns(adw, oracle_lib, dtype, one_pass):
     """Columns of 1100 rows (69 chunks of 16, so the interface systems of the forward
-    run, the recomputation and the transposed y-lines take 64 threads per column),
-    sources and receivers 10 rows apart in the middle of the grid."""
+    run, the recomputation and the transposed y-lines take 64 threads per column; on the
+    FP32 one-pass step the transposed y-lines run on windows: 35 segments of 32 rows, the
+    last one ragged), sources and receivers 10 rows apart in the middle of the grid."""
     c = case(dtype, nx=24, ny=1100, nsteps=24, seed=17)
     nx = c["nx"]
     c["src_idx"] = np.array([550 * nx + 12, 552 * nx + 5], np.int32)
     c["rec_idx"] = np.array([560 * nx + 2 * k + 3 for k in range(8)], np.int32)
-    say(f"adjoint long columns {dtype}")
-    got = gpu_grad(adw, c, 5)
+    say(f"adjoint long columns {dtype} one-pass {one_pass}")
+    got = gpu_grad(adw, c, 5, one_pass=one_pass)
     ref = oracle_grad(oracle_lib, c)
     assert np.abs(ref[1]).max() > 0
     check_grads(c, got, ref, "long columns")
