@@ -350,9 +350,11 @@ typedef struct {
     int y_chunks;             /* number of chunks per y-line */
     int kernels_per_step;     /* launches queued per ADI step */
     size_t workspace_bytes;   /* device bytes owned by the handle */
-    int fused_step;           /* 1: adi_wave_step runs the one-pass step (FP32) */
-    int fused_allowed;        /* 1: the one-pass step's truncation bound holds (FP32) */
-    double r_max;             /* largest r = dt^2 kappa / (2 h^2) (FP32 handles) */
+    int fused_step;           /* 1: adi_wave_step runs the one-pass step */
+    int fused_allowed;        /* 1: the one-pass step's truncation bound holds (FP32:
+                                 r_max <= 0.18 and nx % 4 == 0; FP64: r_max <= 0.13 and nx
+                                 even) */
+    double r_max;             /* largest r = dt^2 kappa / (2 h^2) */
     int line_solver;          /* 1: partition / scan solvers, 2: cyclic-reduction baseline */
     int fused_tile_cols;      /* one-pass step: output columns per tile (64 rows each) or per
                                  column strip; chosen for the device's compute units unless

@@ -294,8 +294,8 @@ class Wave:
                    y_chunk_rows=0, fused_step=None, cyclic_reduction=None, fused_tile_cols=0,
                    fused_lane_nodes=0, fused_segment_rows=0):
         """Override the launch plan (0 / None keeps the current value).  fused_step:
-        True = one-pass step (FP32, when its truncation bound holds), False = exact
-        two-pass step.  cyclic_reduction: True = the paper's cyclic-reduction line
+        True = one-pass step (when its truncation bound holds: FP32 r <= 0.18 and nx % 4
+        == 0, FP64 r <= 0.13 and nx even), False = exact two-pass step.  cyclic_reduction: True = the paper's cyclic-reduction line
         solver (one launch per level, for comparison), False = the default solvers.
         fused_tile_cols: one-pass tile width (multiple of 8, <= 496; -1 = automatic).
         fused_lane_nodes: one-pass x-line nodes per lane, 8 or 4 (4: tiles of at most
