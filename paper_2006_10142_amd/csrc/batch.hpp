@@ -266,10 +266,9 @@ void batch_free(adi_batch_s* b)
 
 bool batch_fits(int tr, adi_dtype dt) { return fuse_fits(tr, dt); }
 
-
 // One-pass column strips of one simulation of a batch: the fewest strips of at
 // most 240 columns, all of one width (a multiple of 8; the last strip is cut by
-// the grid's edge), and segments of at most kBatchStripRows rows of even length.
+// the grid's edge), and segments of equal length, at most kBatchStripRows rows.
 // The many simulations fill the device, so no segment count per compute unit is
 // sought (the plain plan's rule).
 void batch_strip_plan(int nx, int ny, int& wt, int& tx, int& hs, int& tiles)
