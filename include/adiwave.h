@@ -389,7 +389,8 @@ typedef struct {
                                  of a sweep (the paper's Sec. 3.1 solver, as a same-GPU
                                  baseline; allocates 3 nx*ny values), 0 = keep */
     int fused_tile_cols;      /* one-pass tile width: a multiple of 8, at most 496 (240 with 4
-                                 nodes per lane); -1 = back to the automatic choice, 0 = keep */
+                                 nodes per lane; FP64 column strips: at most 64); -1 = back
+                                 to the automatic choice, 0 = keep */
     int fused_lane_nodes;     /* one-pass x-line nodes per lane: 8 or 4; -1 = back to the
                                  automatic choice (4 where the tiles come out narrow), 0 = keep */
     int fused_segment_rows;   /* one-pass step on column strips (at most 240 columns, four

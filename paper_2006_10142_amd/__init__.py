@@ -297,7 +297,8 @@ class Wave:
         True = one-pass step (when its truncation bound holds: FP32 r <= 0.18 and nx % 4
         == 0, FP64 r <= 0.13 and nx even), False = exact two-pass step.  cyclic_reduction: True = the paper's cyclic-reduction line
         solver (one launch per level, for comparison), False = the default solvers.
-        fused_tile_cols: one-pass tile width (multiple of 8, <= 496; -1 = automatic).
+        fused_tile_cols: one-pass tile width (multiple of 8, <= 496; FP64 strips <= 64;
+        -1 = automatic).
         fused_lane_nodes: one-pass x-line nodes per lane, 8 or 4 (4: tiles of at most
         240 columns that keep r in LDS for the y-lines).  fused_segment_rows: one-pass
         step on column strips (<= 240 columns), each workgroup marching down this many output rows (>= 8);

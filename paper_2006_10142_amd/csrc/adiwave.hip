@@ -1016,7 +1016,7 @@ adi_status adi_wave_set_tuning(adi_wave_t w, const adi_tuning* t)
         if (t->fused_lane_nodes > 0 || t->fused_segment_rows == -2)
             return fail(ADI_EINVAL, "the FP64 one-pass step runs on column strips (no tiles, no lane setting)");
         if (t->fused_tile_cols > 0 && (t->fused_tile_cols % 8 != 0 || t->fused_tile_cols > kFrS64))
-            return fail(ADI_EINVAL, "FP64 column strips: fused_tile_cols must be a multiple of 8 and at most 96");
+            return fail(ADI_EINVAL, "FP64 column strips: fused_tile_cols must be a multiple of 8 and at most 64");
     }
     if (t->fused_lane_nodes != 0 && t->fused_lane_nodes != -1 && t->fused_lane_nodes != 4 &&
         t->fused_lane_nodes != 8)

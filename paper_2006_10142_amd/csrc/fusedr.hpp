@@ -7,9 +7,9 @@
 // plan mixes two widths 8 apart so that the strips cover the grid evenly) and hs
 // output rows, and walks down it in bands of B x-rows; band k holds the x-rows
 // [r0 - KY + Bk, r0 - KY + B + Bk).  (FP32: B = 24, NPL = 4 nodes per lane,
-// KX = KY = 8 halo columns and rows, S = 240; FP64: B = 20, NPL = 2, KX = KY = 16,
-// S = 96.)
-//   x-role (XW wavefronts, 12 / 10): XR = B / XW = 2 x-rows each per band, NPL nodes per lane, on the
+// KX = KY = 8 halo columns and rows, S = 240; FP64: B = 22, NPL = 2, KX = KY = 16,
+// S = 64.)
+//   x-role (XW wavefronts, 12 / 11): XR = B / XW = 2 x-rows each per band, NPL nodes per lane, on the
 //     window [c0 - KX, c0 + Wt + KX) as fused4.hpp, except for the entry pivots
 //     (below); w, r and u^n of the central columns go to rings of 2B + KY rows in
 //     LDS.  The inputs of band k + 1 are in registers, and those of band k + 2 are
@@ -61,15 +61,14 @@ template <> struct FrCfg<float> {
     static constexpr int KG = 8;           // y-role rows per group of LDS reads
 };
 template <> struct FrCfg<double> {
-    static constexpr int B = 20;           // 10 x-role wavefronts of two x-rows (24 rows on 8 of
-                                           // three: 5% slower, two fewer wavefronts per CU)
+    static constexpr int B = 22;           // 11 x-role wavefronts of two x-rows
     static constexpr int NPL = 2;
     static constexpr int KX = 16;
     static constexpr int KY = 16;
-    static constexpr int YW = 2;
-    static constexpr int XW = 10;          // 768 threads: up to 168 registers a thread
+    static constexpr int YW = 1;           // one y-role wavefront: strips of at most 64 columns
+    static constexpr int XW = 11;          // 768 threads: up to 168 registers a thread
     static constexpr int PB = 8;           // not used: the lanes read their entry pivots
-    static constexpr int KG = 4;
+    static constexpr int KG = 2;
 };
 
 constexpr int kFrHmin = 256;               // shortest strip segment the plan picks by itself
@@ -79,8 +78,10 @@ struct Fr {
     using C = FrCfg<T>;
     static constexpr int XR = C::B / C::XW;                    // x-rows per x-role wavefront per band (2)
     static_assert(C::B % C::XW == 0, "every x-role wavefront takes the same number of x-rows");
-    static constexpr int R = 2 * C::B + C::KY;                 // ring rows (56 / 56)
-    static constexpr int S = 64 * C::NPL - 2 * C::KX;          // ring row stride, widest strip (240 / 96)
+    static constexpr int R = 2 * C::B + C::KY;                 // ring rows (56 / 60)
+    // ring row stride, widest strip: the x-window's central columns, at most one per
+    // y-role thread (240 / 64)
+    static constexpr int S = 64 * C::NPL - 2 * C::KX < 64 * C::YW ? 64 * C::NPL - 2 * C::KX : 64 * C::YW;
     static constexpr int THREADS = 64 * (C::YW + C::XW);       // workgroup size (1024 / 768)
     static constexpr int LB = (C::PB + C::NPL - 1) / C::NPL;   // lanes the pivot rebuild reaches back
     static constexpr int FIRST = LB * C::NPL - C::PB;          // nodes of the furthest of them skipped
@@ -89,7 +90,7 @@ struct Fr {
 };
 constexpr int kFrThreads = Fr<float>::THREADS;
 constexpr int kFrS = Fr<float>::S;          // widest FP32 strip (240)
-constexpr int kFrS64 = Fr<double>::S;       // widest FP64 strip (96)
+constexpr int kFrS64 = Fr<double>::S;       // widest FP64 strip (64)
 constexpr int kFrThreads64 = Fr<double>::THREADS;
 
 template <typename T>

@@ -216,7 +216,7 @@ F64_STRIP_LAYOUTS = {"auto": -1, "strips_h8": 8, "strips_h30": 30, "strips_h1000
                                    (4, 200), (1504, 33), (64, 1), (40, 3), (194, 90)])
 @pytest.mark.parametrize("layout", sorted(F64_STRIP_LAYOUTS))
 def test_one_pass_f64_matches_oracle(adw, oracle_lib, nx, ny, layout):
-    """The FP64 one-pass step (column strips of at most 96 columns, 16 halo columns and
+    """The FP64 one-pass step (column strips of at most 64 columns, 16 halo columns and
     rows, truncation bound 4 qs^17 below 2^-53) against the FP64 oracle after 30 steps
     with two point sources and six receivers: relative L2 <= 1e-12 and max-norm
     <= 1e-11 (level and traces); the plan's automatic strips and 8-, 30- and 1000-row
@@ -225,7 +225,7 @@ def test_one_pass_f64_matches_oracle(adw, oracle_lib, nx, ny, layout):
     k["lane"], k["tile_cols"], k["hs"] = 0, -1, F64_STRIP_LAYOUTS[layout]
     say(f"one-pass f64 {nx}x{ny} {layout}")
     got, tr, info = gpu(adw, k, True)
-    assert info["fused_step"] == 1 and info["fused_segment_rows"] > 0 and info["fused_tile_cols"] <= 96
+    assert info["fused_step"] == 1 and info["fused_segment_rows"] > 0 and info["fused_tile_cols"] <= 64
     if layout != "auto":
         assert info["fused_segment_rows"] == k["hs"]
     ref, rtr = oracle(oracle_lib, k)
@@ -234,11 +234,11 @@ def test_one_pass_f64_matches_oracle(adw, oracle_lib, nx, ny, layout):
 
 
 def test_one_pass_f64_forced_widths_agree(adw, oracle_lib):
-    """FP64 strips forced to 32, 64 and 96 columns (one width each) and the automatic
+    """FP64 strips forced to 16, 40 and 64 columns (one width each) and the automatic
     mix reach the oracle's level to the FP64 bars on a 1000 x 700 grid."""
     k = case(1000, 700, seed=12, f64=True, nsteps=20)
     ref, _ = oracle(oracle_lib, k)
-    for wt in (32, 64, 96, -1):
+    for wt in (16, 40, 64, -1):
         k["lane"], k["tile_cols"], k["hs"] = 0, wt, -1 if wt == -1 else 200
         say(f"one-pass f64 width {wt}")
         got, _, info = gpu(adw, k, True)
