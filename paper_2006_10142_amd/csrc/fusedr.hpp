@@ -7,12 +7,12 @@
 // plan mixes two widths 8 apart so that the strips cover the grid evenly) and hs
 // output rows, and walks down it in bands of B x-rows; band k holds the x-rows
 // [r0 - KY + Bk, r0 - KY + B + Bk).  (FP32: B = 24, NPL = 4 nodes per lane,
-// KX = KY = 8 halo columns and rows, S = 240; FP64: B = 22, NPL = 2, KX = KY = 16,
+// KX = KY = 8 halo columns and rows, S = 240; FP64: B = 24, NPL = 2, KX = KY = 16,
 // S = 64.)
-//   x-role (XW wavefronts, 12 / 11): XR = B / XW = 2 x-rows each per band, NPL nodes per lane, on the
-//     window [c0 - KX, c0 + Wt + KX) as fused4.hpp, except for the entry pivots
-//     (below); w, r and u^n of the central columns go to rings of 2B + KY rows in
-//     LDS.  The inputs of band k + 1 are in registers, and those of band k + 2 are
+//   x-role (XW = 12 wavefronts): XR = B / XW = 2 x-rows each per band, NPL nodes
+//     per lane, on the window [c0 - KX, c0 + Wt + KX) as fused4.hpp, except for the
+//     entry pivots (below); w, r and u^n of the central columns go to rings in LDS.
+//     The inputs of band k + 1 are in registers, and those of band k + 2 are
 //     requested as soon as band k is solved.
 //   Entry pivots (FP32): each lane rebuilds the elimination pivot entering its
 //     nodes by running the pivot map q -> r / (1 + r (2 - q)) from q = 0 over the
@@ -27,7 +27,7 @@
 //     its lanes read their full-line entry pivots from a plane of one value per
 //     2-node lane (the full-line elimination with the carry entering the window set
 //     to zero, the tiles' truncation, under the same bound).
-//   y-role (YW wavefronts, one thread per column): in the same pass, band k - 1.
+//   y-role (one thread per column): in the same pass, band k - 1.
 //     The forward elimination of each y-line continues down the strip from row
 //     r0 - KY (zero carries: the upper cut, KY + 1 rows above the first output row),
 //     over the band's B rows (g and the pivots replace w and r in the ring).  The
@@ -38,6 +38,11 @@
 //     [r0, r0 + B - KY)) as it goes: u^{n+1} = 2 u^n - u^{n-1} + d, with u^n from
 //     its ring (the x-role had it in registers) and u^{n-1} requested a pass ahead.
 //     The band's last KY rows (g, pivots and u^n) stay in the rings.
+//     FP32: YW = 4 wavefronts side by side, each stage in turn.  FP64 (YSPLIT): a
+//     64-column strip and one wavefront per stage, so that the two dependency
+//     chains of a column (the pivot recurrence with its reciprocal, and the back
+//     substitution) run at once: in pass k the elimination wavefront takes band
+//     k - 1 and the back-substitution wavefront band k - 2.
 // Each output row is the solution of a y-window whose cuts are at least KY + 1 rows
 // away, and each x-row that of an x-window cut KX + 1 columns away, so one step
 // differs from the exact two-pass step by at most 4 qs^(K+1) max|w| (the bound of
@@ -45,7 +50,8 @@
 // arithmetic (2^-24 for FP32 with K = 8, 2^-53 for FP64 with K = 16).  A barrier
 // separates the passes: the ring's 2B + KY rows hold the band being solved (B),
 // the band being eliminated (B) and the look-ahead rows before it (KY), and these
-// never overlap.
+// never overlap; with the y-role split by stage it has 3B + KY rows, one more band
+// for the back substitution.
 
 namespace adw {
 
@@ -59,16 +65,18 @@ template <> struct FrCfg<float> {
     static constexpr int XW = 12;          // x-role wavefronts (8 with three x-rows each measured slower)
     static constexpr int PB = 6;           // nodes a lane rebuilds its entry pivot over
     static constexpr int KG = 8;           // y-role rows per group of LDS reads
+    static constexpr bool YSPLIT = false;  // the y-role's wavefronts share the strip's columns
 };
 template <> struct FrCfg<double> {
-    static constexpr int B = 22;           // 11 x-role wavefronts of two x-rows
+    static constexpr int B = 24;           // 12 x-role wavefronts of two x-rows
     static constexpr int NPL = 2;
     static constexpr int KX = 16;
     static constexpr int KY = 16;
-    static constexpr int YW = 1;           // one y-role wavefront: strips of at most 64 columns
-    static constexpr int XW = 11;          // 768 threads: up to 168 registers a thread
+    static constexpr int YW = 2;           // one elimination and one back-substitution wavefront
+    static constexpr int XW = 12;          // 896 threads: up to 128 registers a thread
     static constexpr int PB = 8;           // not used: the lanes read their entry pivots
-    static constexpr int KG = 2;
+    static constexpr int KG = 8;
+    static constexpr bool YSPLIT = true;   // the y-role split by stage, strips of at most 64 columns
 };
 
 constexpr int kFrHmin = 256;               // shortest strip segment the plan picks by itself
@@ -78,11 +86,16 @@ struct Fr {
     using C = FrCfg<T>;
     static constexpr int XR = C::B / C::XW;                    // x-rows per x-role wavefront per band (2)
     static_assert(C::B % C::XW == 0, "every x-role wavefront takes the same number of x-rows");
-    static constexpr int R = 2 * C::B + C::KY;                 // ring rows (56 / 60)
+    // ring rows: the band being solved, the band being eliminated and the look-ahead
+    // rows before it; with the y-role split by stage also the band being substituted
+    // back (56 / 88)
+    static constexpr int R = (C::YSPLIT ? 3 : 2) * C::B + C::KY;
+    static constexpr int YC = C::YSPLIT ? 1 : C::YW;           // y-role wavefronts across the strip
+    static_assert(!C::YSPLIT || C::YW == 2, "a split y-role has one wavefront per stage");
     // ring row stride, widest strip: the x-window's central columns, at most one per
     // y-role thread (240 / 64)
-    static constexpr int S = 64 * C::NPL - 2 * C::KX < 64 * C::YW ? 64 * C::NPL - 2 * C::KX : 64 * C::YW;
-    static constexpr int THREADS = 64 * (C::YW + C::XW);       // workgroup size (1024 / 768)
+    static constexpr int S = 64 * C::NPL - 2 * C::KX < 64 * YC ? 64 * C::NPL - 2 * C::KX : 64 * YC;
+    static constexpr int THREADS = 64 * (C::YW + C::XW);       // workgroup size (1024 / 896)
     static constexpr int LB = (C::PB + C::NPL - 1) / C::NPL;   // lanes the pivot rebuild reaches back
     static constexpr int FIRST = LB * C::NPL - C::PB;          // nodes of the furthest of them skipped
     static_assert(C::B % C::KG == 0 && C::KY % C::KG == 0, "the y-role reads whole groups of rows");
@@ -205,8 +218,8 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
     const int nl = (wt + 2 * KX) / NPL;                   // lanes of the x-window
     const long long npts = (long long)nx * ny;
     const int xr_lo = r0 - KY, xr_hi = xr_lo + kFrB * nb;   // x-rows of the strip
-    // ring slot of x-row xr_lo + 24 k + i (0 <= i < R): the band's first slot
-    // (24 k mod R) is carried from band to band, so no division is needed
+    // ring slot of x-row xr_lo + B k + i (0 <= i < R): the band's first slot
+    // (B k mod R) is carried from band to band, so no division is needed
     auto wrap = [](int s) { return s >= R ? s - R : s; };
     auto next_base = [&](int sb) { return wrap(sb + kFrB); };
 
@@ -413,8 +426,10 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
         }
     };
 
-    // ---- y-role constants: column c0 + t of the strip (t < wt)
-    const bool ycol = t < wt && c0 + t < nx;
+    // ---- y-role constants: column c0 + yt of the strip (yt < wt); yt is the thread
+    // within the y-role, or within its stage's wavefront when the y-role is split
+    const int yt = C::YSPLIT ? lane : t;
+    const bool ycol = yt < wt && c0 + yt < nx;
     const int lim = (int)(npts * ES);
     const rsrc_t rup = buf(static_cast<const T*>(A.up), lim);
     T gcar = T(0), qcar = T(0);                              // forward carries of the column
@@ -423,7 +438,7 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
     // the column's byte offset in a VGPR (out of range for threads past the strip)
     // and the row's in the scalar offset; rows outside the band's output rows are
     // loaded clamped into the grid (unused) and not stored (a uniform test)
-    const int vcol = ycol ? (c0 + t) * ES : kFuOOB;
+    const int vcol = ycol ? (c0 + yt) * ES : kFuOOB;
     const int rowb = nx * ES;
     auto out_row = [&](int b, int o) {
         const int j = xr_lo + kFrB * b - KY + o;
@@ -433,7 +448,7 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
         const int j = xr_lo + kFrB * b - KY + o;
         return (j < 0 ? 0 : j >= ny ? ny - 1 : j) * rowb;
     };
-    // a band whose 24 output rows all lie inside the segment (most of them) takes a
+    // a band whose B output rows all lie inside the segment (most of them) takes a
     // path with no per-row bound tests or clamps; both paths issue the same loads
     auto band_full = [&](int b) {
         const int j0 = xr_lo + kFrB * b - KY;
@@ -449,38 +464,67 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
             for (int o = 0; o < kFrB; ++o) pu[o] = fr_load1<T, kFuNT>(rup, vcol, srow(b, o));
         }
     };
-    // band b: its u^{n-1} (requested one pass earlier) is taken first, and band
-    // b+1's is requested at once, so that it has a whole pass to arrive;
-    // then the forward elimination over the band's rows (g and the pivots replace
-    // w and r in the ring), and the back substitution with the update
-    auto y_band = [&](int b, int s0) {
+    // band b from ring slot s0, in two stages: the forward elimination over the
+    // band's rows (g and the pivots replace w and r in the ring), then the back
+    // substitution from the band's last row, up through the look-ahead rows of the
+    // band before, with the update.  Its u^{n-1} (requested one pass earlier) is
+    // taken first, and band b+1's is requested at once, so that it has a whole pass
+    // to arrive.  kElim / kBack select the stages (both, or one of them for a
+    // y-role split by stage; there the back substitution's wavefront reads u^{n-1}
+    // in place and requests band b+1's when it is done, since it finishes its
+    // passes early and waits at the barrier).
+    auto y_band = [&](int b, int s0, auto elim_c, auto back_c) {
+        constexpr bool kElim = decltype(elim_c)::value, kBack = decltype(back_c)::value;
         const int xb = xr_lo + kFrB * b;
         T base[kFrB];                                        // -u^{n-1} of the output rows
+        if constexpr (kBack && !C::YSPLIT) {
 #pragma unroll
-        for (int o = 0; o < kFrB; ++o) base[o] = -pu[o];
-        load_upd(b + 1);                                     // past the last band: out of range
+            for (int o = 0; o < kFrB; ++o) base[o] = -pu[o];
+            load_upd(b + 1);                                 // past the last band: out of range
+        }
         // ring slot s (< 2 R) of this column; threads past the strip read a valid
         // column and write nothing, so every thread issues the same memory operations
-        const int ty = t < wt ? t : wt - 1;
+        const int ty = yt < wt ? yt : wt - 1;
         auto at = [&](int s) { return (s >= R ? s - R : s) * S + ty; };
+        if constexpr (kElim && C::YSPLIT) {
+            // the band's reads all first, so that the pivot recurrence then runs
+            // without waiting on LDS; a thread past the strip repeats the values of
+            // column wt - 1 (the same reads from zero carries), so its writes are
+            // duplicates and need no test
+            T rr[kFrB], ww[kFrB];
 #pragma unroll
-        for (int c = 0; c < kFrB / KG; ++c) {
-            T rr[KG], ww[KG];
-#pragma unroll
-            for (int e = 0; e < KG; ++e) {
-                rr[e] = sh.r[at(s0 + KG * c + e)];
-                ww[e] = sh.w[at(s0 + KG * c + e)];
+            for (int e = 0; e < kFrB; ++e) {
+                rr[e] = sh.r[at(s0 + e)];
+                ww[e] = sh.w[at(s0 + e)];
             }
 #pragma unroll
-            for (int e = 0; e < KG; ++e) {
+            for (int e = 0; e < kFrB; ++e) {
                 const T m = pivot_step<T>(rr[e], qcar);
                 gcar = fma_rn(m, ww[e], qcar * gcar);
-                if (t < wt) {
-                    sh.w[at(s0 + KG * c + e)] = gcar;
-                    sh.r[at(s0 + KG * c + e)] = qcar;
+                sh.w[at(s0 + e)] = gcar;
+                sh.r[at(s0 + e)] = qcar;
+            }
+        } else if constexpr (kElim) {
+#pragma unroll
+            for (int c = 0; c < kFrB / KG; ++c) {
+                T rr[KG], ww[KG];
+#pragma unroll
+                for (int e = 0; e < KG; ++e) {
+                    rr[e] = sh.r[at(s0 + KG * c + e)];
+                    ww[e] = sh.w[at(s0 + KG * c + e)];
+                }
+#pragma unroll
+                for (int e = 0; e < KG; ++e) {
+                    const T m = pivot_step<T>(rr[e], qcar);
+                    gcar = fma_rn(m, ww[e], qcar * gcar);
+                    if (yt < wt) {
+                        sh.w[at(s0 + KG * c + e)] = gcar;
+                        sh.r[at(s0 + KG * c + e)] = qcar;
+                    }
                 }
             }
         }
+        if constexpr (!kBack) return;
         // back substitution from the band's last row, up through the look-ahead rows
         // of the band before (rows xb - KY .. xb - 1; band 0 has none: zeros, and its
         // rows there are above the strip, so nothing is stored for them)
@@ -491,8 +535,8 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
             T d = T(0);
 #pragma unroll
             for (int c = 0; c < (kFrB + KY) / KG; ++c) {
-                // group c covers rows xb + 24 - KG (c + 1) .. xb + 23 - KG c; the groups
-                // from c = 24 / KG on are the look-ahead rows
+                // group c covers rows xb + B - KG (c + 1) .. xb + B - 1 - KG c; the
+                // groups from c = B / KG on are the look-ahead rows
                 const bool prev = c >= kFrB / KG;
                 const int sg = prev ? sl + KY - KG * (c - kFrB / KG + 1) : s0 + kFrB - KG * (c + 1);
                 T gg[KG], qq[KG], uu[KG];
@@ -509,7 +553,7 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
                     d = fma_rn(qq[e], d, gg[e]);
                     const int o = o0 + e;                           // rows xb - KY + o
                     if (o < kFrB && (kFull || out_row(b, o))) {
-                        const T v = fma_rn(T(2), uu[e], base[o]) + d;
+                        const T v = fma_rn(T(2), uu[e], C::YSPLIT ? -pu[o] : base[o]) + d;
                         const int so = kFull ? so0 + o * rowb : srow(b, o);
                         fr_store1<T, kFuNT>(v, rup, vcol, so);
                     }
@@ -518,25 +562,51 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
         };
         if (band_full(b)) back(std::true_type{});
         else back(std::false_type{});
+        if constexpr (C::YSPLIT) load_upd(b + 1);        // past the last band: out of range
     };
 
-    // pass k: the x-role solves band k, the y-role band k - 1.  The two roles run
-    // separate loops over the same passes (the x-role two passes per iteration, the
-    // y-role one), each meeting one barrier per pass: nb + 2 barriers for even nb,
-    // nb + 1 for odd, after the one above.  Every wavefront thus meets the same
-    // barriers, and each role has its own registers.
+    // pass k: the x-role solves band k and the y-role band k - 1 (split by stage:
+    // the elimination of band k - 1 and the back substitution of band k - 2).  The
+    // roles run separate loops over the same passes (the x-role two passes per
+    // iteration, the y-role one), each meeting one barrier per pass, and one more
+    // when the x-role's loop makes an odd count, after the one above.  Every
+    // wavefront thus meets the same barriers, and each role has its own registers.
+    const int npass = nb + (C::YSPLIT ? 2 : 1);
     if (wv < C::YW) {
-        // one barrier per pass: pass 0 (band 0 being solved), then band b in pass
-        // b + 1, and a last barrier when the x-role's loop makes an odd count
-        load_upd(0);
-        __syncthreads();
         int sb = 0;
-        for (int b = 0; b < nb; ++b) {
-            y_band(b, sb);
-            sb = next_base(sb);
+        if constexpr (C::YSPLIT) {
+            if (wv == 0) {
+                // elimination of band b in pass b + 1
+                __syncthreads();
+                for (int b = 0; b < nb; ++b) {
+                    y_band(b, sb, std::true_type{}, std::false_type{});
+                    sb = next_base(sb);
+                    __syncthreads();
+                }
+            } else {
+                // back substitution of band b in pass b + 2, with its u^{n-1}
+                // requested a pass ahead
+                load_upd(0);
+                __syncthreads();
+                __syncthreads();
+                for (int b = 0; b < nb; ++b) {
+                    y_band(b, sb, std::false_type{}, std::true_type{});
+                    sb = next_base(sb);
+                    __syncthreads();
+                }
+            }
+            if (wv == 0) __syncthreads();                     // pass nb + 1
+        } else {
+            // pass 0 (band 0 being solved), then band b in pass b + 1
+            load_upd(0);
             __syncthreads();
+            for (int b = 0; b < nb; ++b) {
+                y_band(b, sb, std::true_type{}, std::true_type{});
+                sb = next_base(sb);
+                __syncthreads();
+            }
         }
-        if ((nb & 1) == 0) __syncthreads();
+        if (npass & 1) __syncthreads();
     } else {
         // the loads are issued on every path (rows past the strip's last band read
         // as zero or are never used), so the outstanding-load count is the same at
@@ -545,7 +615,7 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
         load_band(0, PA);
         load_band(1, PB);
         int sb = 0;
-        for (int k = 0; k <= nb; k += 2) {
+        for (int k = 0; k < npass; k += 2) {
             if (k < nb) x_band(k, sb, PA);
             sb = next_base(sb);
             load_band(k + 2, PA);
