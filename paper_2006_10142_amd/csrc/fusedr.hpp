@@ -480,7 +480,7 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
         if constexpr (kBack && !C::YSPLIT) {
 #pragma unroll
             for (int o = 0; o < kFrB; ++o) base[o] = -pu[o];
-            load_upd(b + 1);                                 // past the last band: out of range
+            load_upd(b + 1);                                 // past the last band: clamped rows, unused
         }
         // ring slot s (< 2 R) of this column; threads past the strip read a valid
         // column and write nothing, so every thread issues the same memory operations
@@ -562,7 +562,7 @@ __device__ __forceinline__ void fusedr_strip(const FArgsT<T>& A, int blk, FRShar
         };
         if (band_full(b)) back(std::true_type{});
         else back(std::false_type{});
-        if constexpr (C::YSPLIT) load_upd(b + 1);        // past the last band: out of range
+        if constexpr (C::YSPLIT) load_upd(b + 1);        // past the last band: clamped rows, unused
     };
 
     // pass k: the x-role solves band k and the y-role band k - 1 (split by stage:
