@@ -247,6 +247,21 @@ def test_one_pass_f64_forced_widths_agree(adw, oracle_lib):
         check(got, ref, TOL64, TOL64_MAX, f"width {wt}")
 
 
+def test_one_pass_f64_short_segments(adw, oracle_lib):
+    """FP64 strips of 64 columns forced to segments of 8, 17, 63 and 100 rows: 2, 3, 4
+    and 6 bands a segment, so the pass count of the y-role split by stage (bands + 2)
+    takes both parities and the first and last bands meet; each reaches the oracle's
+    level to the FP64 bars on a 300 x 260 grid."""
+    k = case(300, 260, seed=14, f64=True, nsteps=12)
+    ref, _ = oracle(oracle_lib, k)
+    for hs in (8, 17, 63, 100):
+        k["lane"], k["tile_cols"], k["hs"] = 0, 64, hs
+        say(f"one-pass f64 segments of {hs} rows")
+        got, _, info = gpu(adw, k, True)
+        assert info["fused_tile_cols"] == 64 and info["fused_segment_rows"] == hs
+        check(got, ref, TOL64, TOL64_MAX, f"segments of {hs}")
+
+
 def test_one_pass_mixed_strip_widths(adw, oracle_lib):
     """4096 x 3600: the automatic plan takes 18 column strips, 8 of 232 and 10 of 224
     columns, 14 segments of 258 rows; 3 steps against the oracle (relative L2 and
